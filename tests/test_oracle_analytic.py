@@ -1,0 +1,124 @@
+"""Accuracy of the method (not parity): the oracle against closed-form
+potentials, and the closed forms against the Poisson equation."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import analytic as an
+
+RNG = np.random.default_rng(99)
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _laplacian(f, x, y, z, d=1e-3):
+    return (f(x + d, y, z) + f(x - d, y, z) + f(x, y + d, z) + f(x, y - d, z)
+            + f(x, y, z + d) + f(x, y, z - d) - 6 * f(x, y, z)) / d ** 2
+
+
+def test_ellipsoid_sphere_limit():
+    R = 0.7
+    p = RNG.uniform(-1.5, 1.5, size=(3, 400))
+    a = an.ellipsoid(*p, a=(R, R, R), rho=2.0, G=1.3)
+    M = 2.0 * 4 / 3 * math.pi * R ** 3
+    b = an.uniform_sphere(*p, M=M, R=R, G=1.3)
+    assert np.max(np.abs(a - b) / np.abs(b)) < 1e-12
+
+
+def test_ellipsoid_index_identity():
+    for axes in [(0.5, 1.0, 1.0), (0.08, 0.05, 0.03), (1.0, 0.3, 0.2)]:
+        assert abs(an.ellipsoid_index_sum(axes) - 2.0) < 1e-13
+
+
+@pytest.mark.parametrize("case", ["sphere", "ellipsoid", "plummer", "polytrope"])
+def test_closed_forms_satisfy_poisson(case):
+    """Laplacian of Phi = 4 pi G rho (Sect. 2, Eq. 1) at interior and
+    exterior points, by central differences; far field -> -GM/r."""
+    G = 1.0
+    if case == "sphere":
+        f = lambda x, y, z: an.uniform_sphere(x, y, z, M=2.0, R=0.5, G=G)
+        pts, rho = [(0.1, 0.2, -0.1), (0.9, 0.1, 0.3)], [2.0 / (4 / 3 * math.pi * 0.125), 0.0]
+        M = 2.0
+    elif case == "ellipsoid":
+        ax = (0.5, 0.35, 0.2)
+        f = lambda x, y, z: an.ellipsoid(x, y, z, a=ax, rho=1.5, G=G)
+        pts, rho = [(0.1, 0.1, 0.05), (0.7, 0.2, 0.1)], [1.5, 0.0]
+        M = 1.5 * 4 / 3 * math.pi * ax[0] * ax[1] * ax[2]
+    elif case == "plummer":
+        f = lambda x, y, z: an.plummer(x, y, z, M=1.0, a=0.3, G=G)
+        pts = [(0.1, 0.2, 0.0), (0.5, -0.4, 0.3)]
+        rho = [an.plummer_density(*p, M=1.0, a=0.3) for p in pts]
+        M = 1.0
+    else:
+        f = lambda x, y, z: an.polytrope2(x, y, z, rho0=3.0, R=0.6, G=G)
+        pts = [(0.1, 0.2, -0.05), (0.3, 0.1, 0.2), (0.8, 0.0, 0.1)]
+        rho = [an.polytrope2_density(*p, rho0=3.0, R=0.6) for p in pts]
+        M = an.polytrope2_mass(3.0, 0.6)
+    for p, r in zip(pts, rho):
+        lap = _laplacian(f, *p)
+        assert abs(lap - 4 * math.pi * G * r) < 2e-4 * max(1.0, 4 * math.pi * r)
+    far = np.array([300.0, -200.0, 100.0])
+    rr = np.linalg.norm(far)
+    assert abs(f(*far) + G * M / rr) < 1e-6 * G * M / rr
+
+
+def _level_coords(N, h):
+    x = oracle.cell_centres(N, h)
+    return np.meshgrid(x, x, x, indexing="ij")  # Z, Y, X
+
+
+def _polytrope_errors(N, L, R=0.3):
+    B = 1.0
+    h0 = B / N
+    rho = np.empty((L, N, N, N))
+    ana = np.empty_like(rho)
+    for l in range(L):
+        Z, Y, X = _level_coords(N, h0 / 2 ** l)
+        rho[l] = an.polytrope2_density(X, Y, Z, 1.0, R)
+        ana[l] = an.polytrope2(X, Y, Z, 1.0, R)
+    phi = oracle.solve(rho, h0)
+    return an.relative_error(phi, ana)
+
+
+@pytest.mark.slow
+def test_second_order_convergence():
+    """Sect. 7: second-order convergence of the mean error in the potential
+    with N at fixed geometry (smooth compact density, 2 levels)."""
+    means = []
+    for N in (16, 32, 64):
+        err = _polytrope_errors(N, 2)
+        means.append(err.mean())
+    r1, r2 = means[0] / means[1], means[1] / means[2]
+    assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, (means, r1, r2)
+
+
+@pytest.mark.slow
+def test_paper_table3_ellipsoid_order_of_magnitude():
+    """Sect. 5, Table 3 (convolution row), loosely: oblate ellipsoid
+    0.5:1:1 on four nested grids of 128^3 in [-2.25, 2.25]^3.  The paper's
+    sampling and carry details are unstated, so only the order of magnitude
+    of the max and mean potential errors is checked."""
+    with open(os.path.join(GOLDEN, "table3_convolution.json")) as fh:
+        ref = json.load(fh)["ellipsoid_0.5_1_1"]
+    N, L, B = 128, 4, 4.5
+    h0 = B / N
+    axes = (0.5, 1.0, 1.0)
+    rho = np.empty((L, N, N, N))
+    for l in range(L):
+        Z, Y, X = _level_coords(N, h0 / 2 ** l)
+        rho[l] = ((X / axes[0]) ** 2 + (Y / axes[1]) ** 2 + (Z / axes[2]) ** 2 <= 1.0).astype(float)
+    phi = oracle.solve(rho, h0)
+    errs = []
+    for l in range(L):
+        x = oracle.cell_centres(N, h0 / 2 ** l)
+        j = N // 2  # plane next to y = 0 (Fig. 11 and 12 use the x-z plane)
+        Z, X = np.meshgrid(x, x, indexing="ij")
+        Y = np.full_like(X, x[j])
+        a = an.ellipsoid(X, Y, Z, a=axes, rho=1.0)
+        errs.append(an.relative_error(phi[l][:, j, :], a).ravel())
+    e = np.concatenate(errs) * 100
+    assert ref["max_percent"] / 10 < e.max() < ref["max_percent"] * 10, e.max()
+    assert ref["mean_percent"] / 10 < e.mean() < ref["mean_percent"] * 10, e.mean()
