@@ -1,0 +1,185 @@
+/*
+ * nmc.h - C ABI of libnmc, the MI355X (gfx950) implementation of the
+ * convolution method for the gravitational potential on nested Cartesian
+ * meshes (Vorobyov, McKevitt, Kulikov, Elbakyan, A&A 2023, arXiv:2301.06763).
+ *
+ * Problem (Sect. 2 and 4 of the paper): given densities rho on L concentric
+ * nested grids Omega^1 > ... > Omega^L of N^3 cells each, level m+1 covering
+ * the central half (per axis) of level m with half the cell size, find the
+ * potential Phi(Omega^m) on every level.
+ *
+ * Method: on every level (Sect. 3) the potential of the cell masses M = rho h^3
+ * is the discrete sum Phi = -G sum M / |r - r'| (Eq. 10) with the self-cell
+ * term of Eq. 13, evaluated as a zero-padded FFT convolution on a doubled
+ * periodic mesh (Fig. 4).  The nested mesh is split into full grids Omega^m
+ * and grids with a zeroed cavity Omega^m_hole (Sect. 4, Fig. 5); the result
+ * on Omega^n is Phi^n plus the hole potentials of all coarser grids
+ * interpolated onto it (Eq. 14).
+ *
+ * Conventions for every array argument:
+ *   - Densities and potentials: [L][N][N][N], level 0 = coarsest, index order
+ *     [z][y][x] with x fastest, contiguous, element type double (NMC_F64) or
+ *     float (NMC_F32).  Level l has cell size h0 / 2^l and is centred on the
+ *     origin; level l+1 covers cells [N/4, 3N/4) of level l on each axis.
+ *   - Pointers named "device" must be HIP device memory of the context's
+ *     device; the caller allocates and frees them.
+ *   - Every call returns NMC_OK (0) or a negative status.  All argument
+ *     validation happens before any device work is enqueued; on an error no
+ *     caller buffer is written.  nmc_last_error() describes the last failure.
+ *   - Work is enqueued asynchronously on the caller's hipStream_t (passed as
+ *     void*; NULL = the null stream).  Results are valid after the stream is
+ *     synchronised.  Device faults surface at a later call or the sync.
+ *   - A context is not thread-safe: use one per host thread.
+ */
+#ifndef NMC_H
+#define NMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmc_ctx nmc_ctx;
+
+typedef enum { NMC_F64 = 0, NMC_F32 = 1 } nmc_precision;
+
+enum {
+  NMC_OK = 0,
+  NMC_EINVAL = -1,       /* invalid argument (null pointer, bad N/L/h0/G/refine, aliasing) */
+  NMC_ENOMEM = -2,       /* footprint above the context's HBM budget, or allocation failure */
+  NMC_EDEVICE = -3,      /* HIP runtime error (text in nmc_last_error) */
+  NMC_EUNSUPPORTED = -4, /* N beyond the supported range (padded period above 512) */
+  NMC_EAGAIN = -5        /* serving: ticket not finished yet / nothing admitted yet */
+};
+
+/* Flag bits for nmc_solve / nmc_request.flags. */
+enum {
+  /* Keep the caller's coarse density under finer grids.  Default: replace it
+   * by the mean of the 2^3 finer cells below, cascaded from the finest level
+   * (mass conserving; the paper leaves the coarse mass under a finer grid
+   * unspecified). */
+  NMC_NO_RESTRICT = 1u << 0,
+  /* FP32 only: plain FP32 cross-level sums instead of the compensated
+   * (two-term) carry.  For ablation. */
+  NMC_F32_UNCOMPENSATED = 1u << 2
+};
+
+/* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
+ * library's workspace (0 = no cap); the Green-spectrum cache is extra.
+ * *out receives the context.  Errors: NMC_EINVAL (out null, bad device),
+ * NMC_EDEVICE. */
+int nmc_create(nmc_ctx** out, int hip_device, size_t hbm_budget_bytes);
+
+/* Destroy a context after synchronising its device work; frees every
+ * library-owned buffer.  Caller buffers are untouched.  NULL is a no-op. */
+void nmc_destroy(nmc_ctx* ctx);
+
+/* Text of the last failure on this context (static storage owned by the
+ * context; valid until the next call on it).  Never NULL. */
+const char* nmc_last_error(const nmc_ctx* ctx);
+
+/* Device workspace (bytes) one solve of this shape needs: the per-grid FFT
+ * buffers of all 2L-1 grids plus the restriction and carry buffers.  Pure
+ * host arithmetic.  Errors: NMC_EINVAL, NMC_EUNSUPPORTED. */
+int nmc_footprint_bytes(int N, int L, nmc_precision p, size_t* bytes);
+
+/* Solve one nested mesh (Sect. 4, Eq. 14).
+ *   rho   device, [L][N][N][N] densities (read only, never written)
+ *   phi   device, [L][N][N][N] output; phi[l] = Phi(Omega^(l+1)) on all N^3
+ *         cells of level l, including cells covered by finer levels.
+ *         Must not overlap rho.
+ *   N     cells per axis, multiple of 4, 4 <= N <= 256
+ *   L     levels, 1 <= L <= 16
+ *   h0    coarsest cell size (> 0, finite)
+ *   refine  refinement factor between levels; must be 2
+ *   G     gravitational constant (finite)
+ *   p     element type of rho and phi and arithmetic of the FFT path
+ *   flags NMC_NO_RESTRICT, NMC_F32_UNCOMPENSATED
+ *   hip_stream  hipStream_t to enqueue on
+ * Errors: NMC_EINVAL, NMC_EUNSUPPORTED, NMC_ENOMEM, NMC_EDEVICE. */
+int nmc_solve(nmc_ctx* ctx, const void* rho, void* phi, int N, int L, double h0, int refine,
+              double G, nmc_precision p, unsigned flags, void* hip_stream);
+
+/* One request of a batch (same meaning as the nmc_solve arguments; the
+ * refinement factor is 2). */
+typedef struct {
+  const void* rho;
+  void* phi;
+  int N;
+  int L;
+  double h0;
+  double G;
+  nmc_precision p;
+  unsigned flags;
+} nmc_request;
+
+/* Solve `count` independent nested meshes (Sect. 4: the grids of a solve are
+ * independent, and so are solves).  Requests of equal N and precision share
+ * every FFT pass launch.  Each result is bitwise identical to the same
+ * request solved alone.  All requests are validated before any work. */
+int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_stream);
+
+/* ---- Serving: continuous batching over library-owned streams ----------
+ * Requests are queued by nmc_serve_submit.  Every nmc_serve_tick retires
+ * finished batches (returning their workspace), then admits queued requests
+ * in arrival order while the summed nmc_footprint_bytes of in-flight work
+ * stays within the budget, groups the admitted ones by (N, precision) and
+ * launches each group as one batched solve on the next serving stream, so
+ * new work overlaps the work already on the device.  rho/phi of a submitted
+ * request must stay valid until it is reported done. */
+
+/* Queue a request; *ticket receives its id.  NMC_ENOMEM if the request alone
+ * exceeds the budget (it could never be admitted); NMC_EINVAL/EUNSUPPORTED as
+ * for nmc_solve. */
+int nmc_serve_submit(nmc_ctx* ctx, const nmc_request* req, uint64_t* ticket);
+
+/* One scheduler step (non-blocking).  *launched (may be NULL) receives the
+ * number of requests launched in this step. */
+int nmc_serve_tick(nmc_ctx* ctx, int* launched);
+
+/* *done = 1 once the ticket's result is complete on the device (the
+ * scheduler is ticked first).  NMC_EINVAL for an unknown ticket. */
+int nmc_serve_poll(nmc_ctx* ctx, uint64_t ticket, int* done);
+
+typedef struct {
+  uint64_t submitted, admitted, completed, batches;
+  uint64_t queued;          /* waiting for admission */
+  uint64_t inflight;        /* launched, not yet retired */
+  size_t inflight_bytes;    /* workspace held by in-flight batches */
+  size_t budget_bytes;      /* admission budget (0 = unlimited) */
+  size_t peak_inflight_bytes;
+} nmc_serve_stats;
+
+int nmc_serve_stats_get(nmc_ctx* ctx, nmc_serve_stats* out);
+
+/* Block until every submitted request is complete. */
+int nmc_serve_drain(nmc_ctx* ctx);
+
+/* ---- Diagnostics (same kernels as the solve path) --------------------- */
+
+/* Copy the cached real Green spectrum of period P = nmc_period(N) into
+ * `out` (device, (P/2+1)^3 elements of type p, index [kz][ky][kx]), building
+ * it first if needed.  It is the unnormalised DFT over the doubled periodic
+ * mesh of the inverse cell-centre distance (cell units), with the self-cell
+ * integral of Eq. 13 at offset 0 (Sect. 3, Fig. 4). */
+int nmc_green_spectrum(nmc_ctx* ctx, int N, nmc_precision p, void* out, void* hip_stream);
+
+/* Padded period used for N: the smallest power of two >= 2N (Sect. 3 doubles
+ * the mesh; any period >= 2N-1 gives the same linear convolution).  Returns
+ * 0 for unsupported N. */
+int nmc_period(int N);
+
+/* Batched unnormalised 1-D complex FFT of `nlines` contiguous lines of P
+ * points (interleaved re/im, element type p) with the solve path's FFT
+ * stages; dir = -1 forward (exp(-2 pi i jk/P)), +1 inverse.  in/out device,
+ * may alias.  P in {8, ..., 512}. */
+int nmc_fft_lines(nmc_ctx* ctx, const void* in, void* out, int P, int nlines, int dir,
+                  nmc_precision p, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NMC_H */

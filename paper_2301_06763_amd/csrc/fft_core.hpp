@@ -1,0 +1,199 @@
+// Device-side FFT building blocks for gfx950 (wave64, LDS exchange).
+//
+// A line of P complex points is transformed by TL = P/E threads that each
+// hold E points in registers.  Thread t always holds points t + TL*q,
+// q = 0..E-1, at the start of every stage.  Each stage is a Stockham
+// autosort radix-R step (no bit reversal): butterfly b takes inputs
+// x[b + i P/R], applies the twiddles exp(+-2 pi i * i*k/(Ns R)) with
+// k = b mod Ns (Ns = product of the radices already done), a radix-R DFT in
+// registers, and writes y[(b/Ns) Ns R + k + i Ns].  After the last stage the
+// natural-order output lands in the same registers as the input pattern, so a
+// forward transform can feed an inverse transform without any exchange.
+//
+// Pruning (zero padding of the doubled mesh, Sect. 3 of the paper): in a
+// forward transform whose input is zero for indices >= P/2, the first stage's
+// upper half of inputs is zero; in an inverse transform whose output is only
+// needed for indices < P/2, the last stage keeps the lower half.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+namespace nmc {
+
+template <class R> struct CplxOf;
+template <> struct CplxOf<double> { using T = double2; };
+template <> struct CplxOf<float> { using T = float2; };
+template <class R> using cplx = typename CplxOf<R>::T;
+
+template <class T>
+__device__ __forceinline__ T c_add(T a, T b) { return T{a.x + b.x, a.y + b.y}; }
+template <class T>
+__device__ __forceinline__ T c_sub(T a, T b) { return T{a.x - b.x, a.y - b.y}; }
+// a * w for a twiddle w = exp(-2 pi i j / P) (DIR = -1) or its conjugate (DIR = +1)
+template <int DIR, class T>
+__device__ __forceinline__ T c_mul_tw(T a, T w) {
+  if constexpr (DIR < 0) return T{a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x};
+  else return T{a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
+}
+
+// cos and sin of 2 pi j / 16 for j = 0..15 (exact decimal expansions,
+// rounded once to the working precision).
+struct Angle16 {
+  static constexpr double c[16] = {
+      1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+      0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+      -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+      0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+  static constexpr double s[16] = {
+      0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+      1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+      0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+      -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+};
+
+// a * exp(DIR * 2 pi i K / RR) for compile-time K/RR with RR | 16.
+template <int DIR, int K, int RR, class T>
+__device__ __forceinline__ T c_rot(T a) {
+  using R = decltype(a.x);
+  constexpr int j0 = ((K % RR) + RR) % RR * (16 / RR);
+  constexpr int j = DIR < 0 ? (16 - j0) % 16 : j0;  // angle 2 pi j / 16
+  if constexpr (j == 0) return a;
+  else if constexpr (j == 4) return T{-a.y, a.x};   // * i
+  else if constexpr (j == 8) return T{-a.x, -a.y};  // * -1
+  else if constexpr (j == 12) return T{a.y, -a.x};  // * -i
+  else if constexpr (j == 2) { constexpr R h = (R)Angle16::c[2]; return T{(a.x - a.y) * h, (a.x + a.y) * h}; }
+  else if constexpr (j == 6) { constexpr R h = (R)Angle16::c[2]; return T{-(a.x + a.y) * h, (a.x - a.y) * h}; }
+  else if constexpr (j == 10) { constexpr R h = (R)Angle16::c[2]; return T{(a.y - a.x) * h, -(a.x + a.y) * h}; }
+  else if constexpr (j == 14) { constexpr R h = (R)Angle16::c[2]; return T{(a.x + a.y) * h, (a.y - a.x) * h}; }
+  else {
+    constexpr R c = (R)Angle16::c[j];
+    constexpr R s = (R)Angle16::s[j];
+    return T{a.x * c - a.y * s, a.x * s + a.y * c};
+  }
+}
+
+// In-register DFT of length RR (power of two <= 16) by radix-2 decimation in
+// time; inputs with index >= NZ are taken as zero and never read.
+// DIR = -1: forward exp(-2 pi i jk/RR); DIR = +1: inverse (unnormalised).
+template <int RR, int DIR, int NZ, class T>
+__device__ __forceinline__ void dft(T* u) {
+  if constexpr (RR == 1) {
+    if constexpr (NZ <= 0) u[0] = T{0, 0};
+  } else if constexpr (NZ <= 0) {
+#pragma unroll
+    for (int i = 0; i < RR; ++i) u[i] = T{0, 0};
+  } else if constexpr (NZ == 1) {
+#pragma unroll
+    for (int i = 1; i < RR; ++i) u[i] = u[0];
+  } else {
+    constexpr int H = RR / 2;
+    constexpr int NZE = NZ >= RR ? H : (NZ + 1) / 2;
+    constexpr int NZO = NZ >= RR ? H : NZ / 2;
+    T e[H], o[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      if (2 * i < NZ) e[i] = u[2 * i];
+      if (2 * i + 1 < NZ) o[i] = u[2 * i + 1];
+    }
+    dft<H, DIR, NZE>(e);
+    dft<H, DIR, NZO>(o);
+    [&]<int... K>(std::integer_sequence<int, K...>) {
+      ((u[K] = c_add(e[K], c_rot<DIR, K, RR>(o[K])),
+        u[K + H] = c_sub(e[K], c_rot<DIR, K, RR>(o[K]))), ...);
+    }(std::make_integer_sequence<int, H>{});
+  }
+}
+
+// LDS view for the exchange between stages: point n of line w lives at
+// re[n * SN + w * SW] / im[...] (SoA, so every access is one scalar).
+template <class R>
+struct LdsView {
+  R* re;
+  R* im;
+  int SN, SW, w;
+  __device__ __forceinline__ void put(int n, cplx<R> v) const {
+    re[n * SN + w * SW] = v.x;
+    im[n * SN + w * SW] = v.y;
+  }
+  __device__ __forceinline__ cplx<R> get(int n) const {
+    return cplx<R>{re[n * SN + w * SW], im[n * SN + w * SW]};
+  }
+};
+
+// One Stockham stage and, recursively, the following ones.
+//  P: line length, E: points per thread, DIR: -1 forward / +1 inverse,
+//  NS: product of radices already applied, FIRST: data comes from registers,
+//  PIN: input index >= P/2 is zero (only valid on the first stage),
+//  POUT: only outputs < P/2 are needed (last stage).
+template <class R, int P, int E, int DIR, int NS, bool FIRST, bool PIN, bool POUT, int RAD, int... REST>
+__device__ __forceinline__ void fft_stages(cplx<R>* v, int t, const LdsView<R>& lds,
+                                           const cplx<R>* __restrict__ tw) {
+  constexpr int TL = P / E;
+  constexpr int NB = E / RAD;  // butterflies per thread in this stage
+  constexpr bool LAST = sizeof...(REST) == 0;
+  static_assert(E % RAD == 0, "radix must divide points per thread");
+  if constexpr (!FIRST) {
+    __syncthreads();  // previous stage's writes are visible
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = lds.get(t + TL * q);
+  }
+  if constexpr (!LAST) __syncthreads();  // everyone has read before anyone overwrites
+#pragma unroll
+  for (int m = 0; m < NB; ++m) {
+    cplx<R> u[RAD];
+#pragma unroll
+    for (int i = 0; i < RAD; ++i)
+      if (!(FIRST && PIN) || i < RAD / 2) u[i] = v[m + i * NB];
+    const int b = t + m * TL;
+    const int k = b & (NS - 1);
+    if constexpr (NS > 1) {
+      constexpr int STEP = P / (NS * RAD);
+#pragma unroll
+      for (int i = 1; i < RAD; ++i) u[i] = c_mul_tw<DIR>(u[i], tw[i * k * STEP]);
+    }
+    dft<RAD, DIR, (FIRST && PIN) ? RAD / 2 : RAD>(u);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int i = 0; i < RAD; ++i)
+        if (!POUT || i < RAD / 2) v[m + i * NB] = u[i];
+    } else {
+      const int base = (b / NS) * NS * RAD + k;
+#pragma unroll
+      for (int i = 0; i < RAD; ++i) lds.put(base + i * NS, u[i]);
+    }
+  }
+  if constexpr (!LAST)
+    fft_stages<R, P, E, DIR, NS * RAD, false, false, POUT, REST...>(v, t, lds, tw);
+}
+
+// Per-length plan: points per thread and the radix sequence.
+template <int P> struct Plan;
+template <> struct Plan<8> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8>(); } };
+template <> struct Plan<16> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 2>(); } };
+template <> struct Plan<32> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4>(); } };
+template <> struct Plan<64> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8>(); } };
+template <> struct Plan<128> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8>(); } };
+template <> struct Plan<256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
+template <> struct Plan<512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+
+template <class R, int P, int DIR, bool PIN, bool POUT>
+struct FftRun {
+  cplx<R>* v;
+  int t;
+  const LdsView<R>* lds;
+  const cplx<R>* tw;
+  template <int... RS>
+  __device__ __forceinline__ void go() const {
+    fft_stages<R, P, Plan<P>::E, DIR, 1, true, PIN, POUT, RS...>(v, t, *lds, tw);
+  }
+};
+
+// Transform one line held as v[q] = x[t + TL q] in place (natural order out).
+template <class R, int P, int DIR, bool PIN, bool POUT>
+__device__ __forceinline__ void fft_line(cplx<R>* v, int t, const LdsView<R>& lds,
+                                         const cplx<R>* __restrict__ tw) {
+  Plan<P>::run(FftRun<R, P, DIR, PIN, POUT>{v, t, &lds, tw});
+}
+
+}  // namespace nmc

@@ -1,0 +1,577 @@
+// HIP kernels (gfx950) for the nested-mesh convolution method.
+//
+// Per grid (Sect. 3 of the paper) the potential is the circular convolution,
+// on a doubled periodic mesh of P^3 points, of the zero-padded density with
+// the periodic inverse-distance kernel.  The 3-D transform is done as five
+// passes, each one launch over every grid of the solve:
+//
+//   X  (fwd_x): real lines along x, N nonzero of P -> P/2 complex columns;
+//               the real DC and Nyquist columns are packed into column 0
+//   Y  (fwd_y): lines along y, N nonzero of P -> P
+//   Z  (z):     lines along z: forward, times the real Green spectrum and
+//               the level scale, inverse, keep the output rows
+//   I2 (inv_y): lines along y, P -> keep the output rows
+//   I1 (inv_x): C2R lines along x, P/2 packed columns -> keep the output
+//               cells; full grids of level >= 1 add the carried coarse
+//               potential here (Sect. 4, Eq. 14)
+//
+// Layouts (complex, kx fastest): A[z][y][kx] (N x N x P/2), B[z][ky][kx]
+// (N x P x P/2).  Strided passes give each workgroup W adjacent kx columns,
+// so every global access is a run of W complex values.
+#include <hip/hip_runtime.h>
+
+#include "fft_core.hpp"
+#include "kernels.h"
+
+namespace nmc {
+
+template <class R, int P>
+struct Cfg {
+  static constexpr int E = Plan<P>::E;
+  static constexpr int TL = P / E;
+  static constexpr int BYTES_PT = 2 * (int)sizeof(R);
+  static constexpr int LDS = 65536;
+  static constexpr int WMAX = sizeof(R) == 8 ? 16 : 32;
+  static constexpr int cmin(int a, int b) { return a < b ? a : b; }
+  static constexpr int WS = cmin(cmin(P / 2, WMAX), LDS / (P * BYTES_PT));      // y passes
+  static constexpr int WZ = cmin(cmin(P / 2, WMAX), LDS / (2 * P * BYTES_PT));  // z pass (2 rows)
+  static constexpr int WC = cmin(cmin(256 / TL, 64), LDS / (P * BYTES_PT));     // x passes
+  static_assert(WS >= 1 && WZ >= 1 && WC >= 1, "tile does not fit");
+};
+
+// ---------------------------------------------------------------------------
+// X pass: R2C along x with zero padding (input index >= N is zero).
+template <class R, int P>
+__global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
+k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using C = Cfg<R, P>;
+  using T = cplx<R>;
+  constexpr int E = C::E, TL = C::TL, W = C::WC;
+  __shared__ R sre[W * P], sim[W * P];
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = g.N;
+  const int t = threadIdx.x % TL, w = threadIdx.x / TL;
+  const int line = blockIdx.x * W + w;
+  const bool active = line < N * N;
+  const int z = active ? line / N : 0, y = active ? line % N : 0;
+  const R* rho = static_cast<const R*>(F.rho);
+  const R* rc = static_cast<const R*>(F.rc);
+  const int lo = N / 4, hi = 3 * N / 4, N2 = N / 2;
+  const bool yz_in = z >= lo && z < hi && y >= lo && y < hi;
+  T v[E];
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int n = t + TL * q;
+    R val = 0;
+    if (active && n < N) {
+      if (yz_in && n >= lo && n < hi) {
+        if (!F.hole) val = rc ? rc[((size_t)(z - lo) * N2 + (y - lo)) * N2 + (n - lo)]
+                              : rho[((size_t)z * N + y) * N + n];
+      } else {
+        val = rho[((size_t)z * N + y) * N + n];
+      }
+    }
+    v[q] = T{val, 0};
+  }
+  LdsView<R> lds{sre, sim, 1, P, w};
+  fft_line<R, P, -1, true, false>(v, t, lds, tb.tw);
+  if (active) {
+    T* A = static_cast<T*>(F.A) + ((size_t)z * N + y) * (P / 2);
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) {
+      const int k = t + TL * q;
+      T o = v[q];
+      if (k == 0) o = T{v[0].x, v[E / 2].x};  // DC and Nyquist are real: pack them
+      A[k] = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Y pass: C2C along y, inputs y >= N zero, all P outputs kept.
+template <class R, int P>
+__global__ void __launch_bounds__((Cfg<R, P>::WS * Cfg<R, P>::TL))
+k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using C = Cfg<R, P>;
+  using T = cplx<R>;
+  constexpr int E = C::E, TL = C::TL, W = C::WS, NT = (P / 2) / W;
+  __shared__ R sre[W * P], sim[W * P];
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = g.N;
+  const int w = threadIdx.x % W, t = threadIdx.x / W;
+  const int tile = blockIdx.x % NT, z = blockIdx.x / NT;
+  const int kx = tile * W + w;
+  const T* A = static_cast<const T*>(F.A);
+  T* B = static_cast<T*>(F.B);
+  T v[E];
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int yy = t + TL * q;
+    v[q] = yy < N ? A[((size_t)z * N + yy) * (P / 2) + kx] : T{0, 0};
+  }
+  LdsView<R> lds{sre, sim, W, 1, w};
+  fft_line<R, P, -1, true, false>(v, t, lds, tb.tw);
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int ky = t + TL * q;
+    B[((size_t)z * P + ky) * (P / 2) + kx] = v[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Z pass: forward along z (inputs z >= N zero), multiply by the real Green
+// spectrum times the level scale, inverse along z, keep the output rows.
+// A workgroup owns the rows ky and -ky (mod P) of W adjacent kx columns: the
+// packed DC/Nyquist column needs the value at (-ky, -kz) to separate the two
+// real planes before they are multiplied by different spectra.
+template <class R, int P>
+__global__ void __launch_bounds__((2 * Cfg<R, P>::WZ * Cfg<R, P>::TL))
+k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using C = Cfg<R, P>;
+  using T = cplx<R>;
+  constexpr int E = C::E, TL = C::TL, W = C::WZ, NT = (P / 2) / W, H = P / 2 + 1;
+  __shared__ R sre[2 * W * P], sim[2 * W * P];
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = g.N;
+  const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
+  const int tile = blockIdx.x % NT, p = blockIdx.x / NT;
+  const int ky = side == 0 ? p : (p == 0 ? P / 2 : P - p);
+  const int kx = tile * W + w;
+  T* B = static_cast<T*>(F.B);
+  T v[E];
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int zz = t + TL * q;
+    v[q] = zz < N ? B[((size_t)zz * P + ky) * (P / 2) + kx] : T{0, 0};
+  }
+  LdsView<R> lds{sre, sim, 2 * W, 1, w + W * side};
+  fft_line<R, P, -1, true, false>(v, t, lds, tb.tw);
+
+  const R sc = (R)F.scale;
+  const int kyp = ky <= P / 2 ? ky : P - ky;
+  if (tile == 0) {  // uniform per workgroup
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int kz = t + TL * q;
+        sre[side * P + kz] = v[q].x;
+        sim[side * P + kz] = v[q].y;
+      }
+    }
+    __syncthreads();
+  }
+  const int ps = p == 0 ? side : 1 - side;  // row holding -ky
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int kz = t + TL * q;
+    const int kzp = kz <= P / 2 ? kz : P - kz;
+    const R* grow = tb.green + ((size_t)kzp * H + kyp) * H;
+    if (kx != 0) {
+      const R gv = sc * grow[kx];
+      v[q] = T{v[q].x * gv, v[q].y * gv};
+    } else {
+      // column 0 holds U + iV (U, V spectra of the real DC and Nyquist planes);
+      // with Cm = conj(value at -k): U = (C + Cm)/2, V = (C - Cm)/(2i), and the
+      // product is g0 U + i gN V = (g0+gN)/2 C + (g0-gN)/2 Cm.
+      const int nkz = (P - kz) & (P - 1);
+      const T cm = T{sre[ps * P + nkz], -sim[ps * P + nkz]};
+      const R g0 = grow[0], gn = grow[P / 2];
+      const R a = sc * (R)0.5 * (g0 + gn), b = sc * (R)0.5 * (g0 - gn);
+      v[q] = T{a * v[q].x + b * cm.x, a * v[q].y + b * cm.y};
+    }
+  }
+  fft_line<R, P, +1, false, true>(v, t, lds, tb.tw);
+  const int zlo = F.hole ? N / 4 - 1 : 0, zhi = F.hole ? 3 * N / 4 + 1 : N;
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int zz = t + TL * q;
+    if (zz >= zlo && zz < zhi) B[((size_t)zz * P + ky) * (P / 2) + kx] = v[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// I2 pass: inverse along y over the kept z rows; keep the output y rows.
+template <class R, int P>
+__global__ void __launch_bounds__((Cfg<R, P>::WS * Cfg<R, P>::TL))
+k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using C = Cfg<R, P>;
+  using T = cplx<R>;
+  constexpr int E = C::E, TL = C::TL, W = C::WS, NT = (P / 2) / W;
+  __shared__ R sre[W * P], sim[W * P];
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = g.N;
+  const int lo = F.hole ? N / 4 - 1 : 0, nr = F.hole ? N / 2 + 2 : N;
+  const int r = blockIdx.x / NT;
+  if (r >= nr) return;  // uniform per workgroup
+  const int w = threadIdx.x % W, t = threadIdx.x / W;
+  const int kx = (blockIdx.x % NT) * W + w;
+  const int z = lo + r;
+  const T* B = static_cast<const T*>(F.B);
+  T* A = static_cast<T*>(F.A);
+  T v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[q] = B[((size_t)z * P + t + TL * q) * (P / 2) + kx];
+  LdsView<R> lds{sre, sim, W, 1, w};
+  fft_line<R, P, +1, false, true>(v, t, lds, tb.tw);
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int yy = t + TL * q;
+    if (yy >= lo && yy < lo + nr) A[((size_t)z * N + yy) * (P / 2) + kx] = v[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// I1 pass: C2R along x; hole grids write the stencil box, full grids write
+// the potential, adding the carried coarse potential for levels >= 1.
+template <class R>
+__device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
+  s = a + b;
+  const R bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+template <class R>
+__device__ __forceinline__ R add_carry(R val, const FieldDesc& F, int N, int z, int y, int x) {
+  const R* S = static_cast<const R*>(F.S);
+  const R* Sl = static_cast<const R*>(F.Slo);
+  const int NS = N / 2 + 2;
+  const int iz = z / 2 + 1, iy = y / 2 + 1, ix = x / 2 + 1;
+  const int jz = iz + ((z & 1) ? 1 : -1), jy = iy + ((y & 1) ? 1 : -1), jx = ix + ((x & 1) ? 1 : -1);
+  const size_t in = ((size_t)iz * NS + iy) * NS + ix, jn = ((size_t)jz * NS + jy) * NS + jx;
+  const R a = S[in], b = S[jn];
+  if constexpr (sizeof(R) == 8) {
+    return val + ((R)0.75 * a + (R)0.25 * b);
+  } else {
+    // compensated: 3/4 a + 1/4 b + lo terms, then val + (hi + lo)
+    const R p1 = (R)0.75 * a;
+    const R e1 = __builtin_fmaf((R)0.75, a, -p1);
+    const R p2 = (R)0.25 * b;
+    R s, e2;
+    two_sum(p1, p2, s, e2);
+    R lo = e1 + e2;
+    if (Sl) lo += (R)0.75 * Sl[in] + (R)0.25 * Sl[jn];
+    R o, e3;
+    two_sum(val, s, o, e3);
+    return o + (e3 + lo);
+  }
+}
+
+template <class R, int P>
+__global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
+k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using C = Cfg<R, P>;
+  using T = cplx<R>;
+  constexpr int E = C::E, TL = C::TL, W = C::WC;
+  __shared__ R sre[W * P], sim[W * P];
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = g.N;
+  const int lo = F.hole ? N / 4 - 1 : 0, nr = F.hole ? N / 2 + 2 : N;
+  if ((int)blockIdx.x * W >= nr * nr) return;  // uniform per workgroup
+  const int t = threadIdx.x % TL, w = threadIdx.x / TL;
+  const int line = blockIdx.x * W + w;
+  const bool active = line < nr * nr;
+  const int z = lo + (active ? line / nr : 0), y = lo + (active ? line % nr : 0);
+  const T* row = static_cast<const T*>(F.A) + ((size_t)z * N + y) * (P / 2);
+  T v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int n = t + TL * q;
+    T c = T{0, 0};
+    if (active) {
+      if (n == 0) c = T{row[0].x, 0};
+      else if (n < P / 2) c = row[n];
+      else if (n == P / 2) c = T{row[0].y, 0};
+      else { const T m = row[P - n]; c = T{m.x, -m.y}; }
+    }
+    v[q] = c;
+  }
+  LdsView<R> lds{sre, sim, 1, P, w};
+  fft_line<R, P, +1, false, true>(v, t, lds, tb.tw);
+  if (!active) return;
+  R* out = static_cast<R*>(F.out);
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int xx = t + TL * q;
+    if (xx >= lo && xx < lo + nr) {
+      const R val = v[q].x;
+      if (F.hole) {
+        out[((size_t)(z - lo) * nr + (y - lo)) * nr + (xx - lo)] = val;
+      } else {
+        out[((size_t)z * N + y) * N + xx] = F.has_carry ? add_carry<R>(val, F, N, z, y, xx) : val;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Restriction: mean of the 2^3 children of every child-region cell.
+template <class R>
+__global__ void k_restrict(const R* __restrict__ fine, const R* __restrict__ fine_rc,
+                           R* __restrict__ rc, int N) {
+  const int N2 = N / 2, lo = N / 4, hi = 3 * N / 4;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= N2 * N2 * N2) return;
+  const int ax = id % N2, ay = (id / N2) % N2, az = id / (N2 * N2);
+  R s = 0;
+#pragma unroll
+  for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+    for (int by = 0; by < 2; ++by)
+#pragma unroll
+      for (int bx = 0; bx < 2; ++bx) {
+        const int z = 2 * az + bz, y = 2 * ay + by, x = 2 * ax + bx;
+        const bool cen = fine_rc && z >= lo && z < hi && y >= lo && y < hi && x >= lo && x < hi;
+        s += cen ? fine_rc[((size_t)(z - lo) * N2 + (y - lo)) * N2 + (x - lo)]
+                 : fine[((size_t)z * N + y) * N + x];
+      }
+  rc[id] = s * (R)0.125;
+}
+
+// Carry cascade on the stencil box [N/4-1, 3N/4]^3 (NS = N/2+2 cells).
+template <class R>
+__global__ void k_carry(const R* __restrict__ s_hi, const R* __restrict__ s_lo,
+                        const R* __restrict__ hole, R* __restrict__ o_hi, R* __restrict__ o_lo,
+                        int N, int compensated) {
+  const int NS = N / 2 + 2, lo = N / 4 - 1;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= NS * NS * NS) return;
+  const int x = lo + id % NS, y = lo + (id / NS) % NS, z = lo + id / (NS * NS);
+  const int iz = z / 2 + 1, iy = y / 2 + 1, ix = x / 2 + 1;
+  const int jz = iz + ((z & 1) ? 1 : -1), jy = iy + ((y & 1) ? 1 : -1), jx = ix + ((x & 1) ? 1 : -1);
+  const size_t in = ((size_t)iz * NS + iy) * NS + ix, jn = ((size_t)jz * NS + jy) * NS + jx;
+  const R a = s_hi[in], b = s_hi[jn], h = hole[id];
+  if constexpr (sizeof(R) == 8) {
+    o_hi[id] = ((R)0.75 * a + (R)0.25 * b) + h;
+    if (o_lo) o_lo[id] = 0;
+  } else if (!compensated) {
+    o_hi[id] = ((R)0.75 * a + (R)0.25 * b) + h;
+    if (o_lo) o_lo[id] = 0;
+  } else {
+    const R p1 = (R)0.75 * a;
+    const R e1 = __builtin_fmaf((R)0.75, a, -p1);
+    const R p2 = (R)0.25 * b;
+    R s, e2;
+    two_sum(p1, p2, s, e2);
+    R l = e1 + e2;
+    if (s_lo) l += (R)0.75 * s_lo[in] + (R)0.25 * s_lo[jn];
+    R s2, e3;
+    two_sum(s, h, s2, e3);
+    l += e3;
+    const R hi2 = s2 + l;  // renormalise
+    o_hi[id] = hi2;
+    o_lo[id] = l - (hi2 - s2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Green spectrum, FP64.  The kernel on the doubled mesh is even in every
+// axis, so its transform is real and even and separable passes over the
+// octant [0, P/2]^3 suffice: each line of P values is rebuilt by even
+// extension, transformed, and the real parts of k = 0..P/2 are kept.
+template <int P>
+__global__ void __launch_bounds__((Cfg<double, P>::WC * Cfg<double, P>::TL))
+k_green(int pass, double beta, const double2* tw, const double* __restrict__ src,
+        double* __restrict__ dst) {
+  using C = Cfg<double, P>;
+  constexpr int E = C::E, TL = C::TL, W = C::WC, H = P / 2 + 1;
+  __shared__ double sre[W * P], sim[W * P];
+  const int t = threadIdx.x % TL, w = threadIdx.x / TL;
+  const int line = blockIdx.x * W + w;
+  const bool active = line < H * H;
+  const int a = active ? line % H : 0, b = active ? line / H : 0;
+  double2 v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int n = t + TL * q;
+    const int d = n <= P / 2 ? n : P - n;
+    double val = 0;
+    if (active) {
+      if (pass == 0) {
+        const double r2 = (double)d * d + (double)a * a + (double)b * b;
+        val = r2 == 0 ? beta : 1.0 / sqrt(r2);
+      } else if (pass == 1) {
+        val = src[((size_t)b * H + d) * H + a];
+      } else {
+        val = src[((size_t)d * H + b) * H + a];
+      }
+    }
+    v[q] = double2{val, 0};
+  }
+  LdsView<double> lds{sre, sim, 1, P, w};
+  fft_line<double, P, -1, false, false>(v, t, lds, tw);
+  if (!active) return;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int k = t + TL * q;
+    if (k <= P / 2) {
+      size_t o;
+      if (pass == 0) o = ((size_t)b * H + a) * H + k;
+      else if (pass == 1) o = ((size_t)b * H + k) * H + a;
+      else o = ((size_t)k * H + b) * H + a;
+      dst[o] = v[q].x;
+    }
+  }
+}
+
+__global__ void k_round_f32(const double* __restrict__ in, float* __restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+// Diagnostic: batched unpruned 1-D FFT of contiguous lines.
+template <class R, int P, int DIR>
+__global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
+k_fft_lines(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out, int nlines,
+            const cplx<R>* tw) {
+  using C = Cfg<R, P>;
+  constexpr int E = C::E, TL = C::TL, W = C::WC;
+  __shared__ R sre[W * P], sim[W * P];
+  const int t = threadIdx.x % TL, w = threadIdx.x / TL;
+  const int line = blockIdx.x * W + w;
+  const bool active = line < nlines;
+  cplx<R> v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q)
+    v[q] = active ? in[(size_t)line * P + t + TL * q] : cplx<R>{0, 0};
+  LdsView<R> lds{sre, sim, 1, P, w};
+  fft_line<R, P, DIR, false, false>(v, t, lds, tw);
+  if (!active) return;
+#pragma unroll
+  for (int q = 0; q < E; ++q) out[(size_t)line * P + t + TL * q] = v[q];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+
+template <class F>
+static hipError_t dispatch_p(int P, F&& f) {
+  switch (P) {
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    case 128: f(std::integral_constant<int, 128>{}); break;
+    case 256: f(std::integral_constant<int, 256>{}); break;
+    case 512: f(std::integral_constant<int, 512>{}); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  return dispatch_p(g.P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    using C = Cfg<R, PP>;
+    dim3 grid((g.N * g.N + C::WC - 1) / C::WC, g.nf);
+    hipLaunchKernelGGL((k_fwd_x<R, PP>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+  });
+}
+
+template <class R>
+hipError_t launch_fwd_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  return dispatch_p(g.P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    using C = Cfg<R, PP>;
+    dim3 grid(((PP / 2) / C::WS) * g.N, g.nf);
+    hipLaunchKernelGGL((k_fwd_y<R, PP>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+  });
+}
+
+template <class R>
+hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  return dispatch_p(g.P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    using C = Cfg<R, PP>;
+    dim3 grid(((PP / 2) / C::WZ) * (PP / 2), g.nf);
+    hipLaunchKernelGGL((k_z<R, PP>), grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
+  });
+}
+
+template <class R>
+hipError_t launch_inv_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  return dispatch_p(g.P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    using C = Cfg<R, PP>;
+    dim3 grid(((PP / 2) / C::WS) * g.N, g.nf);
+    hipLaunchKernelGGL((k_inv_y<R, PP>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+  });
+}
+
+template <class R>
+hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  return dispatch_p(g.P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    using C = Cfg<R, PP>;
+    dim3 grid((g.N * g.N + C::WC - 1) / C::WC, g.nf);
+    hipLaunchKernelGGL((k_inv_x<R, PP>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+  });
+}
+
+template <class R>
+hipError_t launch_restrict(const R* fine, const R* fine_rc, R* rc, int N, hipStream_t s) {
+  const int n = (N / 2) * (N / 2) * (N / 2);
+  hipLaunchKernelGGL(k_restrict<R>, dim3((n + 255) / 256), dim3(256), 0, s, fine, fine_rc, rc, N);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_carry(const R* s_hi, const R* s_lo, const R* hole, R* o_hi, R* o_lo, int N,
+                        int compensated, hipStream_t s) {
+  const int NS = N / 2 + 2, n = NS * NS * NS;
+  hipLaunchKernelGGL(k_carry<R>, dim3((n + 255) / 256), dim3(256), 0, s, s_hi, s_lo, hole, o_hi,
+                     o_lo, N, compensated);
+  return hipGetLastError();
+}
+
+hipError_t launch_green(int P, double beta, const double2* tw, double* t1, double* t2, double* out,
+                        hipStream_t s) {
+  return dispatch_p(P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    using C = Cfg<double, PP>;
+    constexpr int H = PP / 2 + 1;
+    dim3 grid((H * H + C::WC - 1) / C::WC);
+    dim3 block(C::WC * C::TL);
+    hipLaunchKernelGGL(k_green<PP>, grid, block, 0, s, 0, beta, tw, (const double*)nullptr, t1);
+    hipLaunchKernelGGL(k_green<PP>, grid, block, 0, s, 1, beta, tw, (const double*)t1, t2);
+    hipLaunchKernelGGL(k_green<PP>, grid, block, 0, s, 2, beta, tw, (const double*)t2, out);
+  });
+}
+
+hipError_t launch_round_f32(const double* in, float* out, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_fft_lines(const void* in, void* out, int P, int nlines, int dir, const void* tw,
+                            hipStream_t s) {
+  using T = cplx<R>;
+  return dispatch_p(P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    using C = Cfg<R, PP>;
+    dim3 grid((nlines + C::WC - 1) / C::WC), block(C::WC * C::TL);
+    if (dir < 0)
+      hipLaunchKernelGGL((k_fft_lines<R, PP, -1>), grid, block, 0, s, (const T*)in, (T*)out,
+                         nlines, (const T*)tw);
+    else
+      hipLaunchKernelGGL((k_fft_lines<R, PP, +1>), grid, block, 0, s, (const T*)in, (T*)out,
+                         nlines, (const T*)tw);
+  });
+}
+
+#define NMC_INSTANTIATE(R)                                                                        \
+  template hipError_t launch_fwd_x<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
+  template hipError_t launch_fwd_y<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
+  template hipError_t launch_z<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);           \
+  template hipError_t launch_inv_y<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
+  template hipError_t launch_inv_x<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
+  template hipError_t launch_restrict<R>(const R*, const R*, R*, int, hipStream_t);               \
+  template hipError_t launch_carry<R>(const R*, const R*, const R*, R*, R*, int, int, hipStream_t); \
+  template hipError_t launch_fft_lines<R>(const void*, void*, int, int, int, const void*, hipStream_t);
+
+NMC_INSTANTIATE(double)
+NMC_INSTANTIATE(float)
+
+}  // namespace nmc

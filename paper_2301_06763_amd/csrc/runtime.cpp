@@ -1,0 +1,707 @@
+// libnmc runtime and C ABI: context, tables, Green-spectrum cache, workspace
+// pool, the batched nested solve, and the continuous-batching serving loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/nmc.h"
+#include "kernels.h"
+
+namespace {
+
+using nmc::FieldDesc;
+using nmc::FieldTable;
+using nmc::PassGeom;
+
+constexpr int kMinN = 4;
+constexpr int kMaxL = 16;
+constexpr int kMaxP = 512;
+constexpr size_t kAlign = 256;
+constexpr int kServeStreams = 4;
+constexpr int kMaxBatchRequests = 32;
+
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+int period_of(int N) {
+  if (N < kMinN || N % 4 != 0) return 0;
+  int P = 8;
+  while (P < 2 * N) P *= 2;
+  return P <= kMaxP ? P : 0;
+}
+
+size_t real_size(nmc_precision p) { return p == NMC_F64 ? 8 : 4; }
+
+// Workspace layout of one request (offsets from its base).
+struct Layout {
+  int N, L, P;
+  size_t r, c;
+  size_t a_bytes, b_bytes, rc_bytes, box_bytes;
+  size_t total;
+  // field f: 0..L-1 full level f, L..2L-2 hole level f-L
+  size_t A(int f) const { return f * (a_bytes + b_bytes); }
+  size_t B(int f) const { return A(f) + a_bytes; }
+  size_t fields_end() const { return (size_t)(2 * L - 1) * (a_bytes + b_bytes); }
+  size_t Rc(int l) const { return fields_end() + (size_t)l * rc_bytes; }            // l < L-1
+  size_t H(int l) const { return Rc(0) + (size_t)(L - 1) * rc_bytes + l * box_bytes; }  // l < L-1
+  size_t Shi(int l) const { return H(0) + (size_t)(L - 1) * box_bytes + (size_t)(l - 1) * 2 * box_bytes; }  // 1 <= l <= L-2
+  size_t Slo(int l) const { return Shi(l) + box_bytes; }
+};
+
+Layout make_layout(int N, int L, nmc_precision p) {
+  Layout lo{};
+  lo.N = N;
+  lo.L = L;
+  lo.P = period_of(N);
+  lo.r = real_size(p);
+  lo.c = 2 * lo.r;
+  const size_t P = lo.P, NS = N / 2 + 2;
+  lo.a_bytes = align_up((size_t)N * N * (P / 2) * lo.c);
+  lo.b_bytes = align_up((size_t)N * P * (P / 2) * lo.c);
+  lo.rc_bytes = align_up((size_t)(N / 2) * (N / 2) * (N / 2) * lo.r);
+  lo.box_bytes = align_up(NS * NS * NS * lo.r);
+  lo.total = lo.fields_end() + (size_t)(L - 1) * lo.rc_bytes + (size_t)(L - 1) * lo.box_bytes +
+             (size_t)std::max(0, L - 2) * 2 * lo.box_bytes;
+  lo.total = std::max(lo.total, kAlign);
+  return lo;
+}
+
+struct Req {
+  const void* rho;
+  void* phi;
+  int N, L;
+  double h0, G;
+  nmc_precision p;
+  unsigned flags;
+};
+
+struct Block {
+  void* ptr;
+  size_t bytes;
+};
+
+struct Lease {
+  std::vector<Block> blocks;
+  hipEvent_t ev = nullptr;
+};
+
+struct PerP {
+  void* tw64 = nullptr;  // double2[P]
+  void* tw32 = nullptr;  // float2[P]
+  double* g64 = nullptr;
+  float* g32 = nullptr;
+};
+
+struct ServeItem {
+  Req r;
+  size_t bytes;
+  int state;  // 0 queued, 1 in flight, 2 done
+};
+
+struct Batch {
+  std::vector<uint64_t> tickets;
+  Lease lease;
+  size_t bytes;
+};
+
+}  // namespace
+
+struct nmc_ctx {
+  int device = 0;
+  size_t budget = 0;
+  std::string err = "no error";
+  std::map<int, PerP> perp;
+  // workspace pool
+  std::vector<Block> free_blocks;
+  std::deque<Lease> leases;  // outstanding (event not yet observed complete)
+  size_t allocated = 0;      // pool + leased
+  // serving
+  hipStream_t streams[kServeStreams] = {};
+  int next_stream = 0;
+  uint64_t next_ticket = 1;
+  std::unordered_map<uint64_t, ServeItem> items;
+  std::deque<uint64_t> queue;
+  std::deque<Batch> inflight;
+  nmc_serve_stats stats{};
+};
+
+namespace {
+
+int fail(nmc_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int hip_fail(nmc_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, NMC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define NMC_HIP(ctx, call)                         \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+// --- tables ------------------------------------------------------------------
+
+int ensure_twiddles(nmc_ctx* ctx, int P, PerP& pp) {
+  if (pp.tw64) return NMC_OK;
+  std::vector<double> t64(2 * P);
+  std::vector<float> t32(2 * P);
+  // exp(-2 pi i j / P), evaluated in long double and rounded once per type
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int j = 0; j < P; ++j) {
+    const long double a = two_pi * (long double)j / (long double)P;
+    const long double c = cosl(a), s = -sinl(a);
+    t64[2 * j] = (double)c;
+    t64[2 * j + 1] = (double)s;
+    t32[2 * j] = (float)c;
+    t32[2 * j + 1] = (float)s;
+  }
+  NMC_HIP(ctx, hipMalloc(&pp.tw64, sizeof(double) * 2 * P));
+  NMC_HIP(ctx, hipMalloc(&pp.tw32, sizeof(float) * 2 * P));
+  NMC_HIP(ctx, hipMemcpy(pp.tw64, t64.data(), sizeof(double) * 2 * P, hipMemcpyHostToDevice));
+  NMC_HIP(ctx, hipMemcpy(pp.tw32, t32.data(), sizeof(float) * 2 * P, hipMemcpyHostToDevice));
+  return NMC_OK;
+}
+
+// Self-cell integral of 1/r over the unit cube (Eq. 13 of the paper):
+// 3 ln(2 + sqrt 3) - pi / 2.
+double self_cell_integral() {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  return (double)(3.0L * logl(2.0L + sqrtl(3.0L)) - pi / 2.0L);
+}
+
+int ensure_green(nmc_ctx* ctx, int P, hipStream_t s) {
+  PerP& pp = ctx->perp[P];
+  int rc = ensure_twiddles(ctx, P, pp);
+  if (rc) return rc;
+  if (pp.g64) return NMC_OK;
+  const size_t H = P / 2 + 1, n = H * H * H;
+  double *t1 = nullptr, *t2 = nullptr;
+  NMC_HIP(ctx, hipMalloc(&pp.g64, n * sizeof(double)));
+  NMC_HIP(ctx, hipMalloc(&pp.g32, n * sizeof(float)));
+  NMC_HIP(ctx, hipMalloc(&t1, n * sizeof(double)));
+  NMC_HIP(ctx, hipMalloc(&t2, n * sizeof(double)));
+  hipError_t e = nmc::launch_green(P, self_cell_integral(), (const double2*)pp.tw64, t1, t2, pp.g64, s);
+  if (e == hipSuccess) e = nmc::launch_round_f32(pp.g64, pp.g32, n, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(t1);
+  (void)hipFree(t2);
+  if (e != hipSuccess) {
+    (void)hipFree(pp.g64);
+    (void)hipFree(pp.g32);
+    pp.g64 = nullptr;
+    pp.g32 = nullptr;
+    return hip_fail(ctx, e, "green spectrum build");
+  }
+  return NMC_OK;
+}
+
+// --- workspace pool ------------------------------------------------------------
+
+void reap_leases(nmc_ctx* ctx, bool wait_oldest) {
+  while (!ctx->leases.empty()) {
+    Lease& l = ctx->leases.front();
+    hipError_t q = wait_oldest ? hipEventSynchronize(l.ev) : hipEventQuery(l.ev);
+    if (q == hipErrorNotReady) break;
+    for (auto& b : l.blocks) ctx->free_blocks.push_back(b);
+    (void)hipEventDestroy(l.ev);
+    ctx->leases.pop_front();
+    wait_oldest = false;
+  }
+}
+
+int pool_alloc(nmc_ctx* ctx, size_t bytes, Block* out) {
+  bytes = align_up(bytes, 2u << 20);
+  reap_leases(ctx, false);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    // best fit among cached blocks within 2x
+    int best = -1;
+    for (size_t i = 0; i < ctx->free_blocks.size(); ++i) {
+      const Block& b = ctx->free_blocks[i];
+      if (b.bytes >= bytes && b.bytes < 2 * bytes && (best < 0 || b.bytes < ctx->free_blocks[best].bytes))
+        best = (int)i;
+    }
+    if (best >= 0) {
+      *out = ctx->free_blocks[best];
+      ctx->free_blocks.erase(ctx->free_blocks.begin() + best);
+      return NMC_OK;
+    }
+    // release cached blocks while over budget (or before a fresh allocation fails)
+    while (ctx->budget && ctx->allocated + bytes > ctx->budget && !ctx->free_blocks.empty()) {
+      auto it = std::max_element(ctx->free_blocks.begin(), ctx->free_blocks.end(),
+                                 [](const Block& a, const Block& b) { return a.bytes < b.bytes; });
+      (void)hipFree(it->ptr);
+      ctx->allocated -= it->bytes;
+      ctx->free_blocks.erase(it);
+    }
+    if (!ctx->budget || ctx->allocated + bytes <= ctx->budget) {
+      void* p = nullptr;
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e == hipSuccess) {
+        ctx->allocated += bytes;
+        *out = Block{p, bytes};
+        return NMC_OK;
+      }
+      (void)hipGetLastError();
+      // free every cached block and retry once
+      for (auto& b : ctx->free_blocks) {
+        (void)hipFree(b.ptr);
+        ctx->allocated -= b.bytes;
+      }
+      ctx->free_blocks.clear();
+      e = hipMalloc(&p, bytes);
+      if (e == hipSuccess) {
+        ctx->allocated += bytes;
+        *out = Block{p, bytes};
+        return NMC_OK;
+      }
+      (void)hipGetLastError();
+    }
+    if (ctx->leases.empty()) break;
+    reap_leases(ctx, true);  // wait for the oldest outstanding solve, then retry
+  }
+  return fail(ctx, NMC_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes does not fit (budget " +
+                                   std::to_string(ctx->budget) + ")");
+}
+
+int lease_close(nmc_ctx* ctx, Lease&& lease, hipStream_t s, std::deque<Lease>* into) {
+  NMC_HIP(ctx, hipEventCreateWithFlags(&lease.ev, hipEventDisableTiming));
+  NMC_HIP(ctx, hipEventRecord(lease.ev, s));
+  into->push_back(std::move(lease));
+  return NMC_OK;
+}
+
+// --- validation ----------------------------------------------------------------
+
+int validate(nmc_ctx* ctx, const Req& r, int refine) {
+  if (!r.rho || !r.phi) return fail(ctx, NMC_EINVAL, "rho and phi must be non-null device pointers");
+  if (r.N < kMinN || r.N % 4 != 0) return fail(ctx, NMC_EINVAL, "N must be a multiple of 4, >= 4");
+  if (!period_of(r.N)) return fail(ctx, NMC_EUNSUPPORTED, "N above 256 (padded period above 512)");
+  if (r.L < 1 || r.L > kMaxL) return fail(ctx, NMC_EINVAL, "L must be in [1, 16]");
+  if (!(r.h0 > 0) || !std::isfinite(r.h0)) return fail(ctx, NMC_EINVAL, "h0 must be positive and finite");
+  if (!std::isfinite(r.G)) return fail(ctx, NMC_EINVAL, "G must be finite");
+  if (refine != 2) return fail(ctx, NMC_EINVAL, "refinement factor must be 2");
+  if (r.p != NMC_F64 && r.p != NMC_F32) return fail(ctx, NMC_EINVAL, "unknown precision");
+  const size_t bytes = (size_t)r.L * r.N * r.N * r.N * real_size(r.p);
+  const char* a = (const char*)r.rho;
+  const char* b = (const char*)r.phi;
+  if (a < b + bytes && b < a + bytes) return fail(ctx, NMC_EINVAL, "rho and phi overlap");
+  return NMC_OK;
+}
+
+// --- the solve -------------------------------------------------------------------
+
+template <class R>
+int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s) {
+  const int N = reqs[0].N;
+  const int P = period_of(N);
+  PerP& pp = ctx->perp[P];
+  nmc::Tables<R> tb;
+  if constexpr (sizeof(R) == 8) {
+    tb.tw = (const double2*)pp.tw64;
+    tb.green = pp.g64;
+  } else {
+    tb.tw = (const float2*)pp.tw32;
+    tb.green = pp.g32;
+  }
+  const size_t lvl = (size_t)N * N * N;
+  std::vector<FieldDesc> fulls, holes;
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    const Req& q = reqs[i];
+    const Layout lo = make_layout(N, q.L, q.p);
+    char* base = ws + off;
+    off += lo.total;
+    const R* rho = (const R*)q.rho;
+    R* phi = (R*)q.phi;
+    const bool restrict_on = !(q.flags & NMC_NO_RESTRICT);
+    const bool comp = !(q.flags & NMC_F32_UNCOMPENSATED);
+    if (restrict_on) {
+      for (int l = q.L - 2; l >= 0; --l) {
+        const R* fine_rc = (l + 1 <= q.L - 2) ? (const R*)(base + lo.Rc(l + 1)) : nullptr;
+        NMC_HIP(ctx, nmc::launch_restrict<R>(rho + (size_t)(l + 1) * lvl, fine_rc, (R*)(base + lo.Rc(l)), N, s));
+      }
+    }
+    const double P3 = (double)P * P * P;
+    for (int l = 0; l < q.L; ++l) {
+      const double h = std::ldexp(q.h0, -l);
+      FieldDesc f{};
+      f.rho = rho + (size_t)l * lvl;
+      f.rc = (restrict_on && l < q.L - 1) ? (const void*)(base + lo.Rc(l)) : nullptr;
+      f.A = base + lo.A(l);
+      f.B = base + lo.B(l);
+      f.out = phi + (size_t)l * lvl;
+      f.scale = -q.G * h * h / P3;
+      f.hole = 0;
+      f.has_carry = l >= 1;
+      if (l == 1) {
+        f.S = base + lo.H(0);
+        f.Slo = nullptr;
+      } else if (l >= 2) {
+        f.S = base + lo.Shi(l - 1);
+        f.Slo = (sizeof(R) == 4 && comp) ? (const void*)(base + lo.Slo(l - 1)) : nullptr;
+      }
+      fulls.push_back(f);
+      if (l < q.L - 1) {
+        FieldDesc hf{};
+        hf.rho = f.rho;
+        hf.rc = nullptr;
+        hf.A = base + lo.A(q.L + l);
+        hf.B = base + lo.B(q.L + l);
+        hf.out = base + lo.H(l);
+        hf.scale = f.scale;
+        hf.hole = 1;
+        holes.push_back(hf);
+      }
+    }
+  }
+  std::vector<FieldDesc> all(fulls);
+  all.insert(all.end(), holes.begin(), holes.end());
+  auto for_chunks = [&](const std::vector<FieldDesc>& fs, auto launch) -> hipError_t {
+    for (size_t a = 0; a < fs.size(); a += nmc::kMaxFieldsPerLaunch) {
+      FieldTable ft{};
+      const int n = (int)std::min<size_t>(nmc::kMaxFieldsPerLaunch, fs.size() - a);
+      for (int k = 0; k < n; ++k) ft.f[k] = fs[a + k];
+      PassGeom g{N, P, n, 0};
+      hipError_t e = launch(ft, g, tb, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  NMC_HIP(ctx, for_chunks(all, nmc::launch_fwd_x<R>));
+  NMC_HIP(ctx, for_chunks(all, nmc::launch_fwd_y<R>));
+  NMC_HIP(ctx, for_chunks(all, nmc::launch_z<R>));
+  NMC_HIP(ctx, for_chunks(all, nmc::launch_inv_y<R>));
+  if (!holes.empty()) NMC_HIP(ctx, for_chunks(holes, nmc::launch_inv_x<R>));
+  // carry cascade per request: S_n = Prolong(S_{n-1}) + Phi^n_hole, S_0 = Phi^0_hole
+  off = 0;
+  for (int i = 0; i < count; ++i) {
+    const Req& q = reqs[i];
+    const Layout lo = make_layout(N, q.L, q.p);
+    char* base = ws + off;
+    off += lo.total;
+    const bool comp = sizeof(R) == 4 && !(q.flags & NMC_F32_UNCOMPENSATED);
+    for (int n = 1; n <= q.L - 2; ++n) {
+      const R* shi = (const R*)(base + (n == 1 ? lo.H(0) : lo.Shi(n - 1)));
+      const R* slo = (n == 1 || !comp) ? nullptr : (const R*)(base + lo.Slo(n - 1));
+      NMC_HIP(ctx, nmc::launch_carry<R>(shi, slo, (const R*)(base + lo.H(n)), (R*)(base + lo.Shi(n)),
+                                        comp ? (R*)(base + lo.Slo(n)) : nullptr, N, comp ? 1 : 0, s));
+    }
+  }
+  NMC_HIP(ctx, for_chunks(fulls, nmc::launch_inv_x<R>));
+  return NMC_OK;
+}
+
+int prepare(nmc_ctx* ctx, int N, hipStream_t s) {
+  const int P = period_of(N);
+  return ensure_green(ctx, P, s);
+}
+
+// Launch requests that share N and precision, on one workspace block.
+int launch_group(nmc_ctx* ctx, const Req* reqs, int count, hipStream_t s, Lease* lease) {
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) total += make_layout(reqs[i].N, reqs[i].L, reqs[i].p).total;
+  int rc = prepare(ctx, reqs[0].N, s);
+  if (rc) return rc;
+  Block b{};
+  rc = pool_alloc(ctx, total, &b);
+  if (rc) return rc;
+  lease->blocks.push_back(b);
+  if (reqs[0].p == NMC_F64) return run_group<double>(ctx, reqs, count, (char*)b.ptr, s);
+  return run_group<float>(ctx, reqs, count, (char*)b.ptr, s);
+}
+
+int solve_many(nmc_ctx* ctx, const Req* reqs, int count, hipStream_t s, Lease* lease) {
+  // group by (N, precision), preserving order inside a group
+  std::map<std::pair<int, int>, std::vector<Req>> groups;
+  for (int i = 0; i < count; ++i) groups[{reqs[i].N, (int)reqs[i].p}].push_back(reqs[i]);
+  for (auto& kv : groups) {
+    auto& v = kv.second;
+    for (size_t a = 0; a < v.size(); a += kMaxBatchRequests) {
+      const int n = (int)std::min<size_t>(kMaxBatchRequests, v.size() - a);
+      int rc = launch_group(ctx, v.data() + a, n, s, lease);
+      if (rc) return rc;
+    }
+  }
+  return NMC_OK;
+}
+
+int set_device(nmc_ctx* ctx) {
+  NMC_HIP(ctx, hipSetDevice(ctx->device));
+  return NMC_OK;
+}
+
+// --- serving ------------------------------------------------------------------
+
+int serve_tick(nmc_ctx* ctx, int* launched) {
+  int n_launched = 0;
+  // 1. retire finished batches
+  while (!ctx->inflight.empty()) {
+    Batch& b = ctx->inflight.front();
+    hipError_t q = hipEventQuery(b.lease.ev);
+    if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) return hip_fail(ctx, q, "serving batch");
+    for (uint64_t t : b.tickets) {
+      ctx->items[t].state = 2;
+      ctx->stats.completed++;
+    }
+    for (auto& blk : b.lease.blocks) ctx->free_blocks.push_back(blk);
+    (void)hipEventDestroy(b.lease.ev);
+    ctx->stats.inflight_bytes -= b.bytes;
+    ctx->stats.inflight -= b.tickets.size();
+    ctx->inflight.pop_front();
+  }
+  // 2. admit in arrival order while the footprint fits
+  std::vector<uint64_t> admitted;
+  size_t bytes = ctx->stats.inflight_bytes;
+  while (!ctx->queue.empty()) {
+    const uint64_t t = ctx->queue.front();
+    const ServeItem& it = ctx->items[t];
+    if (ctx->budget && bytes + it.bytes > ctx->budget) break;
+    bytes += it.bytes;
+    admitted.push_back(t);
+    ctx->queue.pop_front();
+  }
+  // 3. one batch per (N, precision) group, each on the next serving stream
+  std::map<std::pair<int, int>, std::vector<uint64_t>> groups;
+  for (uint64_t t : admitted) groups[{ctx->items[t].r.N, (int)ctx->items[t].r.p}].push_back(t);
+  for (auto& kv : groups) {
+    auto& ts = kv.second;
+    for (size_t a = 0; a < ts.size(); a += kMaxBatchRequests) {
+      const size_t n = std::min<size_t>(kMaxBatchRequests, ts.size() - a);
+      Batch b;
+      std::vector<Req> rs;
+      b.bytes = 0;
+      for (size_t k = 0; k < n; ++k) {
+        const uint64_t t = ts[a + k];
+        rs.push_back(ctx->items[t].r);
+        b.tickets.push_back(t);
+        b.bytes += ctx->items[t].bytes;
+        ctx->items[t].state = 1;
+      }
+      hipStream_t s = ctx->streams[ctx->next_stream];
+      ctx->next_stream = (ctx->next_stream + 1) % kServeStreams;
+      int rc = launch_group(ctx, rs.data(), (int)n, s, &b.lease);
+      if (rc) return rc;
+      NMC_HIP(ctx, hipEventCreateWithFlags(&b.lease.ev, hipEventDisableTiming));
+      NMC_HIP(ctx, hipEventRecord(b.lease.ev, s));
+      ctx->stats.admitted += n;
+      ctx->stats.inflight += n;
+      ctx->stats.batches++;
+      ctx->stats.inflight_bytes += b.bytes;
+      ctx->stats.peak_inflight_bytes = std::max(ctx->stats.peak_inflight_bytes, ctx->stats.inflight_bytes);
+      n_launched += (int)n;
+      ctx->inflight.push_back(std::move(b));
+    }
+  }
+  ctx->stats.queued = ctx->queue.size();
+  if (launched) *launched = n_launched;
+  return NMC_OK;
+}
+
+}  // namespace
+
+// ================================ C ABI ======================================
+
+extern "C" {
+
+int nmc_period(int N) { return period_of(N); }
+
+int nmc_footprint_bytes(int N, int L, nmc_precision p, size_t* bytes) {
+  if (!bytes || N < kMinN || N % 4 != 0 || L < 1 || L > kMaxL || (p != NMC_F64 && p != NMC_F32))
+    return NMC_EINVAL;
+  if (!period_of(N)) return NMC_EUNSUPPORTED;
+  *bytes = make_layout(N, L, p).total;
+  return NMC_OK;
+}
+
+int nmc_create(nmc_ctx** out, int hip_device, size_t hbm_budget_bytes) {
+  if (!out) return NMC_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return NMC_EINVAL;
+  auto* ctx = new nmc_ctx();
+  ctx->device = hip_device;
+  ctx->budget = hbm_budget_bytes;
+  ctx->stats.budget_bytes = hbm_budget_bytes;
+  if (hipSetDevice(hip_device) != hipSuccess) {
+    delete ctx;
+    return NMC_EDEVICE;
+  }
+  for (auto& s : ctx->streams) {
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      delete ctx;
+      return NMC_EDEVICE;
+    }
+  }
+  *out = ctx;
+  return NMC_OK;
+}
+
+void nmc_destroy(nmc_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  reap_leases(ctx, false);
+  for (auto& b : ctx->inflight)
+    for (auto& blk : b.lease.blocks) (void)hipFree(blk.ptr);
+  for (auto& l : ctx->leases)
+    for (auto& blk : l.blocks) (void)hipFree(blk.ptr);
+  for (auto& b : ctx->free_blocks) (void)hipFree(b.ptr);
+  for (auto& kv : ctx->perp) {
+    (void)hipFree(kv.second.tw64);
+    (void)hipFree(kv.second.tw32);
+    (void)hipFree(kv.second.g64);
+    (void)hipFree(kv.second.g32);
+  }
+  for (auto& s : ctx->streams) (void)hipStreamDestroy(s);
+  delete ctx;
+}
+
+const char* nmc_last_error(const nmc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int nmc_solve(nmc_ctx* ctx, const void* rho, void* phi, int N, int L, double h0, int refine, double G,
+              nmc_precision p, unsigned flags, void* hip_stream) {
+  if (!ctx) return NMC_EINVAL;
+  Req r{rho, phi, N, L, h0, G, p, flags};
+  int rc = validate(ctx, r, refine);
+  if (rc) return rc;
+  if ((rc = set_device(ctx))) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  Lease lease;
+  rc = solve_many(ctx, &r, 1, s, &lease);
+  if (rc) {
+    (void)hipStreamSynchronize(s);  // nothing enqueued before the failure may still use the workspace
+    for (auto& b : lease.blocks) ctx->free_blocks.push_back(b);
+    return rc;
+  }
+  return lease_close(ctx, std::move(lease), s, &ctx->leases);
+}
+
+int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_stream) {
+  if (!ctx) return NMC_EINVAL;
+  if (count < 0 || (count > 0 && !reqs)) return fail(ctx, NMC_EINVAL, "bad request array");
+  std::vector<Req> rs;
+  for (int i = 0; i < count; ++i) {
+    Req r{reqs[i].rho, reqs[i].phi, reqs[i].N, reqs[i].L, reqs[i].h0, reqs[i].G, reqs[i].p, reqs[i].flags};
+    int rc = validate(ctx, r, 2);
+    if (rc) return fail(ctx, rc, "request " + std::to_string(i) + ": " + ctx->err);
+    rs.push_back(r);
+  }
+  if (count == 0) return NMC_OK;
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  Lease lease;
+  rc = solve_many(ctx, rs.data(), count, s, &lease);
+  if (rc) {
+    (void)hipStreamSynchronize(s);
+    for (auto& b : lease.blocks) ctx->free_blocks.push_back(b);
+    return rc;
+  }
+  return lease_close(ctx, std::move(lease), s, &ctx->leases);
+}
+
+int nmc_serve_submit(nmc_ctx* ctx, const nmc_request* req, uint64_t* ticket) {
+  if (!ctx) return NMC_EINVAL;
+  if (!req || !ticket) return fail(ctx, NMC_EINVAL, "null request or ticket");
+  Req r{req->rho, req->phi, req->N, req->L, req->h0, req->G, req->p, req->flags};
+  int rc = validate(ctx, r, 2);
+  if (rc) return rc;
+  const size_t bytes = align_up(make_layout(r.N, r.L, r.p).total, 2u << 20);
+  if (ctx->budget && bytes > ctx->budget)
+    return fail(ctx, NMC_ENOMEM, "request footprint " + std::to_string(bytes) + " exceeds the budget");
+  const uint64_t t = ctx->next_ticket++;
+  ctx->items[t] = ServeItem{r, bytes, 0};
+  ctx->queue.push_back(t);
+  ctx->stats.submitted++;
+  ctx->stats.queued = ctx->queue.size();
+  *ticket = t;
+  return NMC_OK;
+}
+
+int nmc_serve_tick(nmc_ctx* ctx, int* launched) {
+  if (!ctx) return NMC_EINVAL;
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  return serve_tick(ctx, launched);
+}
+
+int nmc_serve_poll(nmc_ctx* ctx, uint64_t ticket, int* done) {
+  if (!ctx || !done) return NMC_EINVAL;
+  auto it = ctx->items.find(ticket);
+  if (it == ctx->items.end()) return fail(ctx, NMC_EINVAL, "unknown ticket");
+  if (it->second.state != 2) {
+    int rc = nmc_serve_tick(ctx, nullptr);
+    if (rc) return rc;
+  }
+  *done = ctx->items[ticket].state == 2 ? 1 : 0;
+  return NMC_OK;
+}
+
+int nmc_serve_stats_get(nmc_ctx* ctx, nmc_serve_stats* out) {
+  if (!ctx || !out) return NMC_EINVAL;
+  *out = ctx->stats;
+  out->budget_bytes = ctx->budget;
+  return NMC_OK;
+}
+
+int nmc_serve_drain(nmc_ctx* ctx) {
+  if (!ctx) return NMC_EINVAL;
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  while (!ctx->queue.empty() || !ctx->inflight.empty()) {
+    if ((rc = serve_tick(ctx, nullptr))) return rc;
+    if (!ctx->inflight.empty()) NMC_HIP(ctx, hipEventSynchronize(ctx->inflight.front().lease.ev));
+  }
+  return serve_tick(ctx, nullptr);
+}
+
+int nmc_green_spectrum(nmc_ctx* ctx, int N, nmc_precision p, void* out, void* hip_stream) {
+  if (!ctx) return NMC_EINVAL;
+  if (!out) return fail(ctx, NMC_EINVAL, "null output");
+  const int P = period_of(N);
+  if (!P) return fail(ctx, N < kMinN || N % 4 ? NMC_EINVAL : NMC_EUNSUPPORTED, "bad N");
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if ((rc = ensure_green(ctx, P, s))) return rc;
+  const size_t H = P / 2 + 1, n = H * H * H;
+  PerP& pp = ctx->perp[P];
+  if (p == NMC_F64)
+    NMC_HIP(ctx, hipMemcpyAsync(out, pp.g64, n * 8, hipMemcpyDeviceToDevice, s));
+  else
+    NMC_HIP(ctx, hipMemcpyAsync(out, pp.g32, n * 4, hipMemcpyDeviceToDevice, s));
+  return NMC_OK;
+}
+
+int nmc_fft_lines(nmc_ctx* ctx, const void* in, void* out, int P, int nlines, int dir, nmc_precision p,
+                  void* hip_stream) {
+  if (!ctx) return NMC_EINVAL;
+  if (!in || !out || nlines < 0 || (dir != -1 && dir != 1) || P < 8 || P > kMaxP || (P & (P - 1)))
+    return fail(ctx, NMC_EINVAL, "bad fft_lines arguments");
+  if (nlines == 0) return NMC_OK;
+  int rc = set_device(ctx);
+  if (rc) return rc;
+  PerP& pp = ctx->perp[P];
+  if ((rc = ensure_twiddles(ctx, P, pp))) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (p == NMC_F64)
+    NMC_HIP(ctx, nmc::launch_fft_lines<double>(in, out, P, nlines, dir, pp.tw64, s));
+  else
+    NMC_HIP(ctx, nmc::launch_fft_lines<float>(in, out, P, nlines, dir, pp.tw32, s));
+  return NMC_OK;
+}
+
+}  // extern "C"

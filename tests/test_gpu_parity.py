@@ -1,0 +1,299 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+FP64 path: pointwise relative error <= 1e-12 (the zero-padded convolution is
+exact; both sides only differ by rounding).  FP32 path: <= 1e-5 relative to
+the FP64 oracle.  All inputs are seeded and shared by both sides.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2301_06763_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2301_06763_amd import nmc
+    c = nmc.Context()
+    yield c
+    c.close()
+
+
+def rel_err(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    return np.abs(got - ref) / np.abs(ref)
+
+
+def run(ctx, rho_np, h0, dtype=torch.float64, G=1.0, flags=0):
+    rho = torch.from_numpy(np.ascontiguousarray(rho_np)).to("cuda", dtype)
+    phi = ctx.solve(rho, h0, G, flags)
+    torch.cuda.synchronize()
+    return phi.double().cpu().numpy()
+
+
+# --- FFT core and Green spectrum ---------------------------------------------
+
+@pytest.mark.parametrize("P", [8, 16, 32, 64, 128, 256, 512])
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_fft_lines_match_numpy(ctx, P, dtype):
+    rng = np.random.default_rng(P)
+    n = 37
+    x = rng.standard_normal((n, P)) + 1j * rng.standard_normal((n, P))
+    xt = torch.from_numpy(x).to("cuda", dtype)
+    fwd = ctx.fft_lines(xt, -1).cpu().numpy()
+    inv = ctx.fft_lines(xt, +1).cpu().numpy()
+    ref_f = np.fft.fft(x, axis=1)
+    ref_i = np.fft.ifft(x, axis=1) * P
+    tol = 1e-14 if dtype == torch.complex128 else 2e-6
+    for got, ref in ((fwd, ref_f), (inv, ref_i)):
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        assert err < tol * np.log2(P), (P, err)
+
+
+@pytest.mark.parametrize("N", [4, 12, 32, 64])
+def test_green_spectrum_matches_oracle(ctx, N):
+    from scipy import fft as sfft
+    P = 8
+    while P < 2 * N:
+        P *= 2
+    H = P // 2 + 1
+    ref = sfft.rfftn(oracle.green_periodic(P)).real[:H, :H, :H]
+    got = ctx.green_spectrum(N, torch.float64).cpu().numpy()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    assert err < 1e-14
+    got32 = ctx.green_spectrum(N, torch.float32).cpu().numpy()
+    assert np.array_equal(got32, got.astype(np.float32))
+
+
+# --- single and nested solves, FP64 -----------------------------------------
+
+@pytest.mark.parametrize("N,L", [(4, 1), (4, 2), (4, 3), (8, 1), (8, 3), (12, 1), (12, 2),
+                                 (16, 3), (20, 2), (32, 4)])
+def test_random_levels_fp64(ctx, N, L):
+    w = inputs.random_levels(N, L, seed=100 + N + L)
+    rho = w.rho.numpy()
+    ref = oracle.solve(rho, w.h0, G=1.3)
+    got = run(ctx, rho, w.h0, G=1.3)
+    assert np.max(rel_err(got, ref)) < F64_TOL
+
+
+def test_random12_brute_force(ctx):
+    """The 12^3 single-level brute-force check (N=12 runs on a 32^3 period)."""
+    w = inputs.random12()
+    rho = w.rho.numpy()
+    ref = oracle.solve(rho, w.h0, method="direct")
+    got = run(ctx, rho, w.h0)
+    assert np.max(rel_err(got, ref)) < F64_TOL
+
+
+def test_nested_brute_force_12(ctx):
+    w = inputs.random_levels(12, 3, seed=7)
+    rho = w.rho.numpy()
+    ref = oracle.solve(rho, w.h0, method="direct")
+    got = run(ctx, rho, w.h0)
+    assert np.max(rel_err(got, ref)) < F64_TOL
+
+
+def test_no_restrict_flag(ctx):
+    from paper_2301_06763_amd import nmc
+    w = inputs.random_levels(16, 3, seed=3)
+    rho = w.rho.numpy()
+    ref = oracle.solve(rho, w.h0, restrict=False)
+    got = run(ctx, rho, w.h0, flags=nmc.NMC_NO_RESTRICT)
+    assert np.max(rel_err(got, ref)) < F64_TOL
+
+
+def test_point_mass(ctx):
+    N, L = 16, 3
+    rho = np.zeros((L, N, N, N))
+    rho[2, 5, 9, 3] = 1.0
+    rho[0, 1, 14, 2] = 0.5
+    ref = oracle.solve(rho, 0.25)
+    got = run(ctx, rho, 0.25)
+    assert np.max(rel_err(got, ref)) < F64_TOL
+
+
+def test_zero_density_gives_zero(ctx):
+    got = run(ctx, np.zeros((3, 8, 8, 8)), 0.1)
+    assert np.all(got == 0)
+
+
+def test_plummer32_fp64(ctx):
+    w = inputs.plummer32()
+    rho = w.rho.numpy()
+    ref = oracle.solve(rho, w.h0)
+    got = run(ctx, rho, w.h0)
+    assert np.max(rel_err(got, ref)) < F64_TOL
+
+
+@pytest.fixture(scope="module")
+def ellipsoid64():
+    w = inputs.ellipsoid64()
+    rho = w.rho.numpy()
+    return w, rho, oracle.solve(rho, w.h0)
+
+
+def test_ellipsoid64_fp64(ctx, ellipsoid64):
+    w, rho, ref = ellipsoid64
+    got = run(ctx, rho, w.h0)
+    assert np.max(rel_err(got, ref)) < F64_TOL
+
+
+def test_ellipsoid64_fp32(ctx, ellipsoid64):
+    w, rho, ref = ellipsoid64
+    got = run(ctx, rho, w.h0, dtype=torch.float32)
+    e = rel_err(got, ref)
+    for l in range(w.L):
+        print(f"level {l}: max {e[l].max():.3e} rms {np.sqrt((e[l] ** 2).mean()):.3e}")
+    assert np.max(e) < F32_TOL
+
+
+@pytest.fixture(scope="module")
+def binary128():
+    w = inputs.binary128()
+    rho = w.rho.numpy()
+    return w, rho, oracle.solve(rho, w.h0)
+
+
+def test_binary128_fp64(ctx, binary128):
+    w, rho, ref = binary128
+    got = run(ctx, rho, w.h0)
+    assert np.max(rel_err(got, ref)) < F64_TOL
+
+
+def test_binary128_fp32(ctx, binary128):
+    w, rho, ref = binary128
+    got = run(ctx, rho, w.h0, dtype=torch.float32)
+    e = rel_err(got, ref)
+    for l in range(w.L):
+        print(f"level {l}: max {e[l].max():.3e} rms {np.sqrt((e[l] ** 2).mean()):.3e}")
+    assert np.max(e) < F32_TOL
+
+
+def test_fp32_uncompensated_still_within_tolerance(ctx, binary128):
+    from paper_2301_06763_amd import nmc
+    w, rho, ref = binary128
+    got = run(ctx, rho, w.h0, dtype=torch.float32, flags=nmc.NMC_F32_UNCOMPENSATED)
+    assert np.max(rel_err(got, ref)) < F32_TOL
+
+
+def _sample_points(L, N, rng, k=3):
+    pts = []
+    for l in range(L):
+        for _ in range(k):
+            pts.append((l, *[int(v) for v in rng.integers(0, N, size=3)]))
+        # a cell next to the child-region boundary and a corner
+        pts.append((l, N // 4 - 1, N // 2, 3 * N // 4))
+        pts.append((l, 0, N - 1, 0))
+    return pts
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_clumps256_sampled(ctx, dtype):
+    """Full-size 256^3 x 6 levels: sampled cells against the direct sum."""
+    w = inputs.clumps256(device="cuda")
+    rho = w.rho.to(dtype)
+    phi = ctx.solve(rho, w.h0)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(44)
+    pts = _sample_points(w.L, w.N, rng, k=1)
+    ref = oracle.solve_points(w.rho.cpu().numpy(), w.h0, pts)
+    got = np.array([phi[p].item() for p in pts])
+    tol = F64_TOL if dtype == torch.float64 else F32_TOL
+    assert np.max(rel_err(got, ref)) < tol
+
+
+# --- determinism, batching, serving -------------------------------------------
+
+def test_repeat_determinism(ctx):
+    w = inputs.random_levels(32, 3, seed=5)
+    rho = w.rho.cuda()
+    a = ctx.solve(rho, w.h0).clone()
+    b = ctx.solve(rho, w.h0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def _mixed(n, dtype=torch.float64):
+    out = []
+    for i in range(n):
+        N = [8, 16, 12, 32][i % 4]
+        L = 1 + (i % 4)
+        w = inputs.random_levels(N, L, seed=200 + i)
+        out.append((w.rho.to("cuda", dtype), w.h0 * (1 + 0.1 * i), 1.0 + 0.05 * i))
+    return out
+
+
+def test_batch_equals_alone(ctx):
+    items = _mixed(9)
+    alone = [ctx.solve(r, h, G).clone() for r, h, G in items]
+    batch = ctx.solve_batch(items)
+    torch.cuda.synchronize()
+    for a, b in zip(alone, batch):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_serving_mix_equals_alone(dtype):
+    """Requests solved in the continuous-batching mix give bitwise the same
+    result as alone (grids are independent; kernels are deterministic)."""
+    from paper_2301_06763_amd import nmc
+    items = _mixed(12, dtype)
+    c = nmc.Context(budget_bytes=256 << 20)
+    try:
+        alone = [c.solve(r, h, G).clone() for r, h, G in items]
+        tickets = []
+        for k, (r, h, G) in enumerate(items):
+            tickets.append(c.submit(r, h, G))
+            if k % 3 == 0:
+                c.tick()
+        c.drain()
+        for tk, a in zip(tickets, alone):
+            assert c.poll(tk)
+            assert torch.equal(tk.phi, a)
+        st = c.stats()
+        assert st["completed"] == len(items) and st["inflight"] == 0
+        assert st["peak_inflight_bytes"] <= 256 << 20
+    finally:
+        c.close()
+
+
+# --- boundary errors ------------------------------------------------------------
+
+def test_invalid_arguments(ctx):
+    from paper_2301_06763_amd import nmc
+    rho = torch.zeros((2, 8, 8, 8), dtype=torch.float64, device="cuda")
+    out = torch.full_like(rho, 7.0)
+    L = nmc.lib()
+    s = torch.cuda.current_stream().cuda_stream
+    h = ctx._h
+    assert L.nmc_solve(h, rho.data_ptr(), out.data_ptr(), 6, 2, 0.1, 2, 1.0, 0, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_solve(h, rho.data_ptr(), out.data_ptr(), 8, 0, 0.1, 2, 1.0, 0, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_solve(h, rho.data_ptr(), out.data_ptr(), 8, 2, -1.0, 2, 1.0, 0, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_solve(h, rho.data_ptr(), out.data_ptr(), 8, 2, 0.1, 3, 1.0, 0, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_solve(h, rho.data_ptr(), rho.data_ptr(), 8, 2, 0.1, 2, 1.0, 0, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_solve(h, None, out.data_ptr(), 8, 2, 0.1, 2, 1.0, 0, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_solve(h, rho.data_ptr(), out.data_ptr(), 260, 2, 0.1, 2, 1.0, 0, 0, s) == nmc.NMC_EUNSUPPORTED
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)  # untouched on error
+
+
+def test_budget_rejects_oversized_request():
+    from paper_2301_06763_amd import nmc
+    c = nmc.Context(budget_bytes=8 << 20)
+    try:
+        rho = torch.zeros((4, 64, 64, 64), dtype=torch.float64, device="cuda")
+        with pytest.raises(nmc.NmcError) as ei:
+            c.submit(rho, 0.1)
+        assert ei.value.code == nmc.NMC_ENOMEM
+        with pytest.raises(nmc.NmcError) as ei:
+            c.solve(rho, 0.1)
+        assert ei.value.code == nmc.NMC_ENOMEM
+    finally:
+        c.close()
