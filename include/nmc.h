@@ -178,6 +178,33 @@ int nmc_period(int N);
 int nmc_fft_lines(nmc_ctx* ctx, const void* in, void* out, int P, int nlines, int dir,
                   nmc_precision p, void* hip_stream);
 
+/* ---- Per-pass profiling --------------------------------------------------
+ * When enabled, every pass launch of nmc_solve / nmc_solve_batch / serving is
+ * bracketed by two HIP events recorded on the stream it is launched on, and
+ * the pass's algorithmic HBM bytes (the bytes the pruned method must read and
+ * write for the grids of that launch) are accumulated.  Reading synchronises
+ * on the recorded events. */
+enum {
+  NMC_PASS_RESTRICT = 0, NMC_PASS_X = 1, NMC_PASS_Y = 2, NMC_PASS_Z = 3, NMC_PASS_IY = 4,
+  NMC_PASS_IX_HOLE = 5, NMC_PASS_CARRY = 6, NMC_PASS_IX_FULL = 7, NMC_NUM_PASSES = 8
+};
+
+typedef struct {
+  uint64_t launches;  /* kernel launches recorded */
+  double total_ms;    /* summed event-to-event time of those launches */
+  double bytes;       /* summed algorithmic bytes of those launches */
+} nmc_pass_stat;
+
+/* on = 1 enables recording (and clears earlier records), 0 disables. */
+int nmc_profile_enable(nmc_ctx* ctx, int on);
+
+/* Fill out[0..NMC_NUM_PASSES-1] with the totals since the last enable or
+ * read, then clear them.  Blocks until the recorded events complete. */
+int nmc_profile_read(nmc_ctx* ctx, nmc_pass_stat* out);
+
+/* Name of a pass id ("x", "z", ...), or "?" */
+const char* nmc_pass_name(int pass);
+
 #ifdef __cplusplus
 }
 #endif

@@ -132,6 +132,14 @@ struct nmc_ctx {
   std::deque<uint64_t> queue;
   std::deque<Batch> inflight;
   nmc_serve_stats stats{};
+  // per-pass profiling
+  bool profiling = false;
+  struct ProfRec {
+    int pass;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<ProfRec> prof;
 };
 
 namespace {
@@ -300,6 +308,46 @@ int validate(nmc_ctx* ctx, const Req& r, int refine) {
   return NMC_OK;
 }
 
+// --- profiling -------------------------------------------------------------------
+
+struct ProfScope {
+  nmc_ctx* ctx;
+  hipStream_t s;
+  int pass;
+  double bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(nmc_ctx* c, hipStream_t st, int p, double by) : ctx(c), s(st), pass(p), bytes(by) {
+    if (ctx->profiling && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s) == hipSuccess) {
+      ctx->prof.push_back({pass, a, b, bytes});
+    } else {
+      (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  }
+};
+
+// Algorithmic HBM bytes of one grid in each pass (what the pruned method reads
+// and writes with this layout; the zero padding is never touched).
+struct PassBytes {
+  double r, c, N, P, H, Nz;
+  PassBytes(int N_, int P_, size_t rsz, bool hole)
+      : r((double)rsz), c(2.0 * rsz), N(N_), P(P_), H(P_ / 2 + 1), Nz(hole ? N_ / 2 + 2 : N_) {}
+  double half() const { return P / 2; }
+  double x() const { return N * N * N * r + N * N * half() * c; }
+  double y() const { return N * N * half() * c + N * P * half() * c; }
+  double z() const { return N * P * half() * c + Nz * P * half() * c + H * H * H * r; }
+  double iy() const { return Nz * P * half() * c + Nz * Nz * half() * c; }
+  double ix(bool carry) const {
+    const double NS = N / 2 + 2;
+    return Nz * Nz * half() * c + Nz * Nz * Nz * r + (carry ? 2 * NS * NS * NS * r : 0.0);
+  }
+};
+
 // --- the solve -------------------------------------------------------------------
 
 template <class R>
@@ -330,6 +378,8 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s)
     if (restrict_on) {
       for (int l = q.L - 2; l >= 0; --l) {
         const R* fine_rc = (l + 1 <= q.L - 2) ? (const R*)(base + lo.Rc(l + 1)) : nullptr;
+        const double nn = (double)N * N * N;
+        ProfScope ps(ctx, s, NMC_PASS_RESTRICT, (nn + nn / 8) * sizeof(R));
         NMC_HIP(ctx, nmc::launch_restrict<R>(rho + (size_t)(l + 1) * lvl, fine_rc, (R*)(base + lo.Rc(l)), N, s));
       }
     }
@@ -368,22 +418,34 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s)
   }
   std::vector<FieldDesc> all(fulls);
   all.insert(all.end(), holes.begin(), holes.end());
-  auto for_chunks = [&](const std::vector<FieldDesc>& fs, auto launch) -> hipError_t {
+  auto for_chunks = [&](const std::vector<FieldDesc>& fs, auto launch, int pass) -> hipError_t {
     for (size_t a = 0; a < fs.size(); a += nmc::kMaxFieldsPerLaunch) {
       FieldTable ft{};
       const int n = (int)std::min<size_t>(nmc::kMaxFieldsPerLaunch, fs.size() - a);
-      for (int k = 0; k < n; ++k) ft.f[k] = fs[a + k];
+      double bytes = 0;
+      for (int k = 0; k < n; ++k) {
+        ft.f[k] = fs[a + k];
+        const PassBytes pb(N, P, sizeof(R), ft.f[k].hole != 0);
+        switch (pass) {
+          case NMC_PASS_X: bytes += pb.x(); break;
+          case NMC_PASS_Y: bytes += pb.y(); break;
+          case NMC_PASS_Z: bytes += pb.z(); break;
+          case NMC_PASS_IY: bytes += pb.iy(); break;
+          default: bytes += pb.ix(ft.f[k].has_carry != 0); break;
+        }
+      }
       PassGeom g{N, P, n, 0};
+      ProfScope ps(ctx, s, pass, bytes);
       hipError_t e = launch(ft, g, tb, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   };
-  NMC_HIP(ctx, for_chunks(all, nmc::launch_fwd_x<R>));
-  NMC_HIP(ctx, for_chunks(all, nmc::launch_fwd_y<R>));
-  NMC_HIP(ctx, for_chunks(all, nmc::launch_z<R>));
-  NMC_HIP(ctx, for_chunks(all, nmc::launch_inv_y<R>));
-  if (!holes.empty()) NMC_HIP(ctx, for_chunks(holes, nmc::launch_inv_x<R>));
+  NMC_HIP(ctx, for_chunks(all, nmc::launch_fwd_x<R>, NMC_PASS_X));
+  NMC_HIP(ctx, for_chunks(all, nmc::launch_fwd_y<R>, NMC_PASS_Y));
+  NMC_HIP(ctx, for_chunks(all, nmc::launch_z<R>, NMC_PASS_Z));
+  NMC_HIP(ctx, for_chunks(all, nmc::launch_inv_y<R>, NMC_PASS_IY));
+  if (!holes.empty()) NMC_HIP(ctx, for_chunks(holes, nmc::launch_inv_x<R>, NMC_PASS_IX_HOLE));
   // carry cascade per request: S_n = Prolong(S_{n-1}) + Phi^n_hole, S_0 = Phi^0_hole
   off = 0;
   for (int i = 0; i < count; ++i) {
@@ -395,11 +457,13 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s)
     for (int n = 1; n <= q.L - 2; ++n) {
       const R* shi = (const R*)(base + (n == 1 ? lo.H(0) : lo.Shi(n - 1)));
       const R* slo = (n == 1 || !comp) ? nullptr : (const R*)(base + lo.Slo(n - 1));
+      const double ns3 = std::pow((double)(N / 2 + 2), 3);
+      ProfScope ps(ctx, s, NMC_PASS_CARRY, ns3 * sizeof(R) * (comp ? 6 : 3));
       NMC_HIP(ctx, nmc::launch_carry<R>(shi, slo, (const R*)(base + lo.H(n)), (R*)(base + lo.Shi(n)),
                                         comp ? (R*)(base + lo.Slo(n)) : nullptr, N, comp ? 1 : 0, s));
     }
   }
-  NMC_HIP(ctx, for_chunks(fulls, nmc::launch_inv_x<R>));
+  NMC_HIP(ctx, for_chunks(fulls, nmc::launch_inv_x<R>, NMC_PASS_IX_FULL));
   return NMC_OK;
 }
 
@@ -702,6 +766,44 @@ int nmc_fft_lines(nmc_ctx* ctx, const void* in, void* out, int P, int nlines, in
   else
     NMC_HIP(ctx, nmc::launch_fft_lines<float>(in, out, P, nlines, dir, pp.tw32, s));
   return NMC_OK;
+}
+
+int nmc_profile_enable(nmc_ctx* ctx, int on) {
+  if (!ctx) return NMC_EINVAL;
+  for (auto& r : ctx->prof) {
+    (void)hipEventSynchronize(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  ctx->prof.clear();
+  ctx->profiling = on != 0;
+  return NMC_OK;
+}
+
+int nmc_profile_read(nmc_ctx* ctx, nmc_pass_stat* out) {
+  if (!ctx || !out) return NMC_EINVAL;
+  for (int i = 0; i < NMC_NUM_PASSES; ++i) out[i] = nmc_pass_stat{0, 0.0, 0.0};
+  int rc = NMC_OK;
+  for (auto& r : ctx->prof) {
+    float ms = 0;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess && rc == NMC_OK) rc = hip_fail(ctx, e, "profile events");
+    if (r.pass >= 0 && r.pass < NMC_NUM_PASSES) {
+      out[r.pass].launches++;
+      out[r.pass].total_ms += ms;
+      out[r.pass].bytes += r.bytes;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  ctx->prof.clear();
+  return rc;
+}
+
+const char* nmc_pass_name(int pass) {
+  static const char* names[NMC_NUM_PASSES] = {"restrict", "x", "y", "z", "inv_y", "inv_x_hole", "carry", "inv_x_full"};
+  return (pass >= 0 && pass < NMC_NUM_PASSES) ? names[pass] : "?";
 }
 
 }  // extern "C"

@@ -36,6 +36,13 @@ class Request(ctypes.Structure):
                 ("p", ctypes.c_int), ("flags", ctypes.c_uint)]
 
 
+class PassStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+NUM_PASSES = 8
+
+
 class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
                 ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
@@ -71,6 +78,9 @@ def lib() -> ctypes.CDLL:
         "nmc_green_spectrum": (i, [vp, i, i, vp, vp]),
         "nmc_period": (i, [i]),
         "nmc_fft_lines": (i, [vp, vp, vp, i, i, i, i, vp]),
+        "nmc_profile_enable": (i, [vp, i]),
+        "nmc_profile_read": (i, [vp, ctypes.POINTER(PassStat)]),
+        "nmc_pass_name": (ctypes.c_char_p, [i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -235,6 +245,21 @@ class Context:
         if rc:
             self._err(rc, "nmc_serve_stats_get")
         return {k: getattr(s, k) for k, _ in ServeStats._fields_}
+
+    # -- profiling -------------------------------------------------------------
+    def profile(self, on: bool = True):
+        rc = lib().nmc_profile_enable(self._h, 1 if on else 0)
+        if rc:
+            self._err(rc, "nmc_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{pass name: {launches, total_ms, bytes}} since the last enable/read."""
+        arr = (PassStat * NUM_PASSES)()
+        rc = lib().nmc_profile_read(self._h, arr)
+        if rc:
+            self._err(rc, "nmc_profile_read")
+        return {lib().nmc_pass_name(k).decode(): dict(launches=arr[k].launches, total_ms=arr[k].total_ms,
+                                                       bytes=arr[k].bytes) for k in range(NUM_PASSES)}
 
     # -- diagnostics -------------------------------------------------------------
     def green_spectrum(self, N: int, dtype=torch.float64, stream=None) -> torch.Tensor:
