@@ -63,7 +63,12 @@ enum {
   NMC_NO_RESTRICT = 1u << 0,
   /* FP32 only: plain FP32 cross-level sums instead of the compensated
    * (two-term) carry.  For ablation. */
-  NMC_F32_UNCOMPENSATED = 1u << 2
+  NMC_F32_UNCOMPENSATED = 1u << 2,
+  /* nmc_solve only: always launch the kernels directly.  Default: the second
+   * and later calls with identical arguments (same pointers, shape, h0, G,
+   * precision and flags) replay a captured HIP graph that owns its own
+   * workspace, which removes the per-kernel launch cost. */
+  NMC_NO_GRAPH = 1u << 3
 };
 
 /* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
@@ -142,6 +147,11 @@ int nmc_serve_tick(nmc_ctx* ctx, int* launched);
 /* *done = 1 once the ticket's result is complete on the device (the
  * scheduler is ticked first).  NMC_EINVAL for an unknown ticket. */
 int nmc_serve_poll(nmc_ctx* ctx, uint64_t ticket, int* done);
+
+/* Move up to `cap` tickets that completed since the previous call into
+ * out[0..*n-1] (oldest first); the scheduler is ticked first.  The tickets are
+ * then forgotten by the context (later polls of them return NMC_EINVAL). */
+int nmc_serve_take_completed(nmc_ctx* ctx, uint64_t* out, int cap, int* n);
 
 typedef struct {
   uint64_t submitted, admitted, completed, batches;

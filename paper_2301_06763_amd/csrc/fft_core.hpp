@@ -167,15 +167,38 @@ __device__ __forceinline__ void fft_stages(cplx<R>* v, int t, const LdsView<R>& 
     fft_stages<R, P, E, DIR, NS * RAD, false, false, POUT, REST...>(v, t, lds, tw);
 }
 
-// Per-length plan: points per thread and the radix sequence.
-template <int P> struct Plan;
-template <> struct Plan<8> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8>(); } };
-template <> struct Plan<16> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 2>(); } };
-template <> struct Plan<32> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4>(); } };
-template <> struct Plan<64> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8>(); } };
-template <> struct Plan<128> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8>(); } };
-template <> struct Plan<256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
-template <> struct Plan<512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+// Per-length plan: points per thread E and the radix sequence.  FP64 keeps
+// E = 8 (fewer registers per thread, more resident waves); FP32 uses E = 16
+// where it saves an LDS exchange.
+#ifndef NMC_F64_E16
+#define NMC_F64_E16 0
+#endif
+template <class R, int P> struct Plan;
+template <class R> struct Plan<R, 8> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8>(); } };
+template <class R> struct Plan<R, 16> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 2>(); } };
+template <class R> struct Plan<R, 32> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4>(); } };
+template <class R> struct Plan<R, 64> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8>(); } };
+#ifndef NMC_F32_E8
+#define NMC_F32_E8 1
+#endif
+#if NMC_F32_E8
+template <> struct Plan<float, 128> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4, 4>(); } };
+template <> struct Plan<float, 256> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 4>(); } };
+template <> struct Plan<float, 512> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+#else
+template <> struct Plan<float, 128> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8>(); } };
+template <> struct Plan<float, 256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
+template <> struct Plan<float, 512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+#endif
+#if NMC_F64_E16
+template <> struct Plan<double, 128> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8>(); } };
+template <> struct Plan<double, 256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
+template <> struct Plan<double, 512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+#else
+template <> struct Plan<double, 128> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4, 4>(); } };
+template <> struct Plan<double, 256> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 4>(); } };
+template <> struct Plan<double, 512> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+#endif
 
 template <class R, int P, int DIR, bool PIN, bool POUT>
 struct FftRun {
@@ -185,7 +208,7 @@ struct FftRun {
   const cplx<R>* tw;
   template <int... RS>
   __device__ __forceinline__ void go() const {
-    fft_stages<R, P, Plan<P>::E, DIR, 1, true, PIN, POUT, RS...>(v, t, *lds, tw);
+    fft_stages<R, P, Plan<R, P>::E, DIR, 1, true, PIN, POUT, RS...>(v, t, *lds, tw);
   }
 };
 
@@ -193,7 +216,7 @@ struct FftRun {
 template <class R, int P, int DIR, bool PIN, bool POUT>
 __device__ __forceinline__ void fft_line(cplx<R>* v, int t, const LdsView<R>& lds,
                                          const cplx<R>* __restrict__ tw) {
-  Plan<P>::run(FftRun<R, P, DIR, PIN, POUT>{v, t, &lds, tw});
+  Plan<R, P>::run(FftRun<R, P, DIR, PIN, POUT>{v, t, &lds, tw});
 }
 
 }  // namespace nmc

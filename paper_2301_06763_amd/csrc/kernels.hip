@@ -27,7 +27,7 @@ namespace nmc {
 
 template <class R, int P>
 struct Cfg {
-  static constexpr int E = Plan<P>::E;
+  static constexpr int E = Plan<R, P>::E;
   static constexpr int TL = P / E;
   static constexpr int BYTES_PT = 2 * (int)sizeof(R);
   static constexpr int LDS = 65536;
@@ -39,6 +39,13 @@ struct Cfg {
   static_assert(WS >= 1 && WZ >= 1 && WC >= 1, "tile does not fit");
 };
 
+// Copy the P twiddles exp(-2 pi i j/P) into LDS once per workgroup.  The
+// first read happens in the second FFT stage, after at least one barrier.
+template <class R, int P>
+__device__ __forceinline__ void stage_twiddles(cplx<R>* stw, const cplx<R>* __restrict__ tw) {
+  for (int j = threadIdx.x; j < P; j += blockDim.x) stw[j] = tw[j];
+}
+
 // ---------------------------------------------------------------------------
 // X pass: R2C along x with zero padding (input index >= N is zero).
 template <class R, int P>
@@ -48,6 +55,8 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WC;
   __shared__ R sre[W * P], sim[W * P];
+  __shared__ cplx<R> stw[P];
+  stage_twiddles<R, P>(stw, tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = g.N;
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
@@ -74,7 +83,7 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
     v[q] = T{val, 0};
   }
   LdsView<R> lds{sre, sim, 1, P, w};
-  fft_line<R, P, -1, true, false>(v, t, lds, tb.tw);
+  fft_line<R, P, -1, true, false>(v, t, lds, stw);
   if (active) {
     T* A = static_cast<T*>(F.A) + ((size_t)z * N + y) * (P / 2);
 #pragma unroll
@@ -96,6 +105,8 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WS, NT = (P / 2) / W;
   __shared__ R sre[W * P], sim[W * P];
+  __shared__ cplx<R> stw[P];
+  stage_twiddles<R, P>(stw, tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = g.N;
   const int w = threadIdx.x % W, t = threadIdx.x / W;
@@ -110,7 +121,7 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
     v[q] = yy < N ? A[((size_t)z * N + yy) * (P / 2) + kx] : T{0, 0};
   }
   LdsView<R> lds{sre, sim, W, 1, w};
-  fft_line<R, P, -1, true, false>(v, t, lds, tb.tw);
+  fft_line<R, P, -1, true, false>(v, t, lds, stw);
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int ky = t + TL * q;
@@ -131,6 +142,8 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WZ, NT = (P / 2) / W, H = P / 2 + 1;
   __shared__ R sre[2 * W * P], sim[2 * W * P];
+  __shared__ cplx<R> stw[P];
+  stage_twiddles<R, P>(stw, tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = g.N;
   const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
@@ -144,11 +157,19 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
     const int zz = t + TL * q;
     v[q] = zz < N ? B[((size_t)zz * P + ky) * (P / 2) + kx] : T{0, 0};
   }
+  // spectrum values for this thread's points, fetched with the data
+  const int kyp = ky <= P / 2 ? ky : P - ky;
+  R ga[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int kz = t + TL * q;
+    const int kzp = kz <= P / 2 ? kz : P - kz;
+    ga[q] = tb.green[((size_t)kzp * H + kyp) * H + kx];
+  }
   LdsView<R> lds{sre, sim, 2 * W, 1, w + W * side};
-  fft_line<R, P, -1, true, false>(v, t, lds, tb.tw);
+  fft_line<R, P, -1, true, false>(v, t, lds, stw);
 
   const R sc = (R)F.scale;
-  const int kyp = ky <= P / 2 ? ky : P - ky;
   if (tile == 0) {  // uniform per workgroup
     __syncthreads();
     if (w == 0) {
@@ -165,10 +186,8 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int kz = t + TL * q;
-    const int kzp = kz <= P / 2 ? kz : P - kz;
-    const R* grow = tb.green + ((size_t)kzp * H + kyp) * H;
     if (kx != 0) {
-      const R gv = sc * grow[kx];
+      const R gv = sc * ga[q];
       v[q] = T{v[q].x * gv, v[q].y * gv};
     } else {
       // column 0 holds U + iV (U, V spectra of the real DC and Nyquist planes);
@@ -176,12 +195,13 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
       // product is g0 U + i gN V = (g0+gN)/2 C + (g0-gN)/2 Cm.
       const int nkz = (P - kz) & (P - 1);
       const T cm = T{sre[ps * P + nkz], -sim[ps * P + nkz]};
-      const R g0 = grow[0], gn = grow[P / 2];
+      const int kzp = kz <= P / 2 ? kz : P - kz;
+      const R g0 = ga[q], gn = tb.green[((size_t)kzp * H + kyp) * H + P / 2];
       const R a = sc * (R)0.5 * (g0 + gn), b = sc * (R)0.5 * (g0 - gn);
       v[q] = T{a * v[q].x + b * cm.x, a * v[q].y + b * cm.y};
     }
   }
-  fft_line<R, P, +1, false, true>(v, t, lds, tb.tw);
+  fft_line<R, P, +1, false, true>(v, t, lds, stw);
   const int zlo = F.hole ? N / 4 - 1 : 0, zhi = F.hole ? 3 * N / 4 + 1 : N;
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
@@ -199,6 +219,8 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WS, NT = (P / 2) / W;
   __shared__ R sre[W * P], sim[W * P];
+  __shared__ cplx<R> stw[P];
+  stage_twiddles<R, P>(stw, tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = g.N;
   const int lo = F.hole ? N / 4 - 1 : 0, nr = F.hole ? N / 2 + 2 : N;
@@ -213,7 +235,7 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = B[((size_t)z * P + t + TL * q) * (P / 2) + kx];
   LdsView<R> lds{sre, sim, W, 1, w};
-  fft_line<R, P, +1, false, true>(v, t, lds, tb.tw);
+  fft_line<R, P, +1, false, true>(v, t, lds, stw);
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int yy = t + TL * q;
@@ -264,6 +286,8 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WC;
   __shared__ R sre[W * P], sim[W * P];
+  __shared__ cplx<R> stw[P];
+  stage_twiddles<R, P>(stw, tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = g.N;
   const int lo = F.hole ? N / 4 - 1 : 0, nr = F.hole ? N / 2 + 2 : N;
@@ -287,7 +311,7 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
     v[q] = c;
   }
   LdsView<R> lds{sre, sim, 1, P, w};
-  fft_line<R, P, +1, false, true>(v, t, lds, tb.tw);
+  fft_line<R, P, +1, false, true>(v, t, lds, stw);
   if (!active) return;
   R* out = static_cast<R*>(F.out);
 #pragma unroll
@@ -376,6 +400,8 @@ k_green(int pass, double beta, const double2* tw, const double* __restrict__ src
   using C = Cfg<double, P>;
   constexpr int E = C::E, TL = C::TL, W = C::WC, H = P / 2 + 1;
   __shared__ double sre[W * P], sim[W * P];
+  __shared__ double2 stw[P];
+  stage_twiddles<double, P>(stw, tw);
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
   const int line = blockIdx.x * W + w;
   const bool active = line < H * H;
@@ -399,7 +425,7 @@ k_green(int pass, double beta, const double2* tw, const double* __restrict__ src
     v[q] = double2{val, 0};
   }
   LdsView<double> lds{sre, sim, 1, P, w};
-  fft_line<double, P, -1, false, false>(v, t, lds, tw);
+  fft_line<double, P, -1, false, false>(v, t, lds, stw);
   if (!active) return;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
@@ -427,6 +453,8 @@ k_fft_lines(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out, int nline
   using C = Cfg<R, P>;
   constexpr int E = C::E, TL = C::TL, W = C::WC;
   __shared__ R sre[W * P], sim[W * P];
+  __shared__ cplx<R> stw[P];
+  stage_twiddles<R, P>(stw, tw);
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
   const int line = blockIdx.x * W + w;
   const bool active = line < nlines;
@@ -435,7 +463,7 @@ k_fft_lines(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out, int nline
   for (int q = 0; q < E; ++q)
     v[q] = active ? in[(size_t)line * P + t + TL * q] : cplx<R>{0, 0};
   LdsView<R> lds{sre, sim, 1, P, w};
-  fft_line<R, P, DIR, false, false>(v, t, lds, tw);
+  fft_line<R, P, DIR, false, false>(v, t, lds, stw);
   if (!active) return;
 #pragma unroll
   for (int q = 0; q < E; ++q) out[(size_t)line * P + t + TL * q] = v[q];

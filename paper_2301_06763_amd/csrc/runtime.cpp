@@ -113,6 +113,28 @@ struct Batch {
   size_t bytes;
 };
 
+// A repeated nmc_solve call, identified by every argument.
+struct GraphKey {
+  const void* rho;
+  void* phi;
+  int N, L;
+  double h0, G;
+  int p;
+  unsigned flags;
+  bool operator<(const GraphKey& o) const {
+    return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
+  }
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  Block ws{};
+  hipEvent_t last = nullptr;  // completion of the latest replay
+  uint64_t used = 0;
+};
+
+constexpr size_t kMaxGraphs = 8;
+
 }  // namespace
 
 struct nmc_ctx {
@@ -131,7 +153,13 @@ struct nmc_ctx {
   std::unordered_map<uint64_t, ServeItem> items;
   std::deque<uint64_t> queue;
   std::deque<Batch> inflight;
+  std::deque<uint64_t> completed;
   nmc_serve_stats stats{};
+  // captured solves
+  hipStream_t cap_stream = nullptr;
+  std::map<GraphKey, GraphEntry> graphs;
+  std::map<GraphKey, int> seen;
+  uint64_t clock = 0;
   // per-pass profiling
   bool profiling = false;
   struct ProfRec {
@@ -501,6 +529,64 @@ int solve_many(nmc_ctx* ctx, const Req* reqs, int count, hipStream_t s, Lease* l
   return NMC_OK;
 }
 
+// --- captured (graph) solves ------------------------------------------------------
+
+void drop_graph(nmc_ctx* ctx, std::map<GraphKey, GraphEntry>::iterator it) {
+  GraphEntry& e = it->second;
+  if (e.last) {
+    (void)hipEventSynchronize(e.last);
+    (void)hipEventDestroy(e.last);
+  }
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.ws.ptr) ctx->free_blocks.push_back(e.ws);
+  ctx->graphs.erase(it);
+}
+
+int build_graph(nmc_ctx* ctx, const Req& r, const GraphKey& key, hipStream_t s) {
+  int rc = prepare(ctx, r.N, s);
+  if (rc) return rc;
+  if (!ctx->cap_stream) NMC_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  while (ctx->graphs.size() >= kMaxGraphs) {
+    auto lru = ctx->graphs.begin();
+    for (auto it = ctx->graphs.begin(); it != ctx->graphs.end(); ++it)
+      if (it->second.used < lru->second.used) lru = it;
+    drop_graph(ctx, lru);
+  }
+  GraphEntry e;
+  rc = pool_alloc(ctx, make_layout(r.N, r.L, r.p).total, &e.ws);
+  if (rc) return rc;
+  NMC_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+  rc = r.p == NMC_F64 ? run_group<double>(ctx, &r, 1, (char*)e.ws.ptr, ctx->cap_stream)
+                      : run_group<float>(ctx, &r, 1, (char*)e.ws.ptr, ctx->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &g);
+  if (rc == NMC_OK && ee != hipSuccess) rc = hip_fail(ctx, ee, "hipStreamEndCapture");
+  if (rc == NMC_OK) {
+    ee = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+    if (ee != hipSuccess) rc = hip_fail(ctx, ee, "hipGraphInstantiate");
+  }
+  if (g) (void)hipGraphDestroy(g);
+  if (rc == NMC_OK) {
+    ee = hipEventCreateWithFlags(&e.last, hipEventDisableTiming);
+    if (ee != hipSuccess) rc = hip_fail(ctx, ee, "hipEventCreate");
+  }
+  if (rc) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    ctx->free_blocks.push_back(e.ws);
+    return rc;
+  }
+  ctx->graphs[key] = e;
+  return NMC_OK;
+}
+
+int launch_graph(nmc_ctx* ctx, GraphEntry& e, hipStream_t s) {
+  NMC_HIP(ctx, hipStreamWaitEvent(s, e.last, 0));  // a replay on another stream may still run
+  NMC_HIP(ctx, hipGraphLaunch(e.exec, s));
+  NMC_HIP(ctx, hipEventRecord(e.last, s));
+  e.used = ++ctx->clock;
+  return NMC_OK;
+}
+
 int set_device(nmc_ctx* ctx) {
   NMC_HIP(ctx, hipSetDevice(ctx->device));
   return NMC_OK;
@@ -518,6 +604,7 @@ int serve_tick(nmc_ctx* ctx, int* launched) {
     if (q != hipSuccess) return hip_fail(ctx, q, "serving batch");
     for (uint64_t t : b.tickets) {
       ctx->items[t].state = 2;
+      ctx->completed.push_back(t);
       ctx->stats.completed++;
     }
     for (auto& blk : b.lease.blocks) ctx->free_blocks.push_back(blk);
@@ -618,6 +705,8 @@ void nmc_destroy(nmc_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   reap_leases(ctx, false);
+  while (!ctx->graphs.empty()) drop_graph(ctx, ctx->graphs.begin());
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (auto& b : ctx->inflight)
     for (auto& blk : b.lease.blocks) (void)hipFree(blk.ptr);
   for (auto& l : ctx->leases)
@@ -643,6 +732,28 @@ int nmc_solve(nmc_ctx* ctx, const void* rho, void* phi, int N, int L, double h0,
   if (rc) return rc;
   if ((rc = set_device(ctx))) return rc;
   hipStream_t s = (hipStream_t)hip_stream;
+  if (!ctx->profiling && !(flags & NMC_NO_GRAPH)) {
+    GraphKey key{};
+    std::memset(&key, 0, sizeof(key));
+    key.rho = rho;
+    key.phi = phi;
+    key.N = N;
+    key.L = L;
+    key.h0 = h0;
+    key.G = G;
+    key.p = (int)p;
+    key.flags = flags;
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+      if (ctx->seen.size() > 4096) ctx->seen.clear();
+      if (++ctx->seen[key] >= 2) {
+        rc = build_graph(ctx, r, key, s);
+        if (rc) return rc;
+        it = ctx->graphs.find(key);
+      }
+    }
+    if (it != ctx->graphs.end()) return launch_graph(ctx, it->second, s);
+  }
   Lease lease;
   rc = solve_many(ctx, &r, 1, s, &lease);
   if (rc) {
@@ -711,6 +822,21 @@ int nmc_serve_poll(nmc_ctx* ctx, uint64_t ticket, int* done) {
     if (rc) return rc;
   }
   *done = ctx->items[ticket].state == 2 ? 1 : 0;
+  return NMC_OK;
+}
+
+int nmc_serve_take_completed(nmc_ctx* ctx, uint64_t* out, int cap, int* n) {
+  if (!ctx || !n || cap < 0 || (cap > 0 && !out)) return NMC_EINVAL;
+  int rc = nmc_serve_tick(ctx, nullptr);
+  if (rc) return rc;
+  int k = 0;
+  while (k < cap && !ctx->completed.empty()) {
+    const uint64_t t = ctx->completed.front();
+    ctx->completed.pop_front();
+    out[k++] = t;
+    ctx->items.erase(t);
+  }
+  *n = k;
   return NMC_OK;
 }
 

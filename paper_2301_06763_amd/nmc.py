@@ -13,12 +13,14 @@ from dataclasses import dataclass
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libnmc.so")
+# NMC_LIBRARY may point at another build of the same library (A/B timing).
+LIB_PATH = os.environ.get("NMC_LIBRARY") or os.path.join(HERE, "libnmc.so")
 
 NMC_F64, NMC_F32 = 0, 1
 NMC_OK, NMC_EINVAL, NMC_ENOMEM, NMC_EDEVICE, NMC_EUNSUPPORTED, NMC_EAGAIN = 0, -1, -2, -3, -4, -5
 NMC_NO_RESTRICT = 1 << 0
 NMC_F32_UNCOMPENSATED = 1 << 2
+NMC_NO_GRAPH = 1 << 3
 
 _CODES = {NMC_EINVAL: "EINVAL", NMC_ENOMEM: "ENOMEM", NMC_EDEVICE: "EDEVICE",
           NMC_EUNSUPPORTED: "EUNSUPPORTED", NMC_EAGAIN: "EAGAIN"}
@@ -75,6 +77,7 @@ def lib() -> ctypes.CDLL:
         "nmc_serve_poll": (i, [vp, ctypes.c_uint64, ctypes.POINTER(i)]),
         "nmc_serve_stats_get": (i, [vp, ctypes.POINTER(ServeStats)]),
         "nmc_serve_drain": (i, [vp]),
+        "nmc_serve_take_completed": (i, [vp, ctypes.POINTER(ctypes.c_uint64), i, ctypes.POINTER(i)]),
         "nmc_green_spectrum": (i, [vp, i, i, vp, vp]),
         "nmc_period": (i, [i]),
         "nmc_fft_lines": (i, [vp, vp, vp, i, i, i, i, vp]),
@@ -232,6 +235,18 @@ class Context:
         if d.value:
             self._tickets.pop(tid, None)
         return bool(d.value)
+
+    def take_completed(self, cap: int = 4096) -> list:
+        """Ticket ids completed since the last call (the context forgets them)."""
+        buf = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_int()
+        rc = lib().nmc_serve_take_completed(self._h, buf, cap, ctypes.byref(n))
+        if rc:
+            self._err(rc, "nmc_serve_take_completed")
+        done = [buf[k] for k in range(n.value)]
+        for t in done:
+            self._tickets.pop(t, None)
+        return done
 
     def drain(self):
         rc = lib().nmc_serve_drain(self._h)
