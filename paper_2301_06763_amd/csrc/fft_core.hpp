@@ -74,9 +74,10 @@ __device__ __forceinline__ T c_rot(T a) {
 }
 
 // In-register DFT of length RR (power of two <= 16) by radix-2 decimation in
-// time; inputs with index >= NZ are taken as zero and never read.
+// time; inputs with index >= NZ are taken as zero and never read, and only
+// the outputs below NOUT (RR or RR/2) are formed.
 // DIR = -1: forward exp(-2 pi i jk/RR); DIR = +1: inverse (unnormalised).
-template <int RR, int DIR, int NZ, class T>
+template <int RR, int DIR, int NZ, int NOUT = RR, class T>
 __device__ __forceinline__ void dft(T* u) {
   if constexpr (RR == 1) {
     if constexpr (NZ <= 0) u[0] = T{0, 0};
@@ -98,10 +99,16 @@ __device__ __forceinline__ void dft(T* u) {
     }
     dft<H, DIR, NZE>(e);
     dft<H, DIR, NZO>(o);
-    [&]<int... K>(std::integer_sequence<int, K...>) {
-      ((u[K] = c_add(e[K], c_rot<DIR, K, RR>(o[K])),
-        u[K + H] = c_sub(e[K], c_rot<DIR, K, RR>(o[K]))), ...);
-    }(std::make_integer_sequence<int, H>{});
+    if constexpr (NOUT > H) {
+      [&]<int... K>(std::integer_sequence<int, K...>) {
+        ((u[K] = c_add(e[K], c_rot<DIR, K, RR>(o[K])),
+          u[K + H] = c_sub(e[K], c_rot<DIR, K, RR>(o[K]))), ...);
+      }(std::make_integer_sequence<int, H>{});
+    } else {
+      [&]<int... K>(std::integer_sequence<int, K...>) {
+        ((u[K] = c_add(e[K], c_rot<DIR, K, RR>(o[K]))), ...);
+      }(std::make_integer_sequence<int, H>{});
+    }
   }
 }
 
@@ -152,7 +159,7 @@ __device__ __forceinline__ void fft_stages(cplx<R>* v, int t, const LdsView<R>& 
 #pragma unroll
       for (int i = 1; i < RAD; ++i) u[i] = c_mul_tw<DIR>(u[i], tw[i * k * STEP]);
     }
-    dft<RAD, DIR, (FIRST && PIN) ? RAD / 2 : RAD>(u);
+    dft<RAD, DIR, (FIRST && PIN) ? RAD / 2 : RAD, (LAST && POUT) ? RAD / 2 : RAD>(u);
     if constexpr (LAST) {
 #pragma unroll
       for (int i = 0; i < RAD; ++i)
@@ -181,10 +188,20 @@ template <class R> struct Plan<R, 64> { static constexpr int E = 8; template <cl
 #ifndef NMC_F32_E8
 #define NMC_F32_E8 1
 #endif
+#ifndef NMC_F32_P512_E16
+#define NMC_F32_P512_E16 0
+#endif
+#ifndef NMC_F64_P512_E16
+#define NMC_F64_P512_E16 0
+#endif
 #if NMC_F32_E8
 template <> struct Plan<float, 128> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4, 4>(); } };
 template <> struct Plan<float, 256> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 4>(); } };
+#if NMC_F32_P512_E16
+template <> struct Plan<float, 512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+#else
 template <> struct Plan<float, 512> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+#endif
 #else
 template <> struct Plan<float, 128> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8>(); } };
 template <> struct Plan<float, 256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
@@ -197,7 +214,11 @@ template <> struct Plan<double, 512> { static constexpr int E = 16; template <cl
 #else
 template <> struct Plan<double, 128> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4, 4>(); } };
 template <> struct Plan<double, 256> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 4>(); } };
+#if NMC_F64_P512_E16
+template <> struct Plan<double, 512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+#else
 template <> struct Plan<double, 512> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+#endif
 #endif
 
 template <class R, int P, int DIR, bool PIN, bool POUT>

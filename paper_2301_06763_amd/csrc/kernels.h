@@ -39,7 +39,11 @@ struct PassGeom {
 template <class R>
 struct Tables {
   const typename std::conditional<sizeof(R) == 8, double2, float2>::type* tw;  // exp(-2 pi i j/P), j < P
-  const R* green;  // real spectrum octant [P/2+1]^3, (kz, ky, kx) with kx fastest
+  // Real Green spectrum in the z pass's reading order: gz[kyp][tile][kzp][w]
+  // for kx = tile*W + w < P/2 (W = the z pass's tile width) and gn[kyp][kzp]
+  // for kx = P/2; kyp, kzp in [0, P/2] (the spectrum is even in ky and kz).
+  const R* gz;
+  const R* gn;
 };
 
 // Forward passes and the fused z pass.
@@ -62,6 +66,11 @@ hipError_t launch_carry(const R* s_hi, const R* s_lo, const R* hole, R* o_hi, R*
 hipError_t launch_green(int P, double beta, const double2* tw, double* t1, double* t2, double* out,
                         hipStream_t);
 hipError_t launch_round_f32(const double* in, float* out, size_t n, hipStream_t);
+// Reorder the FP64 octant [kz][ky][kx] into the z pass's layout (gz, gn) for R.
+template <class R>
+hipError_t launch_green_layout(int P, const double* octant, R* gz, R* gn, hipStream_t);
+template <class R>
+size_t green_layout_elems(int P);  // elements of gz (gn has (P/2+1)^2)
 
 // Batched 1-D complex FFT of contiguous lines (diagnostic entry point).
 template <class R>

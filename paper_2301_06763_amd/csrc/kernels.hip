@@ -25,6 +25,15 @@
 
 namespace nmc {
 
+#ifndef NMC_Z_LDS_KB
+#define NMC_Z_LDS_KB 64
+#endif
+#ifndef NMC_MIN_WAVES_F32
+#define NMC_MIN_WAVES_F32 1
+#endif
+#ifndef NMC_MIN_WAVES_F64
+#define NMC_MIN_WAVES_F64 4
+#endif
 template <class R, int P>
 struct Cfg {
   static constexpr int E = Plan<R, P>::E;
@@ -33,9 +42,15 @@ struct Cfg {
   static constexpr int LDS = 65536;
   static constexpr int WMAX = sizeof(R) == 8 ? 16 : 32;
   static constexpr int cmin(int a, int b) { return a < b ? a : b; }
-  static constexpr int WS = cmin(cmin(P / 2, WMAX), LDS / (P * BYTES_PT));      // y passes
-  static constexpr int WZ = cmin(cmin(P / 2, WMAX), LDS / (2 * P * BYTES_PT));  // z pass (2 rows)
-  static constexpr int WC = cmin(cmin(256 / TL, 64), LDS / (P * BYTES_PT));     // x passes
+  static constexpr int WS = cmin(cmin(P / 2, WMAX), LDS / (P * BYTES_PT));  // y passes
+  // z pass: two rows of W columns; W columns make one 128-byte run
+  // and, up to P = 256, the workgroup stays within 512 threads so that two
+  // fit a CU's registers (measured; at P = 512 the wider runs win)
+  static constexpr int WZ0 = cmin(cmin(P / 2, 128 / BYTES_PT), NMC_Z_LDS_KB * 1024 / (2 * P * BYTES_PT));
+  static constexpr int WZ = P >= 512 ? WZ0 : cmin(WZ0, 256 / TL > 0 ? 256 / TL : 1);
+  static constexpr int WC = cmin(cmin(256 / TL, 64), LDS / (P * BYTES_PT));  // x passes
+  // resident waves per SIMD the register allocation must allow
+  static constexpr int MINW = sizeof(R) == 8 ? NMC_MIN_WAVES_F64 : NMC_MIN_WAVES_F32;
   static_assert(WS >= 1 && WZ >= 1 && WC >= 1, "tile does not fit");
 };
 
@@ -48,7 +63,7 @@ __device__ __forceinline__ void stage_twiddles(cplx<R>* stw, const cplx<R>* __re
 
 // ---------------------------------------------------------------------------
 // X pass: R2C along x with zero padding (input index >= N is zero).
-template <class R, int P>
+template <class R, int P, bool FULLN>
 __global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
 k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P>;
@@ -72,7 +87,7 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   for (int q = 0; q < E / 2; ++q) {
     const int n = t + TL * q;
     R val = 0;
-    if (active && n < N) {
+    if (active && (FULLN || n < N)) {
       if (yz_in && n >= lo && n < hi) {
         if (!F.hole) val = rc ? rc[((size_t)(z - lo) * N2 + (y - lo)) * N2 + (n - lo)]
                               : rho[((size_t)z * N + y) * N + n];
@@ -98,8 +113,8 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
 
 // ---------------------------------------------------------------------------
 // Y pass: C2C along y, inputs y >= N zero, all P outputs kept.
-template <class R, int P>
-__global__ void __launch_bounds__((Cfg<R, P>::WS * Cfg<R, P>::TL))
+template <class R, int P, bool FULLN>
+__global__ void __launch_bounds__((Cfg<R, P>::WS * Cfg<R, P>::TL), (Cfg<R, P>::MINW))
 k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P>;
   using T = cplx<R>;
@@ -118,7 +133,7 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int yy = t + TL * q;
-    v[q] = yy < N ? A[((size_t)z * N + yy) * (P / 2) + kx] : T{0, 0};
+    v[q] = (FULLN || yy < N) ? A[((size_t)z * N + yy) * (P / 2) + kx] : T{0, 0};
   }
   LdsView<R> lds{sre, sim, W, 1, w};
   fft_line<R, P, -1, true, false>(v, t, lds, stw);
@@ -135,8 +150,8 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
 // A workgroup owns the rows ky and -ky (mod P) of W adjacent kx columns: the
 // packed DC/Nyquist column needs the value at (-ky, -kz) to separate the two
 // real planes before they are multiplied by different spectra.
-template <class R, int P>
-__global__ void __launch_bounds__((2 * Cfg<R, P>::WZ * Cfg<R, P>::TL))
+template <class R, int P, bool FULLN>
+__global__ void __launch_bounds__((2 * Cfg<R, P>::WZ * Cfg<R, P>::TL), (Cfg<R, P>::MINW))
 k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P>;
   using T = cplx<R>;
@@ -150,27 +165,30 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int tile = blockIdx.x % NT, p = blockIdx.x / NT;
   const int ky = side == 0 ? p : (p == 0 ? P / 2 : P - p);
   const int kx = tile * W + w;
-  T* B = static_cast<T*>(F.B);
+  const int kyp = ky <= P / 2 ? ky : P - ky;
+  T* B = static_cast<T*>(F.B) + (size_t)ky * (P / 2) + kx;  // row z at + z * P * (P/2)
+  constexpr size_t ZS = (size_t)P * (P / 2);
   T v[E];
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int zz = t + TL * q;
-    v[q] = zz < N ? B[((size_t)zz * P + ky) * (P / 2) + kx] : T{0, 0};
+    v[q] = (FULLN || zz < N) ? B[zz * ZS] : T{0, 0};
   }
-  // spectrum values for this thread's points, fetched with the data
-  const int kyp = ky <= P / 2 ? ky : P - ky;
+  // spectrum values of this thread's points, fetched with the data (the
+  // spectrum is even in kz, so kz and P - kz share a value)
+  const R* gcol = tb.gz + (size_t)(kyp * NT + tile) * H * W + w;
   R ga[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int kz = t + TL * q;
-    const int kzp = kz <= P / 2 ? kz : P - kz;
-    ga[q] = tb.green[((size_t)kzp * H + kyp) * H + kx];
+    ga[q] = gcol[(kz <= P / 2 ? kz : P - kz) * W];
   }
   LdsView<R> lds{sre, sim, 2 * W, 1, w + W * side};
   fft_line<R, P, -1, true, false>(v, t, lds, stw);
 
   const R sc = (R)F.scale;
-  if (tile == 0) {  // uniform per workgroup
+  bool plain = true;
+  if (tile == 0) {  // uniform per workgroup: column kx = 0 needs the row -ky
     __syncthreads();
     if (w == 0) {
 #pragma unroll
@@ -181,23 +199,27 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
       }
     }
     __syncthreads();
+    plain = w != 0;
   }
-  const int ps = p == 0 ? side : 1 - side;  // row holding -ky
+  if (plain) {
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int kz = t + TL * q;
-    if (kx != 0) {
+    for (int q = 0; q < E; ++q) {
       const R gv = sc * ga[q];
       v[q] = T{v[q].x * gv, v[q].y * gv};
-    } else {
-      // column 0 holds U + iV (U, V spectra of the real DC and Nyquist planes);
-      // with Cm = conj(value at -k): U = (C + Cm)/2, V = (C - Cm)/(2i), and the
-      // product is g0 U + i gN V = (g0+gN)/2 C + (g0-gN)/2 Cm.
+    }
+  } else {
+    // column 0 holds U + iV (U, V: spectra of the real DC and Nyquist planes);
+    // with Cm = conj(value at -k): U = (C + Cm)/2, V = (C - Cm)/(2i), and the
+    // product is g0 U + i gN V = (g0+gN)/2 C + (g0-gN)/2 Cm.
+    const int ps = p == 0 ? side : 1 - side;  // row holding -ky
+    const R* gn = tb.gn + (size_t)kyp * H;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int kz = t + TL * q;
       const int nkz = (P - kz) & (P - 1);
       const T cm = T{sre[ps * P + nkz], -sim[ps * P + nkz]};
-      const int kzp = kz <= P / 2 ? kz : P - kz;
-      const R g0 = ga[q], gn = tb.green[((size_t)kzp * H + kyp) * H + P / 2];
-      const R a = sc * (R)0.5 * (g0 + gn), b = sc * (R)0.5 * (g0 - gn);
+      const R g0 = ga[q], gnv = gn[kz <= P / 2 ? kz : P - kz];
+      const R a = sc * (R)0.5 * (g0 + gnv), b = sc * (R)0.5 * (g0 - gnv);
       v[q] = T{a * v[q].x + b * cm.x, a * v[q].y + b * cm.y};
     }
   }
@@ -206,14 +228,14 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int zz = t + TL * q;
-    if (zz >= zlo && zz < zhi) B[((size_t)zz * P + ky) * (P / 2) + kx] = v[q];
+    if ((FULLN && !F.hole) || (zz >= zlo && zz < zhi)) B[zz * ZS] = v[q];
   }
 }
 
 // ---------------------------------------------------------------------------
 // I2 pass: inverse along y over the kept z rows; keep the output y rows.
 template <class R, int P>
-__global__ void __launch_bounds__((Cfg<R, P>::WS * Cfg<R, P>::TL))
+__global__ void __launch_bounds__((Cfg<R, P>::WS * Cfg<R, P>::TL), (Cfg<R, P>::MINW))
 k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P>;
   using T = cplx<R>;
@@ -445,6 +467,22 @@ __global__ void k_round_f32(const double* __restrict__ in, float* __restrict__ o
   if (i < n) out[i] = (float)in[i];
 }
 
+// Reorder the octant [kz][ky][kx] into gz[kyp][tile][kzp][w] and gn[kyp][kzp].
+template <class R, int P>
+__global__ void k_green_layout(const double* __restrict__ oct, R* __restrict__ gz, R* __restrict__ gn) {
+  constexpr int H = P / 2 + 1, W = Cfg<R, P>::WZ, NT = (P / 2) / W;
+  const size_t n = (size_t)H * NT * H * W;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int w = i % W, kzp = (i / W) % H, tile = (i / ((size_t)W * H)) % NT, kyp = i / ((size_t)W * H * NT);
+    gz[i] = (R)oct[((size_t)kzp * H + kyp) * H + tile * W + w];
+  }
+  if (i < (size_t)H * H) {
+    const int kzp = i % H, kyp = i / H;
+    gn[i] = (R)oct[((size_t)kzp * H + kyp) * H + P / 2];
+  }
+}
+
 // Diagnostic: batched unpruned 1-D FFT of contiguous lines.
 template <class R, int P, int DIR>
 __global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
@@ -493,7 +531,10 @@ hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP>;
     dim3 grid((g.N * g.N + C::WC - 1) / C::WC, g.nf);
-    hipLaunchKernelGGL((k_fwd_x<R, PP>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+    if (g.N == PP / 2)
+      hipLaunchKernelGGL((k_fwd_x<R, PP, true>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+    else
+      hipLaunchKernelGGL((k_fwd_x<R, PP, false>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
   });
 }
 
@@ -503,7 +544,10 @@ hipError_t launch_fwd_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP>;
     dim3 grid(((PP / 2) / C::WS) * g.N, g.nf);
-    hipLaunchKernelGGL((k_fwd_y<R, PP>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+    if (g.N == PP / 2)
+      hipLaunchKernelGGL((k_fwd_y<R, PP, true>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+    else
+      hipLaunchKernelGGL((k_fwd_y<R, PP, false>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
   });
 }
 
@@ -513,7 +557,10 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP>;
     dim3 grid(((PP / 2) / C::WZ) * (PP / 2), g.nf);
-    hipLaunchKernelGGL((k_z<R, PP>), grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
+    if (g.N == PP / 2)
+      hipLaunchKernelGGL((k_z<R, PP, true>), grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
+    else
+      hipLaunchKernelGGL((k_z<R, PP, false>), grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
   });
 }
 
@@ -567,6 +614,26 @@ hipError_t launch_green(int P, double beta, const double2* tw, double* t1, doubl
   });
 }
 
+template <class R>
+size_t green_layout_elems(int P) {
+  size_t n = 0;
+  (void)dispatch_p(P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    n = (size_t)(PP / 2 + 1) * (PP / 2 + 1) * (PP / 2);
+  });
+  return n;
+}
+
+template <class R>
+hipError_t launch_green_layout(int P, const double* octant, R* gz, R* gn, hipStream_t s) {
+  return dispatch_p(P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    const size_t n = (size_t)(PP / 2 + 1) * (PP / 2 + 1) * (PP / 2);
+    hipLaunchKernelGGL((k_green_layout<R, PP>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, octant,
+                       gz, gn);
+  });
+}
+
 hipError_t launch_round_f32(const double* in, float* out, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_round_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
   return hipGetLastError();
@@ -597,7 +664,9 @@ hipError_t launch_fft_lines(const void* in, void* out, int P, int nlines, int di
   template hipError_t launch_inv_x<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
   template hipError_t launch_restrict<R>(const R*, const R*, R*, int, hipStream_t);               \
   template hipError_t launch_carry<R>(const R*, const R*, const R*, R*, R*, int, int, hipStream_t); \
-  template hipError_t launch_fft_lines<R>(const void*, void*, int, int, int, const void*, hipStream_t);
+  template hipError_t launch_fft_lines<R>(const void*, void*, int, int, int, const void*, hipStream_t); \
+  template hipError_t launch_green_layout<R>(int, const double*, R*, R*, hipStream_t);                 \
+  template size_t green_layout_elems<R>(int);
 
 NMC_INSTANTIATE(double)
 NMC_INSTANTIATE(float)

@@ -97,8 +97,10 @@ struct Lease {
 struct PerP {
   void* tw64 = nullptr;  // double2[P]
   void* tw32 = nullptr;  // float2[P]
-  double* g64 = nullptr;
+  double* g64 = nullptr;  // spectrum octant [kz][ky][kx]
   float* g32 = nullptr;
+  double *gz64 = nullptr, *gn64 = nullptr;  // z-pass layouts
+  float *gz32 = nullptr, *gn32 = nullptr;
 };
 
 struct ServeItem {
@@ -228,16 +230,25 @@ int ensure_green(nmc_ctx* ctx, int P, hipStream_t s) {
   NMC_HIP(ctx, hipMalloc(&pp.g32, n * sizeof(float)));
   NMC_HIP(ctx, hipMalloc(&t1, n * sizeof(double)));
   NMC_HIP(ctx, hipMalloc(&t2, n * sizeof(double)));
+  const size_t nz64 = nmc::green_layout_elems<double>(P), nz32 = nmc::green_layout_elems<float>(P);
+  NMC_HIP(ctx, hipMalloc(&pp.gz64, nz64 * sizeof(double)));
+  NMC_HIP(ctx, hipMalloc(&pp.gn64, H * H * sizeof(double)));
+  NMC_HIP(ctx, hipMalloc(&pp.gz32, nz32 * sizeof(float)));
+  NMC_HIP(ctx, hipMalloc(&pp.gn32, H * H * sizeof(float)));
   hipError_t e = nmc::launch_green(P, self_cell_integral(), (const double2*)pp.tw64, t1, t2, pp.g64, s);
   if (e == hipSuccess) e = nmc::launch_round_f32(pp.g64, pp.g32, n, s);
+  if (e == hipSuccess) e = nmc::launch_green_layout<double>(P, pp.g64, pp.gz64, pp.gn64, s);
+  if (e == hipSuccess) e = nmc::launch_green_layout<float>(P, pp.g64, pp.gz32, pp.gn32, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(t1);
   (void)hipFree(t2);
   if (e != hipSuccess) {
-    (void)hipFree(pp.g64);
-    (void)hipFree(pp.g32);
+    for (void* q : {(void*)pp.g64, (void*)pp.g32, (void*)pp.gz64, (void*)pp.gn64, (void*)pp.gz32, (void*)pp.gn32})
+      (void)hipFree(q);
     pp.g64 = nullptr;
     pp.g32 = nullptr;
+    pp.gz64 = pp.gn64 = nullptr;
+    pp.gz32 = pp.gn32 = nullptr;
     return hip_fail(ctx, e, "green spectrum build");
   }
   return NMC_OK;
@@ -386,10 +397,12 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s)
   nmc::Tables<R> tb;
   if constexpr (sizeof(R) == 8) {
     tb.tw = (const double2*)pp.tw64;
-    tb.green = pp.g64;
+    tb.gz = pp.gz64;
+    tb.gn = pp.gn64;
   } else {
     tb.tw = (const float2*)pp.tw32;
-    tb.green = pp.g32;
+    tb.gz = pp.gz32;
+    tb.gn = pp.gn32;
   }
   const size_t lvl = (size_t)N * N * N;
   std::vector<FieldDesc> fulls, holes;
@@ -624,37 +637,68 @@ int serve_tick(nmc_ctx* ctx, int* launched) {
     admitted.push_back(t);
     ctx->queue.pop_front();
   }
-  // 3. one batch per (N, precision) group, each on the next serving stream
+  // 3. batches per (N, precision) group, each on the next serving stream.  A
+  // batch holds at most a quarter of the budget so that several batches are
+  // in flight and overlap on the device.
+  const size_t max_batch_bytes = ctx->budget ? std::max<size_t>(ctx->budget / 4, 1) : SIZE_MAX;
   std::map<std::pair<int, int>, std::vector<uint64_t>> groups;
   for (uint64_t t : admitted) groups[{ctx->items[t].r.N, (int)ctx->items[t].r.p}].push_back(t);
+  std::vector<std::vector<uint64_t>> batches;
   for (auto& kv : groups) {
-    auto& ts = kv.second;
-    for (size_t a = 0; a < ts.size(); a += kMaxBatchRequests) {
-      const size_t n = std::min<size_t>(kMaxBatchRequests, ts.size() - a);
-      Batch b;
-      std::vector<Req> rs;
-      b.bytes = 0;
-      for (size_t k = 0; k < n; ++k) {
-        const uint64_t t = ts[a + k];
-        rs.push_back(ctx->items[t].r);
-        b.tickets.push_back(t);
-        b.bytes += ctx->items[t].bytes;
-        ctx->items[t].state = 1;
+    std::vector<uint64_t> cur;
+    size_t cur_bytes = 0;
+    for (uint64_t t : kv.second) {
+      const size_t b = ctx->items[t].bytes;
+      if (!cur.empty() && ((int)cur.size() >= kMaxBatchRequests || cur_bytes + b > max_batch_bytes)) {
+        batches.push_back(std::move(cur));
+        cur.clear();
+        cur_bytes = 0;
       }
-      hipStream_t s = ctx->streams[ctx->next_stream];
-      ctx->next_stream = (ctx->next_stream + 1) % kServeStreams;
-      int rc = launch_group(ctx, rs.data(), (int)n, s, &b.lease);
-      if (rc) return rc;
-      NMC_HIP(ctx, hipEventCreateWithFlags(&b.lease.ev, hipEventDisableTiming));
-      NMC_HIP(ctx, hipEventRecord(b.lease.ev, s));
-      ctx->stats.admitted += n;
-      ctx->stats.inflight += n;
-      ctx->stats.batches++;
-      ctx->stats.inflight_bytes += b.bytes;
-      ctx->stats.peak_inflight_bytes = std::max(ctx->stats.peak_inflight_bytes, ctx->stats.inflight_bytes);
-      n_launched += (int)n;
-      ctx->inflight.push_back(std::move(b));
+      cur.push_back(t);
+      cur_bytes += b;
     }
+    if (!cur.empty()) batches.push_back(std::move(cur));
+  }
+  std::vector<uint64_t> requeue;
+  for (auto& ts : batches) {
+    if (!requeue.empty()) {  // an earlier batch did not fit: keep arrival order
+      requeue.insert(requeue.end(), ts.begin(), ts.end());
+      continue;
+    }
+    Batch b;
+    std::vector<Req> rs;
+    for (uint64_t t : ts) rs.push_back(ctx->items[t].r);
+    hipStream_t s = ctx->streams[ctx->next_stream];
+    int rc = launch_group(ctx, rs.data(), (int)rs.size(), s, &b.lease);
+    if (rc == NMC_ENOMEM) {
+      // the pool could not place it next to the work in flight (block sizes
+      // differ from footprints): nothing was enqueued, retry on a later tick
+      for (auto& blk : b.lease.blocks) ctx->free_blocks.push_back(blk);
+      requeue.insert(requeue.end(), ts.begin(), ts.end());
+      continue;
+    }
+    if (rc) return rc;
+    ctx->next_stream = (ctx->next_stream + 1) % kServeStreams;
+    NMC_HIP(ctx, hipEventCreateWithFlags(&b.lease.ev, hipEventDisableTiming));
+    NMC_HIP(ctx, hipEventRecord(b.lease.ev, s));
+    b.tickets = ts;
+    b.bytes = 0;
+    for (auto& blk : b.lease.blocks) b.bytes += blk.bytes;  // what the device really holds
+    for (uint64_t t : ts) ctx->items[t].state = 1;
+    ctx->stats.admitted += ts.size();
+    ctx->stats.inflight += ts.size();
+    ctx->stats.batches++;
+    ctx->stats.inflight_bytes += b.bytes;
+    ctx->stats.peak_inflight_bytes = std::max(ctx->stats.peak_inflight_bytes, ctx->stats.inflight_bytes);
+    n_launched += (int)ts.size();
+    ctx->inflight.push_back(std::move(b));
+  }
+  if (!requeue.empty()) {
+    if (ctx->inflight.empty())
+      return fail(ctx, NMC_ENOMEM, "serving: a batch does not fit the budget with nothing in flight");
+    // back to the front of the queue, in arrival order
+    std::sort(requeue.begin(), requeue.end());
+    for (auto it = requeue.rbegin(); it != requeue.rend(); ++it) ctx->queue.push_front(*it);
   }
   ctx->stats.queued = ctx->queue.size();
   if (launched) *launched = n_launched;
@@ -717,6 +761,10 @@ void nmc_destroy(nmc_ctx* ctx) {
     (void)hipFree(kv.second.tw32);
     (void)hipFree(kv.second.g64);
     (void)hipFree(kv.second.g32);
+    (void)hipFree(kv.second.gz64);
+    (void)hipFree(kv.second.gn64);
+    (void)hipFree(kv.second.gz32);
+    (void)hipFree(kv.second.gn32);
   }
   for (auto& s : ctx->streams) (void)hipStreamDestroy(s);
   delete ctx;
