@@ -30,7 +30,9 @@ WORKLOADS = {
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed solves (default: about 50 ms of work per precision for the workload)")
+    ap.add_argument("--flags", type=int, default=0, help="nmc flag bits passed to every solve")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ellipsoid64", choices=sorted(WORKLOADS) + ["serving", "copyref"])
     ap.add_argument("--requests", type=int, default=1000, help="serving: number of requests")
@@ -41,16 +43,23 @@ def parse():
                     help="wall-clock budget of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.steps is None:
+        a.steps = {"plummer32": 500, "ellipsoid64": 400, "binary128": 50, "clumps256": 10}.get(a.workload, 20)
+        if a.workload in ("serving",):
+            a.steps = a.requests
+        if a.workload == "copyref":
+            a.steps = 10
+    return a
 
 
-def time_solves(ctx, rho, h0, steps, warmup, torch):
+def time_solves(ctx, rho, h0, steps, warmup, torch, flags=0):
     """Timed region: `steps` solves back to back (repeated calls replay the
     captured graph).  Then the same `steps` solves again with per-pass HIP
     events recorded by the library on its launch stream (direct launches)."""
     out = torch.empty_like(rho)
     for _ in range(warmup):
-        ctx.solve(rho, h0, out=out)
+        ctx.solve(rho, h0, flags=flags, out=out)
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -58,7 +67,7 @@ def time_solves(ctx, rho, h0, steps, warmup, torch):
     t0 = time.perf_counter()
     for k in range(steps):
         starts[k].record()
-        ctx.solve(rho, h0, out=out)
+        ctx.solve(rho, h0, flags=flags, out=out)
         ends[k].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -66,7 +75,7 @@ def time_solves(ctx, rho, h0, steps, warmup, torch):
     ctx.profile(True)
     torch.cuda.synchronize()
     for k in range(steps):
-        ctx.solve(rho, h0, out=out)
+        ctx.solve(rho, h0, flags=flags, out=out)
     torch.cuda.synchronize()
     prof = ctx.profile_read()
     ctx.profile(False)
@@ -252,7 +261,7 @@ def main():
     outs = {}
     for tag, dt in (("f32", torch.float32), ("f64", torch.float64)):
         rho = w.rho.to(dt).contiguous()
-        out, el, prof, lat = time_solves(ctx, rho, w.h0, args.steps, args.warmup, torch)
+        out, el, prof, lat = time_solves(ctx, rho, w.h0, args.steps, args.warmup, torch, args.flags)
         outs[tag] = out.double()
         res[tag] = {"solves_per_s": args.steps / el, "ms_per_step": el / args.steps * 1e3,
                     "passes": pass_table(prof), "lat": lat, "prof": prof}

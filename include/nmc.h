@@ -68,7 +68,11 @@ enum {
    * and later calls with identical arguments (same pointers, shape, h0, G,
    * precision and flags) replay a captured HIP graph that owns its own
    * workspace, which removes the per-kernel launch cost. */
-  NMC_NO_GRAPH = 1u << 3
+  NMC_NO_GRAPH = 1u << 3,
+  /* Enqueue every grid on hip_stream only.  Default: the grids that need no
+   * restriction run on a second, library-owned stream forked from and joined
+   * back into hip_stream, overlapping the restriction cascade. */
+  NMC_ONE_STREAM = 1u << 4
 };
 
 /* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
@@ -101,8 +105,11 @@ int nmc_footprint_bytes(int N, int L, nmc_precision p, size_t* bytes);
  *   refine  refinement factor between levels; must be 2
  *   G     gravitational constant (finite)
  *   p     element type of rho and phi and arithmetic of the FFT path
- *   flags NMC_NO_RESTRICT, NMC_F32_UNCOMPENSATED
- *   hip_stream  hipStream_t to enqueue on
+ *   flags NMC_NO_RESTRICT, NMC_F32_UNCOMPENSATED, NMC_NO_GRAPH
+ *   hip_stream  hipStream_t to enqueue on.  The hole grids and the carry
+ *         cascade run on a second, library-owned stream that is forked from
+ *         and joined back into hip_stream, so completion is ordered on
+ *         hip_stream alone.
  * Errors: NMC_EINVAL, NMC_EUNSUPPORTED, NMC_ENOMEM, NMC_EDEVICE. */
 int nmc_solve(nmc_ctx* ctx, const void* rho, void* phi, int N, int L, double h0, int refine,
               double G, nmc_precision p, unsigned flags, void* hip_stream);

@@ -21,6 +21,7 @@ NMC_OK, NMC_EINVAL, NMC_ENOMEM, NMC_EDEVICE, NMC_EUNSUPPORTED, NMC_EAGAIN = 0, -
 NMC_NO_RESTRICT = 1 << 0
 NMC_F32_UNCOMPENSATED = 1 << 2
 NMC_NO_GRAPH = 1 << 3
+NMC_ONE_STREAM = 1 << 4
 
 _CODES = {NMC_EINVAL: "EINVAL", NMC_ENOMEM: "ENOMEM", NMC_EDEVICE: "EDEVICE",
           NMC_EUNSUPPORTED: "EUNSUPPORTED", NMC_EAGAIN: "EAGAIN"}
