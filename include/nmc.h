@@ -203,7 +203,9 @@ int nmc_fft_lines(nmc_ctx* ctx, const void* in, void* out, int P, int nlines, in
  * on the recorded events. */
 enum {
   NMC_PASS_RESTRICT = 0, NMC_PASS_X = 1, NMC_PASS_Y = 2, NMC_PASS_Z = 3, NMC_PASS_IY = 4,
-  NMC_PASS_IX_HOLE = 5, NMC_PASS_CARRY = 6, NMC_PASS_IX_FULL = 7, NMC_NUM_PASSES = 8
+  NMC_PASS_IX_SECOND = 5, /* last pass of the hole grids or child-region boxes */
+  NMC_PASS_CARRY = 6,     /* carry cascade (hole-grid formulation only) */
+  NMC_PASS_IX_FULL = 7, NMC_NUM_PASSES = 8
 };
 
 typedef struct {

@@ -9,19 +9,32 @@
 
 namespace nmc {
 
-// One grid to convolve: a full level (Omega^m) or a level with its cavity
-// zeroed (Omega^m_hole), Sect. 4 of the paper.
+// One grid to convolve (Sect. 3 of the paper) on the doubled period P.  Its
+// input occupies cells [0, nin) per axis and its output rows [olo, olo + nout):
+//  * kind 0, a full level Omega^m: nin = nout = N, olo = 0; density rho with
+//    the child region replaced by its restriction rc when rc is set;
+//  * kind 1, the child region of a level alone, embedded with a one-cell
+//    margin in a box of nin = nout = N/2 + 2 cells per axis (the stencil box
+//    [N/4 - 1, 3N/4] of the level): density rc (or rho's child region when
+//    rc is null), zero in the margin.  Its potential C on the box gives the
+//    hole potential of Sect. 4 by linearity: Phi_hole = Phi - C;
+//  * kind 2, the level with its child region zeroed (Omega^m_hole of Sect. 4,
+//    Fig. 5): nin = N, output only on the stencil box (olo = N/4 - 1,
+//    nout = N/2 + 2).
 struct FieldDesc {
   const void* rho;   // level density [N][N][N] (x fastest), caller-owned
   const void* rc;    // restricted density of the child region [(N/2)^3], or null
-  void* A;           // workspace [N][N][P/2] complex: x-pass output, y-inverse output
-  void* B;           // workspace [N][P][P/2] complex: y-pass output, z-pass in place
-  void* out;         // full: potential [N][N][N]; hole: stencil box [(N/2+2)^3]
-  const void* S;     // full, level >= 1: carried coarse potential (hi) on the stencil box
+  void* A;           // workspace [nin][nin][P/2] complex: x-pass output, y-inverse output
+  void* B;           // workspace [nin][P][P/2] complex: y-pass output, z-pass in place
+  void* out;         // kind 0: potential [N][N][N]; kinds 1, 2: box [(N/2+2)^3]
+  const void* S;     // kind 0, level >= 1: carried coarse potential S_{l-1} on the box (hi)
   const void* Slo;   // its compensation term (FP32 path) or null
+  void* Sout;        // kind 0 with kind-1 boxes, level < L-1: S_l = Phi(Omega^l) - C_l (hi)
+  void* Slo_out;     // its compensation term (FP32 path) or null
+  const void* C;     // with Sout: C_l on the box
   double scale;      // -G h^2 / P^3 (mass = rho h^3, kernel 1/(h |d|), 1/P^3 of the inverse)
-  int hole;          // 1 for Omega_hole
-  int has_carry;     // full field of a level >= 1
+  int kind;          // 0 full level, 1 child-region box, 2 level with its child region zeroed
+  int comp;          // FP32: compensated (two-term) carry
 };
 
 constexpr int kMaxFieldsPerLaunch = 24;
@@ -30,10 +43,10 @@ struct FieldTable {
 };
 
 struct PassGeom {
-  int N;     // cells per axis
+  int N;     // cells per axis of the level
   int P;     // padded period (power of two >= 2N)
-  int nf;    // fields in this launch
-  int flags;
+  int n;     // largest nin (x, y passes) or nout (inverse passes) of the launch's grids
+  int nf;    // grids in this launch
 };
 
 template <class R>

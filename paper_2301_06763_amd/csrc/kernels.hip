@@ -61,8 +61,18 @@ __device__ __forceinline__ void stage_twiddles(cplx<R>* stw, const cplx<R>* __re
   for (int j = threadIdx.x; j < P; j += blockDim.x) stw[j] = tw[j];
 }
 
+// Input extent nin and output rows [olo, olo + nout) of a grid (FieldDesc).
+struct GridGeo {
+  int nin, olo, nout;
+};
+__device__ __forceinline__ GridGeo grid_geo(int kind, int N) {
+  if (kind == 0) return GridGeo{N, 0, N};
+  if (kind == 1) return GridGeo{N / 2 + 2, 0, N / 2 + 2};
+  return GridGeo{N, N / 4 - 1, N / 2 + 2};
+}
+
 // ---------------------------------------------------------------------------
-// X pass: R2C along x with zero padding (input index >= N is zero).
+// X pass: R2C along x with zero padding (input index >= nin is zero).
 template <class R, int P, bool FULLN>
 __global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
 k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
@@ -73,34 +83,55 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ cplx<R> stw[P];
   stage_twiddles<R, P>(stw, tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
-  const int N = g.N;
+  const int N = g.N, n = grid_geo(F.kind, N).nin;
+  if ((int)blockIdx.x * W >= n * n) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
   const int line = blockIdx.x * W + w;
-  const bool active = line < N * N;
-  const int z = active ? line / N : 0, y = active ? line % N : 0;
+  const bool active = line < n * n;
+  const int z = active ? line / n : 0, y = active ? line % n : 0;
   const R* rho = static_cast<const R*>(F.rho);
   const R* rc = static_cast<const R*>(F.rc);
-  const int lo = N / 4, hi = 3 * N / 4, N2 = N / 2;
-  const bool yz_in = z >= lo && z < hi && y >= lo && y < hi;
+  const int N2 = N / 2;
   T v[E];
+  if (F.kind != 1) {
+    // full level (child region from rc when set) or level with the child
+    // region zeroed (kind 2)
+    const int lo = N / 4, hi = 3 * N / 4;
+    const bool yz_in = z >= lo && z < hi && y >= lo && y < hi;
+    const bool use_rc = F.kind == 0 && rc && yz_in;
+    const bool zero_c = F.kind == 2 && yz_in;
+    const size_t row = ((size_t)z * N + y) * N;
+    const size_t rrow = use_rc ? ((size_t)(z - lo) * N2 + (y - lo)) * N2 : 0;
 #pragma unroll
-  for (int q = 0; q < E / 2; ++q) {
-    const int n = t + TL * q;
-    R val = 0;
-    if (active && (FULLN || n < N)) {
-      if (yz_in && n >= lo && n < hi) {
-        if (!F.hole) val = rc ? rc[((size_t)(z - lo) * N2 + (y - lo)) * N2 + (n - lo)]
-                              : rho[((size_t)z * N + y) * N + n];
-      } else {
-        val = rho[((size_t)z * N + y) * N + n];
+    for (int q = 0; q < E / 2; ++q) {
+      const int x = t + TL * q;
+      R val = 0;
+      if (active && (FULLN || x < N)) {
+        const bool cen = x >= lo && x < hi;
+        if (!(zero_c && cen)) val = (use_rc && cen) ? rc[rrow + (x - lo)] : rho[row + x];
       }
+      v[q] = T{val, 0};
     }
-    v[q] = T{val, 0};
+  } else {
+    // box cell (x, y, z) is level cell (x, y, z) + N/4 - 1; the child region
+    // is box cells [1, N/2 + 1) per axis
+    const bool yz_in = active && z >= 1 && z <= N2 && y >= 1 && y <= N2;
+    const int off = N / 4 - 1;
+    const size_t row = !yz_in ? 0
+                       : rc ? ((size_t)(z - 1) * N2 + (y - 1)) * N2
+                            : ((size_t)(z + off) * N + (y + off)) * N + off + 1;
+    const R* src = rc ? rc : rho;
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) {
+      const int x = t + TL * q;
+      const R val = (yz_in && x >= 1 && x <= N2) ? src[row + (x - 1)] : (R)0;
+      v[q] = T{val, 0};
+    }
   }
   LdsView<R> lds{sre, sim, 1, P, w};
   fft_line<R, P, -1, true, false>(v, t, lds, stw);
   if (active) {
-    T* A = static_cast<T*>(F.A) + ((size_t)z * N + y) * (P / 2);
+    T* A = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int k = t + TL * q;
@@ -112,7 +143,7 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
 }
 
 // ---------------------------------------------------------------------------
-// Y pass: C2C along y, inputs y >= N zero, all P outputs kept.
+// Y pass: C2C along y, inputs y >= n zero, all P outputs kept.
 template <class R, int P, bool FULLN>
 __global__ void __launch_bounds__((Cfg<R, P>::WS * Cfg<R, P>::TL), (Cfg<R, P>::MINW))
 k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
@@ -123,30 +154,29 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ cplx<R> stw[P];
   stage_twiddles<R, P>(stw, tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
-  const int N = g.N;
-  const int w = threadIdx.x % W, t = threadIdx.x / W;
+  const bool full = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks
+  const int n = grid_geo(F.kind, g.N).nin;
   const int tile = blockIdx.x % NT, z = blockIdx.x / NT;
+  if (z >= n) return;  // uniform: a smaller grid of a mixed launch
+  const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int kx = tile * W + w;
-  const T* A = static_cast<const T*>(F.A);
-  T* B = static_cast<T*>(F.B);
+  const T* A = static_cast<const T*>(F.A) + (size_t)z * n * (P / 2) + kx;
+  T* B = static_cast<T*>(F.B) + (size_t)z * P * (P / 2) + kx;
   T v[E];
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int yy = t + TL * q;
-    v[q] = (FULLN || yy < N) ? A[((size_t)z * N + yy) * (P / 2) + kx] : T{0, 0};
+    v[q] = (full || yy < n) ? A[(size_t)yy * (P / 2)] : T{0, 0};
   }
   LdsView<R> lds{sre, sim, W, 1, w};
   fft_line<R, P, -1, true, false>(v, t, lds, stw);
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int ky = t + TL * q;
-    B[((size_t)z * P + ky) * (P / 2) + kx] = v[q];
-  }
+  for (int q = 0; q < E; ++q) B[(size_t)(t + TL * q) * (P / 2)] = v[q];
 }
 
 // ---------------------------------------------------------------------------
-// Z pass: forward along z (inputs z >= N zero), multiply by the real Green
-// spectrum times the level scale, inverse along z, keep the output rows.
+// Z pass: forward along z (inputs z >= n zero), multiply by the real Green
+// spectrum times the level scale, inverse along z, keep rows z < n.
 // A workgroup owns the rows ky and -ky (mod P) of W adjacent kx columns: the
 // packed DC/Nyquist column needs the value at (-ky, -kz) to separate the two
 // real planes before they are multiplied by different spectra.
@@ -160,7 +190,10 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ cplx<R> stw[P];
   stage_twiddles<R, P>(stw, tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
-  const int N = g.N;
+  const bool full_in = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks on loads
+  const bool full = FULLN && F.kind == 0;     // nout = N = P/2 as well
+  const GridGeo gg = grid_geo(F.kind, g.N);
+  const int n = gg.nin;
   const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
   const int tile = blockIdx.x % NT, p = blockIdx.x / NT;
   const int ky = side == 0 ? p : (p == 0 ? P / 2 : P - p);
@@ -172,7 +205,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int zz = t + TL * q;
-    v[q] = (FULLN || zz < N) ? B[zz * ZS] : T{0, 0};
+    v[q] = (full_in || zz < n) ? B[zz * ZS] : T{0, 0};
   }
   // spectrum values of this thread's points, fetched with the data (the
   // spectrum is even in kz, so kz and P - kz share a value)
@@ -224,17 +257,16 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
     }
   }
   fft_line<R, P, +1, false, true>(v, t, lds, stw);
-  const int zlo = F.hole ? N / 4 - 1 : 0, zhi = F.hole ? 3 * N / 4 + 1 : N;
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int zz = t + TL * q;
-    if ((FULLN && !F.hole) || (zz >= zlo && zz < zhi)) B[zz * ZS] = v[q];
+    if (full || (zz >= gg.olo && zz < gg.olo + gg.nout)) B[zz * ZS] = v[q];
   }
 }
 
 // ---------------------------------------------------------------------------
-// I2 pass: inverse along y over the kept z rows; keep the output y rows.
-template <class R, int P>
+// I2 pass: inverse along y over rows z < n; keep rows y < n.
+template <class R, int P, bool FULLN>
 __global__ void __launch_bounds__((Cfg<R, P>::WS * Cfg<R, P>::TL), (Cfg<R, P>::MINW))
 k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P>;
@@ -244,61 +276,39 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ cplx<R> stw[P];
   stage_twiddles<R, P>(stw, tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
-  const int N = g.N;
-  const int lo = F.hole ? N / 4 - 1 : 0, nr = F.hole ? N / 2 + 2 : N;
+  const bool full = FULLN && F.kind == 0;  // nout = N = P/2: no bound checks
+  const GridGeo gg = grid_geo(F.kind, g.N);
   const int r = blockIdx.x / NT;
-  if (r >= nr) return;  // uniform per workgroup
+  if (r >= gg.nout) return;  // uniform: a smaller grid of a mixed launch
+  const int z = gg.olo + r;
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int kx = (blockIdx.x % NT) * W + w;
-  const int z = lo + r;
-  const T* B = static_cast<const T*>(F.B);
-  T* A = static_cast<T*>(F.A);
+  const T* B = static_cast<const T*>(F.B) + (size_t)z * P * (P / 2) + kx;
+  T* A = static_cast<T*>(F.A) + (size_t)z * gg.nin * (P / 2) + kx;
   T v[E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) v[q] = B[((size_t)z * P + t + TL * q) * (P / 2) + kx];
+  for (int q = 0; q < E; ++q) v[q] = B[(size_t)(t + TL * q) * (P / 2)];
   LdsView<R> lds{sre, sim, W, 1, w};
   fft_line<R, P, +1, false, true>(v, t, lds, stw);
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int yy = t + TL * q;
-    if (yy >= lo && yy < lo + nr) A[((size_t)z * N + yy) * (P / 2) + kx] = v[q];
+    if (full || (yy >= gg.olo && yy < gg.olo + gg.nout)) A[(size_t)yy * (P / 2)] = v[q];
   }
 }
 
 // ---------------------------------------------------------------------------
-// I1 pass: C2R along x; hole grids write the stencil box, full grids write
-// the potential, adding the carried coarse potential for levels >= 1.
+// I1 pass: C2R along x.  Child-region grids (kind 1) write their potential C
+// on the stencil box.  Full grids write Phi(Omega^l) = Phi^l + Prolong(S_{l-1})
+// (Sect. 4, Eq. 14) and, on the stencil box of a level that has a finer one,
+// the next carry S_l = Phi(Omega^l) - C_l.  The carry is Eqs. 3-6 applied to
+// every fine cell: parent c = N/4 + f/2, neighbour c + s with s = +1 for odd
+// f and -1 for even f per axis, 3/4 and 1/4 weights along the diagonal.
 template <class R>
 __device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
   s = a + b;
   const R bb = s - a;
   e = (a - (s - bb)) + (b - bb);
-}
-
-template <class R>
-__device__ __forceinline__ R add_carry(R val, const FieldDesc& F, int N, int z, int y, int x) {
-  const R* S = static_cast<const R*>(F.S);
-  const R* Sl = static_cast<const R*>(F.Slo);
-  const int NS = N / 2 + 2;
-  const int iz = z / 2 + 1, iy = y / 2 + 1, ix = x / 2 + 1;
-  const int jz = iz + ((z & 1) ? 1 : -1), jy = iy + ((y & 1) ? 1 : -1), jx = ix + ((x & 1) ? 1 : -1);
-  const size_t in = ((size_t)iz * NS + iy) * NS + ix, jn = ((size_t)jz * NS + jy) * NS + jx;
-  const R a = S[in], b = S[jn];
-  if constexpr (sizeof(R) == 8) {
-    return val + ((R)0.75 * a + (R)0.25 * b);
-  } else {
-    // compensated: 3/4 a + 1/4 b + lo terms, then val + (hi + lo)
-    const R p1 = (R)0.75 * a;
-    const R e1 = __builtin_fmaf((R)0.75, a, -p1);
-    const R p2 = (R)0.25 * b;
-    R s, e2;
-    two_sum(p1, p2, s, e2);
-    R lo = e1 + e2;
-    if (Sl) lo += (R)0.75 * Sl[in] + (R)0.25 * Sl[jn];
-    R o, e3;
-    two_sum(val, s, o, e3);
-    return o + (e3 + lo);
-  }
 }
 
 template <class R, int P>
@@ -312,23 +322,25 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   stage_twiddles<R, P>(stw, tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = g.N;
-  const int lo = F.hole ? N / 4 - 1 : 0, nr = F.hole ? N / 2 + 2 : N;
-  if ((int)blockIdx.x * W >= nr * nr) return;  // uniform per workgroup
+  const GridGeo gg = grid_geo(F.kind, N);
+  const int n = gg.nout;
+  if ((int)blockIdx.x * W >= n * n) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
   const int line = blockIdx.x * W + w;
-  const bool active = line < nr * nr;
-  const int z = lo + (active ? line / nr : 0), y = lo + (active ? line % nr : 0);
-  const T* row = static_cast<const T*>(F.A) + ((size_t)z * N + y) * (P / 2);
+  const bool active = line < n * n;
+  const int zr = active ? line / n : 0, yr = active ? line % n : 0;  // within the output box
+  const int z = gg.olo + zr, y = gg.olo + yr;
+  const T* row = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
   T v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
-    const int n = t + TL * q;
+    const int k = t + TL * q;
     T c = T{0, 0};
     if (active) {
-      if (n == 0) c = T{row[0].x, 0};
-      else if (n < P / 2) c = row[n];
-      else if (n == P / 2) c = T{row[0].y, 0};
-      else { const T m = row[P - n]; c = T{m.x, -m.y}; }
+      if (k == 0) c = T{row[0].x, 0};
+      else if (k < P / 2) c = row[k];
+      else if (k == P / 2) c = T{row[0].y, 0};
+      else { const T m = row[P - k]; c = T{m.x, -m.y}; }
     }
     v[q] = c;
   }
@@ -336,15 +348,64 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   fft_line<R, P, +1, false, true>(v, t, lds, stw);
   if (!active) return;
   R* out = static_cast<R*>(F.out);
+  if (F.kind != 0) {  // box output (C or the hole potential)
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) {
+      const int x = t + TL * q;
+      if (x >= gg.olo && x < gg.olo + n) out[((size_t)zr * n + yr) * n + (x - gg.olo)] = v[q].x;
+    }
+    return;
+  }
+  const int NS = N / 2 + 2, blo = N / 4 - 1;
+  const R* S = static_cast<const R*>(F.S);
+  const R* Sl = static_cast<const R*>(F.Slo);
+  R* So = static_cast<R*>(F.Sout);
+  R* Slo = static_cast<R*>(F.Slo_out);
+  const R* Cb = static_cast<const R*>(F.C);
+  const bool yz_box = So && z >= blo && z < blo + NS && y >= blo && y < blo + NS;
+  // carry source rows for this (y, z): parent and diagonal neighbour
+  const int iz = z / 2 + 1, iy = y / 2 + 1;
+  const int jz = iz + ((z & 1) ? 1 : -1), jy = iy + ((y & 1) ? 1 : -1);
+  const size_t srow_i = ((size_t)iz * NS + iy) * NS, srow_j = ((size_t)jz * NS + jy) * NS;
+  const size_t brow = ((size_t)(z - blo) * NS + (y - blo)) * NS - blo;
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
-    const int xx = t + TL * q;
-    if (xx >= lo && xx < lo + nr) {
-      const R val = v[q].x;
-      if (F.hole) {
-        out[((size_t)(z - lo) * nr + (y - lo)) * nr + (xx - lo)] = val;
+    const int x = t + TL * q;
+    if (x >= N) continue;
+    const R val = v[q].x;
+    R hi = val, lo = 0;  // Phi(Omega^l) as an unevaluated sum hi + lo
+    if (S) {
+      const int ix = x / 2 + 1, jx = ix + ((x & 1) ? 1 : -1);
+      const R a = S[srow_i + ix], b = S[srow_j + jx];
+      if (sizeof(R) == 8 || !F.comp) {
+        hi = val + ((R)0.75 * a + (R)0.25 * b);
       } else {
-        out[((size_t)z * N + y) * N + xx] = F.has_carry ? add_carry<R>(val, F, N, z, y, xx) : val;
+        // 3/4 a exactly as p1 + e1 (FMA), 1/4 b is exact; add the carried lo
+        // terms and val with TwoSum
+        const R p1 = (R)0.75 * a;
+        const R e1 = fma((R)0.75, a, -p1);
+        R s1, e2, s2, e3;
+        two_sum(p1, (R)0.25 * b, s1, e2);
+        R l = e1 + e2;
+        if (Sl) l += (R)0.75 * Sl[srow_i + ix] + (R)0.25 * Sl[srow_j + jx];
+        two_sum(val, s1, s2, e3);
+        hi = s2;
+        lo = e3 + l;
+      }
+    }
+    out[((size_t)z * N + y) * N + x] = hi + lo;
+    if (yz_box && x >= blo && x < blo + NS) {
+      const size_t bi = brow + x;
+      if (sizeof(R) == 8 || !F.comp) {
+        So[bi] = hi - Cb[bi];
+        if (Slo) Slo[bi] = 0;
+      } else {
+        R d, e;
+        two_sum(hi, -Cb[bi], d, e);
+        e += lo;
+        const R dh = d + e;
+        So[bi] = dh;
+        if (Slo) Slo[bi] = e - (dh - d);
       }
     }
   }
@@ -374,7 +435,8 @@ __global__ void k_restrict(const R* __restrict__ fine, const R* __restrict__ fin
   rc[id] = s * (R)0.125;
 }
 
-// Carry cascade on the stencil box [N/4-1, 3N/4]^3 (NS = N/2+2 cells).
+// Carry cascade on the stencil box [N/4-1, 3N/4]^3 (NS = N/2+2 cells):
+// S_n = Prolong(S_{n-1}) + Phi^n_hole, the 3/4-1/4 diagonal rule of Eqs. 3-6.
 template <class R>
 __global__ void k_carry(const R* __restrict__ s_hi, const R* __restrict__ s_lo,
                         const R* __restrict__ hole, R* __restrict__ o_hi, R* __restrict__ o_lo,
@@ -387,15 +449,12 @@ __global__ void k_carry(const R* __restrict__ s_hi, const R* __restrict__ s_lo,
   const int jz = iz + ((z & 1) ? 1 : -1), jy = iy + ((y & 1) ? 1 : -1), jx = ix + ((x & 1) ? 1 : -1);
   const size_t in = ((size_t)iz * NS + iy) * NS + ix, jn = ((size_t)jz * NS + jy) * NS + jx;
   const R a = s_hi[in], b = s_hi[jn], h = hole[id];
-  if constexpr (sizeof(R) == 8) {
-    o_hi[id] = ((R)0.75 * a + (R)0.25 * b) + h;
-    if (o_lo) o_lo[id] = 0;
-  } else if (!compensated) {
+  if (sizeof(R) == 8 || !compensated) {
     o_hi[id] = ((R)0.75 * a + (R)0.25 * b) + h;
     if (o_lo) o_lo[id] = 0;
   } else {
     const R p1 = (R)0.75 * a;
-    const R e1 = __builtin_fmaf((R)0.75, a, -p1);
+    const R e1 = fma((R)0.75, a, -p1);
     const R p2 = (R)0.25 * b;
     R s, e2;
     two_sum(p1, p2, s, e2);
@@ -530,7 +589,7 @@ hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP>;
-    dim3 grid((g.N * g.N + C::WC - 1) / C::WC, g.nf);
+    dim3 grid((g.n * g.n + C::WC - 1) / C::WC, g.nf);
     if (g.N == PP / 2)
       hipLaunchKernelGGL((k_fwd_x<R, PP, true>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
     else
@@ -543,7 +602,7 @@ hipError_t launch_fwd_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP>;
-    dim3 grid(((PP / 2) / C::WS) * g.N, g.nf);
+    dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
     if (g.N == PP / 2)
       hipLaunchKernelGGL((k_fwd_y<R, PP, true>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
     else
@@ -569,8 +628,11 @@ hipError_t launch_inv_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP>;
-    dim3 grid(((PP / 2) / C::WS) * g.N, g.nf);
-    hipLaunchKernelGGL((k_inv_y<R, PP>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+    dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
+    if (g.N == PP / 2)
+      hipLaunchKernelGGL((k_inv_y<R, PP, true>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+    else
+      hipLaunchKernelGGL((k_inv_y<R, PP, false>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
   });
 }
 
@@ -579,7 +641,7 @@ hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP>;
-    dim3 grid((g.N * g.N + C::WC - 1) / C::WC, g.nf);
+    dim3 grid((g.n * g.n + C::WC - 1) / C::WC, g.nf);
     hipLaunchKernelGGL((k_inv_x<R, PP>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
   });
 }

@@ -41,19 +41,34 @@ int period_of(int N) {
 
 size_t real_size(nmc_precision p) { return p == NMC_F64 ? 8 : 4; }
 
-// Workspace layout of one request (offsets from its base).
+// Two ways to obtain the hole potentials of Sect. 4 on the stencil box:
+//  * hole grids (kind 2): each level with its child region zeroed, carried by
+//    a small cascade S_n = Prolong(S_{n-1}) + Phi^n_hole;
+//  * child-region boxes (kind 1): the child region alone in an (N/2+2)^3 box,
+//    Phi_hole = Phi - C, and S_l = Phi(Omega^l) - C_l left by the last pass of
+//    level l.  Cheaper grids but one last-pass launch per level, which pays
+//    from N = 128 up (measured).
+bool use_boxes(int N) { return N >= 128; }
+
+// Workspace layout of one request (offsets from its base): per level l the
+// full grid's A and B; per level l < L-1 the second grid (hole grid or
+// child-region box), the restricted density Rc, the box potential (hole
+// potential or C) and the carried potential S (hi, and lo for the FP32 path).
 struct Layout {
-  int N, L, P;
+  int N, L, P, NC;
+  bool boxes;
   size_t r, c;
-  size_t a_bytes, b_bytes, rc_bytes, box_bytes;
+  size_t a_full, b_full, a_sec, b_sec, rc_bytes, box_bytes;
   size_t total;
-  // field f: 0..L-1 full level f, L..2L-2 hole level f-L
-  size_t A(int f) const { return f * (a_bytes + b_bytes); }
-  size_t B(int f) const { return A(f) + a_bytes; }
-  size_t fields_end() const { return (size_t)(2 * L - 1) * (a_bytes + b_bytes); }
-  size_t Rc(int l) const { return fields_end() + (size_t)l * rc_bytes; }            // l < L-1
-  size_t H(int l) const { return Rc(0) + (size_t)(L - 1) * rc_bytes + l * box_bytes; }  // l < L-1
-  size_t Shi(int l) const { return H(0) + (size_t)(L - 1) * box_bytes + (size_t)(l - 1) * 2 * box_bytes; }  // 1 <= l <= L-2
+  size_t A(int l) const { return (size_t)l * (a_full + b_full); }
+  size_t B(int l) const { return A(l) + a_full; }
+  size_t full_end() const { return (size_t)L * (a_full + b_full); }
+  size_t As(int l) const { return full_end() + (size_t)l * (a_sec + b_sec); }
+  size_t Bs(int l) const { return As(l) + a_sec; }
+  size_t sec_end() const { return full_end() + (size_t)(L - 1) * (a_sec + b_sec); }
+  size_t Rc(int l) const { return sec_end() + (size_t)l * rc_bytes; }
+  size_t Box(int l) const { return Rc(0) + (size_t)(L - 1) * rc_bytes + (size_t)l * box_bytes; }
+  size_t Shi(int l) const { return Box(0) + (size_t)(L - 1) * box_bytes + (size_t)l * 2 * box_bytes; }
   size_t Slo(int l) const { return Shi(l) + box_bytes; }
 };
 
@@ -62,15 +77,18 @@ Layout make_layout(int N, int L, nmc_precision p) {
   lo.N = N;
   lo.L = L;
   lo.P = period_of(N);
+  lo.NC = N / 2 + 2;
+  lo.boxes = use_boxes(N);
   lo.r = real_size(p);
   lo.c = 2 * lo.r;
-  const size_t P = lo.P, NS = N / 2 + 2;
-  lo.a_bytes = align_up((size_t)N * N * (P / 2) * lo.c);
-  lo.b_bytes = align_up((size_t)N * P * (P / 2) * lo.c);
+  const size_t P = lo.P, NC = lo.NC, ns = lo.boxes ? NC : (size_t)N;
+  lo.a_full = align_up((size_t)N * N * (P / 2) * lo.c);
+  lo.b_full = align_up((size_t)N * P * (P / 2) * lo.c);
+  lo.a_sec = align_up(ns * ns * (P / 2) * lo.c);
+  lo.b_sec = align_up(ns * P * (P / 2) * lo.c);
   lo.rc_bytes = align_up((size_t)(N / 2) * (N / 2) * (N / 2) * lo.r);
-  lo.box_bytes = align_up(NS * NS * NS * lo.r);
-  lo.total = lo.fields_end() + (size_t)(L - 1) * lo.rc_bytes + (size_t)(L - 1) * lo.box_bytes +
-             (size_t)std::max(0, L - 2) * 2 * lo.box_bytes;
+  lo.box_bytes = align_up(NC * NC * NC * lo.r);
+  lo.total = lo.Shi(0) + (size_t)(L - 1) * 2 * lo.box_bytes;
   lo.total = std::max(lo.total, kAlign);
   return lo;
 }
@@ -374,19 +392,26 @@ struct ProfScope {
 };
 
 // Algorithmic HBM bytes of one grid in each pass (what the pruned method reads
-// and writes with this layout; the zero padding is never touched).
+// and writes with this layout; the zero padding is never touched).  nin is
+// the grid's input extent per axis and nout its output rows (FieldDesc).
 struct PassBytes {
-  double r, c, N, P, H, Nz;
-  PassBytes(int N_, int P_, size_t rsz, bool hole)
-      : r((double)rsz), c(2.0 * rsz), N(N_), P(P_), H(P_ / 2 + 1), Nz(hole ? N_ / 2 + 2 : N_) {}
+  double r, c, N, nin, nout, P, H, NS;
+  int kind;
+  PassBytes(int N_, int P_, size_t rsz, int kind_)
+      : r((double)rsz), c(2.0 * rsz), N(N_), nin(kind_ == 1 ? N_ / 2 + 2 : N_),
+        nout(kind_ == 0 ? N_ : N_ / 2 + 2), P(P_), H(P_ / 2 + 1), NS(N_ / 2 + 2), kind(kind_) {}
   double half() const { return P / 2; }
-  double x() const { return N * N * N * r + N * N * half() * c; }
-  double y() const { return N * N * half() * c + N * P * half() * c; }
-  double z() const { return N * P * half() * c + Nz * P * half() * c + H * H * H * r; }
-  double iy() const { return Nz * P * half() * c + Nz * Nz * half() * c; }
-  double ix(bool carry) const {
-    const double NS = N / 2 + 2;
-    return Nz * Nz * half() * c + Nz * Nz * Nz * r + (carry ? 2 * NS * NS * NS * r : 0.0);
+  double x() const {
+    const double in = kind == 1 ? std::pow(N / 2, 3) : N * N * N;
+    return in * r + nin * nin * half() * c;
+  }
+  double y() const { return nin * nin * half() * c + nin * P * half() * c; }
+  double z() const { return (nin + nout) * P * half() * c + H * H * H * r; }
+  double iy() const { return nout * P * half() * c + nout * nout * half() * c; }
+  double ix(bool carry, bool next) const {
+    // the carried box S is read once per level; C is read and S_l written
+    return nout * nout * half() * c + nout * nout * nout * r + (carry ? NS * NS * NS * r : 0.0) +
+           (next ? 2 * NS * NS * NS * r : 0.0);
   }
 };
 
@@ -396,6 +421,8 @@ template <class R>
 int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s, hipStream_t aux) {
   const int N = reqs[0].N;
   const int P = period_of(N);
+  const int NC = N / 2 + 2;
+  const bool boxes = use_boxes(N);
   PerP& pp = ctx->perp[P];
   nmc::Tables<R> tb;
   if constexpr (sizeof(R) == 8) {
@@ -408,23 +435,32 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     tb.gn = pp.gn32;
   }
   const size_t lvl = (size_t)N * N * N;
-  std::vector<FieldDesc> fulls, holes;
+  std::vector<FieldDesc> fulls, secs;  // full grids; hole grids or child-region boxes
+  std::vector<int> full_level;
   struct RestrictStep {
     const R* fine;
     const R* fine_rc;
     R* out;
   };
   std::vector<RestrictStep> restricts;
+  struct CarryStep {
+    const R *shi, *slo, *hole;
+    R *ohi, *olo;
+    int comp;
+  };
+  std::vector<CarryStep> carries;
+  int maxL = 0;
   size_t off = 0;
   for (int i = 0; i < count; ++i) {
     const Req& q = reqs[i];
     const Layout lo = make_layout(N, q.L, q.p);
     char* base = ws + off;
     off += lo.total;
+    maxL = std::max(maxL, q.L);
     const R* rho = (const R*)q.rho;
     R* phi = (R*)q.phi;
     const bool restrict_on = !(q.flags & NMC_NO_RESTRICT);
-    const bool comp = !(q.flags & NMC_F32_UNCOMPENSATED);
+    const bool comp = sizeof(R) == 4 && !(q.flags & NMC_F32_UNCOMPENSATED);
     if (restrict_on) {
       for (int l = q.L - 2; l >= 0; --l) {
         const R* fine_rc = (l + 1 <= q.L - 2) ? (const R*)(base + lo.Rc(l + 1)) : nullptr;
@@ -434,57 +470,68 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     const double P3 = (double)P * P * P;
     for (int l = 0; l < q.L; ++l) {
       const double h = std::ldexp(q.h0, -l);
+      const bool finer = l < q.L - 1;  // a finer level exists
       FieldDesc f{};
       f.rho = rho + (size_t)l * lvl;
-      f.rc = (restrict_on && l < q.L - 1) ? (const void*)(base + lo.Rc(l)) : nullptr;
+      f.rc = (restrict_on && finer) ? (const void*)(base + lo.Rc(l)) : nullptr;
       f.A = base + lo.A(l);
       f.B = base + lo.B(l);
       f.out = phi + (size_t)l * lvl;
-      f.scale = -q.G * h * h / P3;
-      f.hole = 0;
-      f.has_carry = l >= 1;
-      if (l == 1) {
-        f.S = base + lo.H(0);
-        f.Slo = nullptr;
-      } else if (l >= 2) {
-        f.S = base + lo.Shi(l - 1);
-        f.Slo = (sizeof(R) == 4 && comp) ? (const void*)(base + lo.Slo(l - 1)) : nullptr;
+      if (l >= 1) {
+        // hole grids: S_0 is the hole potential itself; boxes: S_0 lives in Shi(0)
+        f.S = (!boxes && l == 1) ? base + lo.Box(0) : base + lo.Shi(l - 1);
+        f.Slo = (comp && (boxes || l >= 2)) ? (const void*)(base + lo.Slo(l - 1)) : nullptr;
       }
+      if (boxes && finer) {
+        f.Sout = base + lo.Shi(l);
+        f.Slo_out = comp ? (void*)(base + lo.Slo(l)) : nullptr;
+        f.C = base + lo.Box(l);
+      }
+      f.scale = -q.G * h * h / P3;
+      f.kind = 0;
+      f.comp = comp ? 1 : 0;
       fulls.push_back(f);
-      if (l < q.L - 1) {
-        FieldDesc hf{};
-        hf.rho = f.rho;
-        hf.rc = nullptr;
-        hf.A = base + lo.A(q.L + l);
-        hf.B = base + lo.B(q.L + l);
-        hf.out = base + lo.H(l);
-        hf.scale = f.scale;
-        hf.hole = 1;
-        holes.push_back(hf);
+      full_level.push_back(l);
+      if (finer) {
+        FieldDesc c{};
+        c.rho = f.rho;
+        c.rc = boxes ? f.rc : nullptr;
+        c.A = base + lo.As(l);
+        c.B = base + lo.Bs(l);
+        c.out = base + lo.Box(l);
+        c.scale = f.scale;
+        c.kind = boxes ? 1 : 2;
+        c.comp = f.comp;
+        secs.push_back(c);
+      }
+      if (!boxes && l >= 1 && finer) {  // S_l = Prolong(S_{l-1}) + Phi^l_hole
+        carries.push_back({(const R*)(base + (l == 1 ? lo.Box(0) : lo.Shi(l - 1))),
+                           (l == 1 || !comp) ? nullptr : (const R*)(base + lo.Slo(l - 1)),
+                           (const R*)(base + lo.Box(l)), (R*)(base + lo.Shi(l)),
+                           comp ? (R*)(base + lo.Slo(l)) : nullptr, comp ? 1 : 0});
       }
     }
   }
-  std::vector<FieldDesc> all(fulls);
-  all.insert(all.end(), holes.begin(), holes.end());
-  auto for_chunks = [&](const std::vector<FieldDesc>& fs, auto launch, int pass, hipStream_t s) -> hipError_t {
+  auto for_chunks = [&](const std::vector<FieldDesc>& fs, int n, auto launch, int pass,
+                        hipStream_t st) -> hipError_t {
     for (size_t a = 0; a < fs.size(); a += nmc::kMaxFieldsPerLaunch) {
       FieldTable ft{};
-      const int n = (int)std::min<size_t>(nmc::kMaxFieldsPerLaunch, fs.size() - a);
+      const int cnt = (int)std::min<size_t>(nmc::kMaxFieldsPerLaunch, fs.size() - a);
       double bytes = 0;
-      for (int k = 0; k < n; ++k) {
+      for (int k = 0; k < cnt; ++k) {
         ft.f[k] = fs[a + k];
-        const PassBytes pb(N, P, sizeof(R), ft.f[k].hole != 0);
+        const PassBytes pb(N, P, sizeof(R), ft.f[k].kind);
         switch (pass) {
           case NMC_PASS_X: bytes += pb.x(); break;
           case NMC_PASS_Y: bytes += pb.y(); break;
           case NMC_PASS_Z: bytes += pb.z(); break;
           case NMC_PASS_IY: bytes += pb.iy(); break;
-          default: bytes += pb.ix(ft.f[k].has_carry != 0); break;
+          default: bytes += pb.ix(ft.f[k].S != nullptr, ft.f[k].Sout != nullptr); break;
         }
       }
-      PassGeom g{N, P, n, 0};
-      ProfScope ps(ctx, s, pass, bytes);
-      hipError_t e = launch(ft, g, tb, s);
+      PassGeom g{N, P, n, cnt};
+      ProfScope ps(ctx, st, pass, bytes);
+      hipError_t e = launch(ft, g, tb, st);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -497,59 +544,60 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     }
     return NMC_OK;
   };
-  // carry cascade per request: S_n = Prolong(S_{n-1}) + Phi^n_hole, S_0 = Phi^0_hole
   auto carry_cascade = [&](hipStream_t st) -> int {
-    size_t o = 0;
-    for (int i = 0; i < count; ++i) {
-      const Req& q = reqs[i];
-      const Layout lo = make_layout(N, q.L, q.p);
-      char* base = ws + o;
-      o += lo.total;
-      const bool comp = sizeof(R) == 4 && !(q.flags & NMC_F32_UNCOMPENSATED);
-      for (int n = 1; n <= q.L - 2; ++n) {
-        const R* shi = (const R*)(base + (n == 1 ? lo.H(0) : lo.Shi(n - 1)));
-        const R* slo = (n == 1 || !comp) ? nullptr : (const R*)(base + lo.Slo(n - 1));
-        const double ns3 = std::pow((double)(N / 2 + 2), 3);
-        ProfScope ps(ctx, st, NMC_PASS_CARRY, ns3 * sizeof(R) * (comp ? 6 : 3));
-        NMC_HIP(ctx, nmc::launch_carry<R>(shi, slo, (const R*)(base + lo.H(n)), (R*)(base + lo.Shi(n)),
-                                          comp ? (R*)(base + lo.Slo(n)) : nullptr, N, comp ? 1 : 0, st));
-      }
+    const double ns3 = std::pow((double)NC, 3);
+    for (const auto& c : carries) {
+      ProfScope ps(ctx, st, NMC_PASS_CARRY, ns3 * sizeof(R) * (c.comp ? 6 : 3));
+      NMC_HIP(ctx, nmc::launch_carry<R>(c.shi, c.slo, c.hole, c.ohi, c.olo, N, c.comp, st));
     }
     return NMC_OK;
   };
+  auto forward_to_iy = [&](const std::vector<FieldDesc>& fs, int nin, int nout, hipStream_t st) -> int {
+    if (fs.empty()) return NMC_OK;
+    NMC_HIP(ctx, for_chunks(fs, nin, nmc::launch_fwd_x<R>, NMC_PASS_X, st));
+    NMC_HIP(ctx, for_chunks(fs, nin, nmc::launch_fwd_y<R>, NMC_PASS_Y, st));
+    NMC_HIP(ctx, for_chunks(fs, nin, nmc::launch_z<R>, NMC_PASS_Z, st));
+    NMC_HIP(ctx, for_chunks(fs, nout, nmc::launch_inv_y<R>, NMC_PASS_IY, st));
+    return NMC_OK;
+  };
   int rc;
-  // The split pays off once the passes are long enough to overlap (measured
-  // stable from N = 128 up; below, it varied from run to run).
-  const bool one_stream = (reqs[0].flags & NMC_ONE_STREAM) != 0 || N < 128;
-  if (aux && aux != s && !holes.empty() && !ctx->profiling && !one_stream) {
-    // Two branches: the hole grids and the carry cascade need no restriction,
-    // so they run on `aux` while `s` restricts and transforms the full grids;
-    // only the final inverse-x pass of the full grids needs both.
+  if (!boxes) {
+    // hole grids: one stream, full and hole grids share every launch
+    if ((rc = restrict_cascade(s))) return rc;
+    std::vector<FieldDesc> all(fulls);
+    all.insert(all.end(), secs.begin(), secs.end());
+    if ((rc = forward_to_iy(all, N, N, s))) return rc;
+    if (!secs.empty()) NMC_HIP(ctx, for_chunks(secs, NC, nmc::launch_inv_x<R>, NMC_PASS_IX_SECOND, s));
+    if ((rc = carry_cascade(s))) return rc;
+    NMC_HIP(ctx, for_chunks(fulls, N, nmc::launch_inv_x<R>, NMC_PASS_IX_FULL, s));
+    return NMC_OK;
+  }
+  // child-region boxes: they need the restriction, then the boxes and the
+  // full grids are independent until the last pass and may use two streams
+  if ((rc = restrict_cascade(s))) return rc;
+  const bool one_stream = (reqs[0].flags & NMC_ONE_STREAM) != 0;
+  if (aux && aux != s && !secs.empty() && !ctx->profiling && !one_stream) {
     NMC_HIP(ctx, hipEventRecord(ctx->ev_fork, s));
     NMC_HIP(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0));
-    NMC_HIP(ctx, for_chunks(holes, nmc::launch_fwd_x<R>, NMC_PASS_X, aux));
-    if ((rc = restrict_cascade(s))) return rc;
-    NMC_HIP(ctx, for_chunks(holes, nmc::launch_fwd_y<R>, NMC_PASS_Y, aux));
-    NMC_HIP(ctx, for_chunks(fulls, nmc::launch_fwd_x<R>, NMC_PASS_X, s));
-    NMC_HIP(ctx, for_chunks(holes, nmc::launch_z<R>, NMC_PASS_Z, aux));
-    NMC_HIP(ctx, for_chunks(fulls, nmc::launch_fwd_y<R>, NMC_PASS_Y, s));
-    NMC_HIP(ctx, for_chunks(holes, nmc::launch_inv_y<R>, NMC_PASS_IY, aux));
-    NMC_HIP(ctx, for_chunks(fulls, nmc::launch_z<R>, NMC_PASS_Z, s));
-    NMC_HIP(ctx, for_chunks(holes, nmc::launch_inv_x<R>, NMC_PASS_IX_HOLE, aux));
-    if ((rc = carry_cascade(aux))) return rc;
-    NMC_HIP(ctx, for_chunks(fulls, nmc::launch_inv_y<R>, NMC_PASS_IY, s));
+    if ((rc = forward_to_iy(secs, NC, NC, aux))) return rc;
+    NMC_HIP(ctx, for_chunks(secs, NC, nmc::launch_inv_x<R>, NMC_PASS_IX_SECOND, aux));
+    if ((rc = forward_to_iy(fulls, N, N, s))) return rc;
     NMC_HIP(ctx, hipEventRecord(ctx->ev_join, aux));
     NMC_HIP(ctx, hipStreamWaitEvent(s, ctx->ev_join, 0));
   } else {
-    if ((rc = restrict_cascade(s))) return rc;
-    NMC_HIP(ctx, for_chunks(all, nmc::launch_fwd_x<R>, NMC_PASS_X, s));
-    NMC_HIP(ctx, for_chunks(all, nmc::launch_fwd_y<R>, NMC_PASS_Y, s));
-    NMC_HIP(ctx, for_chunks(all, nmc::launch_z<R>, NMC_PASS_Z, s));
-    NMC_HIP(ctx, for_chunks(all, nmc::launch_inv_y<R>, NMC_PASS_IY, s));
-    if (!holes.empty()) NMC_HIP(ctx, for_chunks(holes, nmc::launch_inv_x<R>, NMC_PASS_IX_HOLE, s));
-    if ((rc = carry_cascade(s))) return rc;
+    std::vector<FieldDesc> all(fulls);
+    all.insert(all.end(), secs.begin(), secs.end());
+    if ((rc = forward_to_iy(all, N, N, s))) return rc;
+    if (!secs.empty()) NMC_HIP(ctx, for_chunks(secs, NC, nmc::launch_inv_x<R>, NMC_PASS_IX_SECOND, s));
   }
-  NMC_HIP(ctx, for_chunks(fulls, nmc::launch_inv_x<R>, NMC_PASS_IX_FULL, s));
+  // Last pass of the full grids, coarsest level first: level l adds the carry
+  // S_{l-1} left by level l-1 and leaves S_l for level l+1.
+  for (int l = 0; l < maxL; ++l) {
+    std::vector<FieldDesc> fl;
+    for (size_t k = 0; k < fulls.size(); ++k)
+      if (full_level[k] == l) fl.push_back(fulls[k]);
+    NMC_HIP(ctx, for_chunks(fl, N, nmc::launch_inv_x<R>, NMC_PASS_IX_FULL, s));
+  }
   return NMC_OK;
 }
 
@@ -1030,7 +1078,7 @@ int nmc_profile_read(nmc_ctx* ctx, nmc_pass_stat* out) {
 }
 
 const char* nmc_pass_name(int pass) {
-  static const char* names[NMC_NUM_PASSES] = {"restrict", "x", "y", "z", "inv_y", "inv_x_hole", "carry", "inv_x_full"};
+  static const char* names[NMC_NUM_PASSES] = {"restrict", "x", "y", "z", "inv_y", "inv_x_second", "carry", "inv_x_full"};
   return (pass >= 0 && pass < NMC_NUM_PASSES) ? names[pass] : "?";
 }
 

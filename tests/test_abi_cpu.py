@@ -51,12 +51,17 @@ def test_period(lib):
 def test_footprint(lib):
     from paper_2301_06763_amd import nmc
     import torch
-    # per grid: A = N*N*(P/2) and B = N*P*(P/2) complex values, 2L-1 grids
+    # per full grid: A = N*N*(P/2) and B = N*P*(P/2) complex values; L full grids and
+    # L-1 smaller child-region boxes
     N, L = 64, 5
     P = 128
     grid = (N * N * (P // 2) + N * P * (P // 2)) * 16
     fp = nmc.footprint_bytes(N, L, torch.float64)
-    assert (2 * L - 1) * grid <= fp < (2 * L - 1) * grid * 1.05
+    assert (2 * L - 1) * grid <= fp < (2 * L - 1) * grid * 1.05  # hole grids below N = 128
+    N2, P2 = 128, 256
+    grid2 = (N2 * N2 * (P2 // 2) + N2 * P2 * (P2 // 2)) * 16
+    fp2 = nmc.footprint_bytes(N2, L, torch.float64)
+    assert L * grid2 < fp2 < (2 * L - 1) * grid2  # smaller child-region boxes from N = 128
     assert nmc.footprint_bytes(N, L, torch.float32) < fp
     out = ctypes.c_size_t()
     assert lib.nmc_footprint_bytes(6, 2, 0, ctypes.byref(out)) == nmc.NMC_EINVAL
@@ -87,5 +92,5 @@ def test_create_without_gpu_fails_cleanly(lib):
 
 def test_pass_names(lib):
     names = [lib.nmc_pass_name(i).decode() for i in range(8)]
-    assert names == ["restrict", "x", "y", "z", "inv_y", "inv_x_hole", "carry", "inv_x_full"]
+    assert names == ["restrict", "x", "y", "z", "inv_y", "inv_x_second", "carry", "inv_x_full"]
     assert lib.nmc_pass_name(99) == b"?"
