@@ -23,7 +23,7 @@ namespace nmc {
 //    nout = N/2 + 2).
 struct FieldDesc {
   const void* rho;   // level density [N][N][N] (x fastest), caller-owned
-  const void* rc;    // restricted density of the child region [(N/2)^3], or null
+  const void* rc;    // restriction data of the child region (pyramid slab of level l+1), or null
   void* A;           // workspace [nin][nin][P/2] complex: x-pass output, y-inverse output
   void* B;           // workspace [nin][P][P/2] complex: y-pass output, z-pass in place
   void* out;         // kind 0: potential [N][N][N]; kinds 1, 2: box [(N/2+2)^3]
@@ -33,9 +33,65 @@ struct FieldDesc {
   void* Slo_out;     // its compensation term (FP32 path) or null
   const void* C;     // with Sout: C_l on the box
   double scale;      // -G h^2 / P^3 (mass = rho h^3, kernel 1/(h |d|), 1/P^3 of the inverse)
+  long long rslab;   // elements between the restriction slabs of consecutive levels
+  int rdepth;        // terms of the restricted value (1: rc holds the finished restriction)
   int kind;          // 0 full level, 1 child-region box, 2 level with its child region zeroed
   int comp;          // FP32: compensated (two-term) carry
 };
+
+// Restriction data (Sect. 2: the density of a level's child region is the
+// mean over the 2x2x2 children of the next finer level, whose own child
+// region is restricted in turn).  Unrolled, the restricted value of cell c
+// of level l's child region is a sum over the finer levels k > l of the
+// mean of m_k over c's footprint on level k, where m_k is level k's density
+// with its own child region zeroed (k < L-1).  When N is a multiple of 2^L
+// every footprint is an aligned block of 2^(k-l) cells per axis, so with
+// block means of m_k at every size 2^d stored per level ("pyramid"), the
+// restricted value is L-1-l loads.  Level k's slab holds, for d = 1, 2, ...,
+// the block means at size 2^d ((N >> d)^3 values each, x fastest), one after
+// the other; the slab of level k starts (k-1)*slab elements after level 1's.
+// rdepth = 1 reads a single finished value per cell (cascaded restriction).
+inline long long pyramid_slab(int N, int L) {
+  long long s = 0;
+  for (int d = 1; d <= L - 1 && (N >> d) > 0; ++d) s += (long long)(N >> d) * (N >> d) * (N >> d);
+  return s;
+}
+inline bool pyramid_exact(int N, int L) { return L >= 2 && L - 1 <= 5 && N % (1 << L) == 0; }
+constexpr int kMaxPyramidDepth = 5;  // blocks up to 32^3 cells per workgroup
+// Edge of the cube of level k a workgroup reduces: a multiple of 2^k that
+// divides N, grown up to 16 cells when N allows.
+__host__ __device__ inline int pyramid_cube(int N, int k) {
+  int S = 1 << k;
+  while (S < 16 && N % (2 * S) == 0) S *= 2;
+  return S;
+}
+
+struct PyramidDesc {
+  const void* rho;  // the request's densities, L levels of N^3
+  void* pyr;        // slab of level 1; level k at (k-1)*slab
+  long long slab;
+  int L;
+};
+constexpr int kMaxPyramidsPerLaunch = 24;
+struct PyramidTable {
+  PyramidDesc r[kMaxPyramidsPerLaunch];
+};
+
+// Carry cascade of the hole pipeline (Sect. 4, Eqs. 3-6), on the stencil box
+// [N/4-1, 3N/4]^3 of every level (NB = N/2+2 cells per axis, x fastest):
+// S_0 = Phi^0_hole, S_n = Prolong(S_{n-1}) + Phi^n_hole.
+struct CarryDesc {
+  const void* hole;    // Phi^n_hole of level n at hole + n * box
+  void* S;             // S_n (hi) at S + n * 2 * box, its compensation term box elements later
+  long long box;       // elements per box (padded)
+  int comp;            // FP32: keep the two-term (hi, lo) sums
+};
+constexpr int kMaxCarriesPerLaunch = 24;
+struct CarryTable {
+  CarryDesc r[kMaxCarriesPerLaunch];
+  int nlev[kMaxCarriesPerLaunch];  // levels n0..n0+nlev-1 of this launch, per request
+};
+constexpr int kMaxCarryDepth = 4;  // levels per launch: each S_n from S_{n0-1} in one recursion
 
 constexpr int kMaxFieldsPerLaunch = 24;
 struct FieldTable {
@@ -67,13 +123,18 @@ template <class R> hipError_t launch_z(const FieldTable&, PassGeom, Tables<R>, h
 template <class R> hipError_t launch_inv_y(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 template <class R> hipError_t launch_inv_x(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 
-// Restriction of level l+1 onto the child region of level l.
+// Restriction of level l+1 onto the child region of level l, one level per
+// launch (any N); fine_rc is the finished restriction of level l+1 or null.
 template <class R>
 hipError_t launch_restrict(const R* fine, const R* fine_rc, R* rc_out, int N, hipStream_t);
-// S_n = Prolong(S_{n-1}) + Phi^n_hole on the stencil box (hi/lo pair; lo may be null).
+// Block-mean pyramids of every level k >= 1 of up to kMaxPyramidsPerLaunch
+// requests in one launch (requires pyramid_exact(N, L) for each).
 template <class R>
-hipError_t launch_carry(const R* s_hi, const R* s_lo, const R* hole, R* o_hi, R* o_lo, int N,
-                        int compensated, hipStream_t);
+hipError_t launch_pyramid(const PyramidTable&, int count, int N, int maxL, hipStream_t);
+// S_n for n = n0 .. n0 + nlev - 1 (nlev <= kMaxCarryDepth), each from S_{n0-1}
+// (S_0 = Phi^0_hole when n0 = 1) by unrolling the cascade, in one launch.
+template <class R>
+hipError_t launch_carry(const CarryTable&, int count, int N, int n0, hipStream_t);
 
 // Green spectrum, FP64: three separable passes over the even octant.
 hipError_t launch_green(int P, double beta, const double2* tw, double* t1, double* t2, double* out,

@@ -20,6 +20,8 @@
 // so every global access is a run of W complex values.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fft_core.hpp"
 #include "kernels.h"
 
@@ -29,7 +31,10 @@ namespace nmc {
 #define NMC_Z_LDS_KB 64
 #endif
 #ifndef NMC_MIN_WAVES_F32
-#define NMC_MIN_WAVES_F32 1
+#define NMC_MIN_WAVES_F32 6
+#endif
+#ifndef NMC_MIN_WAVES_F32_BIG
+#define NMC_MIN_WAVES_F32_BIG 1
 #endif
 #ifndef NMC_MIN_WAVES_F64
 #define NMC_MIN_WAVES_F64 4
@@ -49,8 +54,10 @@ struct Cfg {
   static constexpr int WZ0 = cmin(cmin(P / 2, 128 / BYTES_PT), NMC_Z_LDS_KB * 1024 / (2 * P * BYTES_PT));
   static constexpr int WZ = P >= 512 ? WZ0 : cmin(WZ0, 256 / TL > 0 ? 256 / TL : 1);
   static constexpr int WC = cmin(cmin(256 / TL, 64), LDS / (P * BYTES_PT));  // x passes
-  // resident waves per SIMD the register allocation must allow
-  static constexpr int MINW = sizeof(R) == 8 ? NMC_MIN_WAVES_F64 : NMC_MIN_WAVES_F32;
+  // resident waves per SIMD the register allocation must allow (FP32: 6,
+  // i.e. 80 VGPRs and three z workgroups per CU, up to P = 128; at P = 256
+  // the two-stream schedule ran faster with the unconstrained allocation)
+  static constexpr int MINW = sizeof(R) == 8 ? NMC_MIN_WAVES_F64 : P <= 128 ? NMC_MIN_WAVES_F32 : NMC_MIN_WAVES_F32_BIG;
   static_assert(WS >= 1 && WZ >= 1 && WC >= 1, "tile does not fit");
 };
 
@@ -59,6 +66,64 @@ struct Cfg {
 template <class R, int P>
 __device__ __forceinline__ void stage_twiddles(cplx<R>* stw, const cplx<R>* __restrict__ tw) {
   for (int j = threadIdx.x; j < P; j += blockDim.x) stw[j] = tw[j];
+}
+
+// The same for a workgroup of NTH threads, split in two: the loads are
+// issued first (constructor) and the LDS writes (put) come after the
+// kernel's own data loads, so that no load waits for another.
+template <class R, int P, int NTH>
+struct TwStage {
+  static constexpr int K = (P + NTH - 1) / NTH;
+  cplx<R> r[K];
+  __device__ __forceinline__ explicit TwStage(const cplx<R>* __restrict__ tw) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = threadIdx.x + k * NTH;
+      if (j < P) r[k] = tw[j];
+    }
+  }
+  __device__ __forceinline__ void put(cplx<R>* stw) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = threadIdx.x + k * NTH;
+      if (j < P) stw[j] = r[k];
+    }
+  }
+};
+
+// Restricted density of cell (cz, cy, cx) of a level's child region (cell
+// c + N/4 of the level) from the restriction data F.rc: the sum over the
+// finer levels k = l+1, l+2, ... of the block mean of m_k over the cell's
+// footprint (Sect. 2; the unrolled cascade, kernels.h).  The footprint on
+// level l+1 is the block [2c, 2c+2); on the next level it is
+// [2 z - N/2, ...) twice as wide, as long as it lies inside that level.
+template <class R>
+__device__ __forceinline__ R restricted_at(const FieldDesc& F, int N, int cz, int cy, int cx) {
+  const R* base = static_cast<const R*>(F.rc);
+  const R* p = base;
+  int z = 2 * cz, y = 2 * cy, x = 2 * cx;
+  bool on = true;
+  size_t off = 0;
+  // every term's load is issued before the first is used; terms past the
+  // footprint's last level read the first value and are dropped
+  R t[kMaxPyramidDepth];
+#pragma unroll
+  for (int d = 1; d <= kMaxPyramidDepth; ++d) {
+    on = on && d <= F.rdepth;
+    const int nd = N >> d;
+    t[d - 1] = on ? p[off + ((size_t)(z >> d) * nd + (y >> d)) * nd + (x >> d)] : base[0];
+    if (!on) t[d - 1] = 0;
+    z = 2 * z - N / 2;
+    y = 2 * y - N / 2;
+    x = 2 * x - N / 2;
+    on = on && (unsigned)z < (unsigned)N && (unsigned)y < (unsigned)N && (unsigned)x < (unsigned)N;
+    p += F.rslab;
+    off += (size_t)nd * nd * nd;
+  }
+  R s = 0;
+#pragma unroll
+  for (int d = 0; d < kMaxPyramidDepth; ++d) s += t[d];
+  return s;
 }
 
 // Input extent nin and output rows [olo, olo + nout) of a grid (FieldDesc).
@@ -81,35 +146,40 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   constexpr int E = C::E, TL = C::TL, W = C::WC;
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
-  stage_twiddles<R, P>(stw, tb.tw);
+  const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
-  const int N = g.N, n = grid_geo(F.kind, N).nin;
+  const int N = FULLN ? P / 2 : g.N, n = grid_geo(F.kind, N).nin;
   if ((int)blockIdx.x * W >= n * n) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
   const int line = blockIdx.x * W + w;
   const bool active = line < n * n;
   const int z = active ? line / n : 0, y = active ? line % n : 0;
   const R* rho = static_cast<const R*>(F.rho);
-  const R* rc = static_cast<const R*>(F.rc);
+  const bool rc = F.rc != nullptr;
   const int N2 = N / 2;
   T v[E];
   if (F.kind != 1) {
-    // full level (child region from rc when set) or level with the child
-    // region zeroed (kind 2)
+    // full level (child region restricted when rc is set) or level with the
+    // child region zeroed (kind 2)
     const int lo = N / 4, hi = 3 * N / 4;
     const bool yz_in = z >= lo && z < hi && y >= lo && y < hi;
     const bool use_rc = F.kind == 0 && rc && yz_in;
     const bool zero_c = F.kind == 2 && yz_in;
     const size_t row = ((size_t)z * N + y) * N;
-    const size_t rrow = use_rc ? ((size_t)(z - lo) * N2 + (y - lo)) * N2 : 0;
+    // the level's own values first, all loads at once (a valid cell stands
+    // in where the value is dropped), then the restricted child region
+    R own[E / 2];
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int x = t + TL * q;
-      R val = 0;
-      if (active && (FULLN || x < N)) {
-        const bool cen = x >= lo && x < hi;
-        if (!(zero_c && cen)) val = (use_rc && cen) ? rc[rrow + (x - lo)] : rho[row + x];
-      }
+      own[q] = rho[row + ((FULLN || x < N) ? x : 0)];
+    }
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) {
+      const int x = t + TL * q;
+      const bool cen = x >= lo && x < hi;
+      R val = (active && (FULLN || x < N) && !(zero_c && cen)) ? own[q] : (R)0;
+      if (active && use_rc && cen) val = restricted_at<R>(F, N, z - lo, y - lo, x - lo);
       v[q] = T{val, 0};
     }
   } else {
@@ -117,18 +187,17 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
     // is box cells [1, N/2 + 1) per axis
     const bool yz_in = active && z >= 1 && z <= N2 && y >= 1 && y <= N2;
     const int off = N / 4 - 1;
-    const size_t row = !yz_in ? 0
-                       : rc ? ((size_t)(z - 1) * N2 + (y - 1)) * N2
-                            : ((size_t)(z + off) * N + (y + off)) * N + off + 1;
-    const R* src = rc ? rc : rho;
+    const size_t row = yz_in ? ((size_t)(z + off) * N + (y + off)) * N + off + 1 : 0;
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int x = t + TL * q;
-      const R val = (yz_in && x >= 1 && x <= N2) ? src[row + (x - 1)] : (R)0;
+      R val = 0;
+      if (yz_in && x >= 1 && x <= N2) val = rc ? restricted_at<R>(F, N, z - 1, y - 1, x - 1) : rho[row + (x - 1)];
       v[q] = T{val, 0};
     }
   }
   LdsView<R> lds{sre, sim, 1, P, w};
+  tws.put(stw);
   fft_line<R, P, -1, true, false>(v, t, lds, stw);
   if (active) {
     T* A = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
@@ -152,10 +221,10 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   constexpr int E = C::E, TL = C::TL, W = C::WS, NT = (P / 2) / W;
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
-  stage_twiddles<R, P>(stw, tb.tw);
+  const TwStage<R, P, C::WS * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const bool full = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks
-  const int n = grid_geo(F.kind, g.N).nin;
+  const int n = grid_geo(F.kind, FULLN ? P / 2 : g.N).nin;
   const int tile = blockIdx.x % NT, z = blockIdx.x / NT;
   if (z >= n) return;  // uniform: a smaller grid of a mixed launch
   const int w = threadIdx.x % W, t = threadIdx.x / W;
@@ -166,9 +235,12 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int yy = t + TL * q;
-    v[q] = (full || yy < n) ? A[(size_t)yy * (P / 2)] : T{0, 0};
+    const bool in = full || yy < n;
+    const T a = A[(size_t)(in ? yy : 0) * (P / 2)];  // branch-free: a valid row, value dropped
+    v[q] = in ? a : T{0, 0};
   }
   LdsView<R> lds{sre, sim, W, 1, w};
+  tws.put(stw);
   fft_line<R, P, -1, true, false>(v, t, lds, stw);
 #pragma unroll
   for (int q = 0; q < E; ++q) B[(size_t)(t + TL * q) * (P / 2)] = v[q];
@@ -188,11 +260,11 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   constexpr int E = C::E, TL = C::TL, W = C::WZ, NT = (P / 2) / W, H = P / 2 + 1;
   __shared__ R sre[2 * W * P], sim[2 * W * P];
   __shared__ cplx<R> stw[P];
-  stage_twiddles<R, P>(stw, tb.tw);
+  const TwStage<R, P, 2 * C::WZ * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const bool full_in = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks on loads
   const bool full = FULLN && F.kind == 0;     // nout = N = P/2 as well
-  const GridGeo gg = grid_geo(F.kind, g.N);
+  const GridGeo gg = grid_geo(F.kind, FULLN ? P / 2 : g.N);
   const int n = gg.nin;
   const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
   const int tile = blockIdx.x % NT, p = blockIdx.x / NT;
@@ -201,23 +273,41 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int kyp = ky <= P / 2 ? ky : P - ky;
   T* B = static_cast<T*>(F.B) + (size_t)ky * (P / 2) + kx;  // row z at + z * P * (P/2)
   constexpr size_t ZS = (size_t)P * (P / 2);
+  // rows z >= n are zero (no load)
   T v[E];
+  if (full_in) {
 #pragma unroll
-  for (int q = 0; q < E / 2; ++q) {
-    const int zz = t + TL * q;
-    v[q] = (full_in || zz < n) ? B[zz * ZS] : T{0, 0};
+    for (int q = 0; q < E / 2; ++q) v[q] = B[(size_t)(t + TL * q) * ZS];
+  } else {
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) {
+      const int zz = t + TL * q;
+      v[q] = zz < n ? B[(size_t)zz * ZS] : T{0, 0};
+    }
   }
-  // spectrum values of this thread's points, fetched with the data (the
-  // spectrum is even in kz, so kz and P - kz share a value)
+  // spectrum values of this thread's points (the spectrum is even in kz:
+  // kz = t + TL q reads row kz for q < E/2 and row P - kz = P/2 - t - TL (q - E/2)
+  // above)
   const R* gcol = tb.gz + (size_t)(kyp * NT + tile) * H * W + w;
+  const R* glo = gcol + t * W;
+  const R* ghi = gcol + (P / 2 - t) * W;
+  // FP32: fetched after the forward transform, so that they hold no
+  // registers during it (the earlier fetch cost a resident workgroup);
+  // FP64: fetched with the data (measured faster)
+  constexpr bool late = sizeof(R) == 4;
   R ga[E];
+  auto fetch_spectrum = [&]() {
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int kz = t + TL * q;
-    ga[q] = gcol[(kz <= P / 2 ? kz : P - kz) * W];
-  }
+    for (int q = 0; q < E / 2; ++q) {
+      ga[q] = glo[TL * q * W];
+      ga[q + E / 2] = ghi[-TL * q * W];
+    }
+  };
+  if constexpr (!late) fetch_spectrum();
   LdsView<R> lds{sre, sim, 2 * W, 1, w + W * side};
+  tws.put(stw);
   fft_line<R, P, -1, true, false>(v, t, lds, stw);
+  if constexpr (late) fetch_spectrum();
 
   const R sc = (R)F.scale;
   bool plain = true;
@@ -274,10 +364,10 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   constexpr int E = C::E, TL = C::TL, W = C::WS, NT = (P / 2) / W;
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
-  stage_twiddles<R, P>(stw, tb.tw);
+  const TwStage<R, P, C::WS * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const bool full = FULLN && F.kind == 0;  // nout = N = P/2: no bound checks
-  const GridGeo gg = grid_geo(F.kind, g.N);
+  const GridGeo gg = grid_geo(F.kind, FULLN ? P / 2 : g.N);
   const int r = blockIdx.x / NT;
   if (r >= gg.nout) return;  // uniform: a smaller grid of a mixed launch
   const int z = gg.olo + r;
@@ -289,6 +379,7 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = B[(size_t)(t + TL * q) * (P / 2)];
   LdsView<R> lds{sre, sim, W, 1, w};
+  tws.put(stw);
   fft_line<R, P, +1, false, true>(v, t, lds, stw);
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
@@ -319,7 +410,7 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   constexpr int E = C::E, TL = C::TL, W = C::WC;
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
-  stage_twiddles<R, P>(stw, tb.tw);
+  const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = g.N;
   const GridGeo gg = grid_geo(F.kind, N);
@@ -331,20 +422,23 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int zr = active ? line / n : 0, yr = active ? line % n : 0;  // within the output box
   const int z = gg.olo + zr, y = gg.olo + yr;
   const T* row = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
+  // Hermitian extension of the packed half spectrum; every load is issued
+  // without a branch (inactive lines read row 0 and drop it)
   T v[E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int k = t + TL * q;
-    T c = T{0, 0};
-    if (active) {
-      if (k == 0) c = T{row[0].x, 0};
-      else if (k < P / 2) c = row[k];
-      else if (k == P / 2) c = T{row[0].y, 0};
-      else { const T m = row[P - k]; c = T{m.x, -m.y}; }
-    }
-    v[q] = c;
+  for (int q = 0; q < E / 2; ++q) {
+    const int k = t + TL * q;  // < P/2; k = 0 holds the real DC value in .x
+    const T m = row[k];
+    v[q] = !active ? T{0, 0} : (k == 0 ? T{m.x, 0} : m);
+  }
+#pragma unroll
+  for (int q = E / 2; q < E; ++q) {
+    const int kk = P - (t + TL * q);  // in (0, P/2]; P/2 is the Nyquist value in row[0].y
+    const T m = row[kk == P / 2 ? 0 : kk];
+    v[q] = !active ? T{0, 0} : (kk == P / 2 ? T{m.y, 0} : T{m.x, -m.y});
   }
   LdsView<R> lds{sre, sim, 1, P, w};
+  tws.put(stw);
   fft_line<R, P, +1, false, true>(v, t, lds, stw);
   if (!active) return;
   R* out = static_cast<R*>(F.out);
@@ -435,38 +529,151 @@ __global__ void k_restrict(const R* __restrict__ fine, const R* __restrict__ fin
   rc[id] = s * (R)0.125;
 }
 
-// Carry cascade on the stencil box [N/4-1, 3N/4]^3 (NS = N/2+2 cells):
-// S_n = Prolong(S_{n-1}) + Phi^n_hole, the 3/4-1/4 diagonal rule of Eqs. 3-6.
+// Block-mean pyramids (the unrolled restriction, kernels.h).  A workgroup
+// owns an aligned cube of S = pyramid_cube(N, k) cells per axis of one
+// level k >= 1:
+// it forms the 2x2x2 means of m_k (the density with the level's child region
+// zeroed, except on the finest level), then the means of those means, up to
+// blocks of 2^k cells, writing every size to the level's slab.
 template <class R>
-__global__ void k_carry(const R* __restrict__ s_hi, const R* __restrict__ s_lo,
-                        const R* __restrict__ hole, R* __restrict__ o_hi, R* __restrict__ o_lo,
-                        int N, int compensated) {
-  const int NS = N / 2 + 2, lo = N / 4 - 1;
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= NS * NS * NS) return;
-  const int x = lo + id % NS, y = lo + (id / NS) % NS, z = lo + id / (NS * NS);
-  const int iz = z / 2 + 1, iy = y / 2 + 1, ix = x / 2 + 1;
-  const int jz = iz + ((z & 1) ? 1 : -1), jy = iy + ((y & 1) ? 1 : -1), jx = ix + ((x & 1) ? 1 : -1);
-  const size_t in = ((size_t)iz * NS + iy) * NS + ix, jn = ((size_t)jz * NS + jy) * NS + jx;
-  const R a = s_hi[in], b = s_hi[jn], h = hole[id];
-  if (sizeof(R) == 8 || !compensated) {
-    o_hi[id] = ((R)0.75 * a + (R)0.25 * b) + h;
-    if (o_lo) o_lo[id] = 0;
+__global__ void __launch_bounds__(256) k_pyramid(PyramidTable tab, int N, int maxL) {
+  const PyramidDesc& D = tab.r[blockIdx.y];
+  int b = blockIdx.x, k = 1, S = 0, nc = 0;
+  for (; k < maxL; ++k) {
+    S = pyramid_cube(N, k);
+    nc = N / S;
+    if (b < nc * nc * nc) break;
+    b -= nc * nc * nc;
+  }
+  if (k >= D.L) return;  // uniform: a request with fewer levels
+  const R* rho = static_cast<const R*>(D.rho) + (size_t)k * N * N * N;
+  R* pyr = static_cast<R*>(D.pyr) + (size_t)(k - 1) * D.slab;
+  const int ox = (b % nc) * S, oy = (b / nc % nc) * S, oz = b / (nc * nc) * S;
+  const bool mask = k < D.L - 1;
+  const int lo = N / 4, hi = 3 * N / 4;
+  constexpr int S0 = 1 << kMaxPyramidDepth;
+  __shared__ R buf[(S0 / 2) * (S0 / 2) * (S0 / 2) + (S0 / 4) * (S0 / 4) * (S0 / 4)];
+  R* src = buf;
+  R* dst = buf + (S0 / 2) * (S0 / 2) * (S0 / 2);
+  int e = S / 2;  // blocks per axis of the cube at the current size
+  {
+    const int nd = N >> 1;
+    for (int j = threadIdx.x; j < e * e * e; j += blockDim.x) {
+      const int gx = ox + 2 * (j % e), gy = oy + 2 * (j / e % e), gz = oz + 2 * (j / (e * e));
+      R s = 0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int zz = gz + a, yy = gy + c;
+          const bool yz_in = mask && zz >= lo && zz < hi && yy >= lo && yy < hi;
+          const R* row = rho + ((size_t)zz * N + yy) * N;
+#pragma unroll
+          for (int x = 0; x < 2; ++x) {
+            const int xx = gx + x;
+            if (!(yz_in && xx >= lo && xx < hi)) s += row[xx];
+          }
+        }
+      const R m = s * (R)0.125;
+      pyr[((size_t)(gz >> 1) * nd + (gy >> 1)) * nd + (gx >> 1)] = m;
+      if (k >= 2) src[j] = m;
+    }
+  }
+  size_t off = (size_t)(N >> 1) * (N >> 1) * (N >> 1);
+  for (int d = 2; d <= k; ++d) {
+    __syncthreads();
+    const int e2 = e / 2, nd = N >> d;
+    for (int j = threadIdx.x; j < e2 * e2 * e2; j += blockDim.x) {
+      const int sx = j % e2, sy = j / e2 % e2, sz = j / (e2 * e2);
+      R s = 0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int x = 0; x < 2; ++x) s += src[((2 * sz + a) * e + 2 * sy + c) * e + 2 * sx + x];
+      const R m = s * (R)0.125;
+      pyr[off + ((size_t)((oz >> d) + sz) * nd + (oy >> d) + sy) * nd + (ox >> d) + sx] = m;
+      dst[j] = m;
+    }
+    R* t = src;
+    src = dst;
+    dst = t;
+    e = e2;
+    off += (size_t)nd * nd * nd;
+  }
+}
+
+// One step of the carry cascade, S = (3/4 A + 1/4 B) + Phi_hole (the diagonal
+// rule of Eqs. 3-6); with comp, (hi, lo) pairs carry the rounding error of
+// every operation (TwoSum, and an FMA for the product by 3/4).
+template <class R>
+__device__ __forceinline__ void carry_step(R ahi, R alo, R bhi, R blo, R h, bool comp, R& hi, R& lo) {
+  if (sizeof(R) == 8 || !comp) {
+    hi = ((R)0.75 * ahi + (R)0.25 * bhi) + h;
+    lo = 0;
   } else {
-    const R p1 = (R)0.75 * a;
-    const R e1 = fma((R)0.75, a, -p1);
-    const R p2 = (R)0.25 * b;
+    const R p1 = (R)0.75 * ahi;
+    const R e1 = fma((R)0.75, ahi, -p1);
     R s, e2;
-    two_sum(p1, p2, s, e2);
+    two_sum(p1, (R)0.25 * bhi, s, e2);
     R l = e1 + e2;
-    if (s_lo) l += (R)0.75 * s_lo[in] + (R)0.25 * s_lo[jn];
+    l += (R)0.75 * alo + (R)0.25 * blo;
     R s2, e3;
     two_sum(s, h, s2, e3);
     l += e3;
-    const R hi2 = s2 + l;  // renormalise
-    o_hi[id] = hi2;
-    o_lo[id] = l - (hi2 - s2);
+    hi = s2 + l;  // renormalise
+    lo = l - (hi - s2);
   }
+}
+
+// S_n at box cell (bz, by, bx), unrolling the cascade down to S_base.  Box
+// cell b is level cell b + N/4 - 1; a fine cell f takes its parent
+// f/2 + 1 (box coordinates of the coarser level) and the diagonal neighbour
+// one further in every axis, towards f's side of the parent.
+template <class R, int D>
+__device__ __forceinline__ void carry_tree(const CarryDesc& C, int N, int n, int base, int bz, int by,
+                                           int bx, R& hi, R& lo) {
+  const int NB = N / 2 + 2;
+  const size_t id = ((size_t)bz * NB + by) * NB + bx;
+  if constexpr (D > 0) {
+    if (n > base) {
+      const int off = N / 4 - 1;
+      const int z = bz + off, y = by + off, x = bx + off;
+      const int iz = z / 2 + 1, iy = y / 2 + 1, ix = x / 2 + 1;
+      R ahi, alo, bhi, blo;
+      carry_tree<R, D - 1>(C, N, n - 1, base, iz, iy, ix, ahi, alo);
+      carry_tree<R, D - 1>(C, N, n - 1, base, iz + ((z & 1) ? 1 : -1), iy + ((y & 1) ? 1 : -1),
+                           ix + ((x & 1) ? 1 : -1), bhi, blo);
+      const R h = static_cast<const R*>(C.hole)[(size_t)n * C.box + id];
+      carry_step(ahi, alo, bhi, blo, h, C.comp != 0, hi, lo);
+      return;
+    }
+  }
+  if (base == 0) {  // S_0 is the hole potential of level 0
+    hi = static_cast<const R*>(C.hole)[id];
+    lo = 0;
+  } else {
+    const R* S = static_cast<const R*>(C.S) + (size_t)base * 2 * C.box;
+    hi = S[id];
+    lo = C.comp ? S[C.box + id] : (R)0;
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_carry(CarryTable tab, int N, int n0) {
+  const int NB = N / 2 + 2, nb3 = NB * NB * NB, per = (nb3 + 255) / 256;
+  const int r = blockIdx.y, lv = blockIdx.x / per;
+  if (lv >= tab.nlev[r]) return;  // uniform: a request with fewer levels
+  const int id = (blockIdx.x % per) * 256 + threadIdx.x;
+  if (id >= nb3) return;
+  const CarryDesc& C = tab.r[r];
+  const int n = n0 + lv;
+  R hi, lo;
+  carry_tree<R, kMaxCarryDepth>(C, N, n, n0 - 1, id / (NB * NB), id / NB % NB, id % NB, hi, lo);
+  R* S = static_cast<R*>(C.S) + (size_t)n * 2 * C.box;
+  S[id] = hi;
+  if (C.comp) S[C.box + id] = lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -654,11 +861,23 @@ hipError_t launch_restrict(const R* fine, const R* fine_rc, R* rc, int N, hipStr
 }
 
 template <class R>
-hipError_t launch_carry(const R* s_hi, const R* s_lo, const R* hole, R* o_hi, R* o_lo, int N,
-                        int compensated, hipStream_t s) {
-  const int NS = N / 2 + 2, n = NS * NS * NS;
-  hipLaunchKernelGGL(k_carry<R>, dim3((n + 255) / 256), dim3(256), 0, s, s_hi, s_lo, hole, o_hi,
-                     o_lo, N, compensated);
+hipError_t launch_pyramid(const PyramidTable& tab, int count, int N, int maxL, hipStream_t s) {
+  int blocks = 0;
+  for (int k = 1; k < maxL; ++k) {
+    const int S = pyramid_cube(N, k), nc = N / S;
+    blocks += nc * nc * nc;
+  }
+  hipLaunchKernelGGL(k_pyramid<R>, dim3(blocks, count), dim3(256), 0, s, tab, N, maxL);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_carry(const CarryTable& tab, int count, int N, int n0, hipStream_t s) {
+  const int NB = N / 2 + 2, per = (NB * NB * NB + 255) / 256;
+  int nl = 0;
+  for (int i = 0; i < count; ++i) nl = std::max(nl, tab.nlev[i]);
+  if (nl <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_carry<R>, dim3(per * nl, count), dim3(256), 0, s, tab, N, n0);
   return hipGetLastError();
 }
 
@@ -725,7 +944,8 @@ hipError_t launch_fft_lines(const void* in, void* out, int P, int nlines, int di
   template hipError_t launch_inv_y<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
   template hipError_t launch_inv_x<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
   template hipError_t launch_restrict<R>(const R*, const R*, R*, int, hipStream_t);               \
-  template hipError_t launch_carry<R>(const R*, const R*, const R*, R*, R*, int, int, hipStream_t); \
+  template hipError_t launch_pyramid<R>(const PyramidTable&, int, int, int, hipStream_t);          \
+  template hipError_t launch_carry<R>(const CarryTable&, int, int, int, hipStream_t);              \
   template hipError_t launch_fft_lines<R>(const void*, void*, int, int, int, const void*, hipStream_t); \
   template hipError_t launch_green_layout<R>(int, const double*, R*, R*, hipStream_t);                 \
   template size_t green_layout_elems<R>(int);

@@ -52,8 +52,10 @@ bool use_boxes(int N) { return N >= 128; }
 
 // Workspace layout of one request (offsets from its base): per level l the
 // full grid's A and B; per level l < L-1 the second grid (hole grid or
-// child-region box), the restricted density Rc, the box potential (hole
-// potential or C) and the carried potential S (hi, and lo for the FP32 path).
+// child-region box), the restriction data Rc (the block-mean pyramid of level
+// l+1, or the cascaded restriction in its first (N/2)^3 values), the box
+// potential (hole potential or C) and the carried potential S (hi, and lo for
+// the FP32 path).
 struct Layout {
   int N, L, P, NC;
   bool boxes;
@@ -86,7 +88,7 @@ Layout make_layout(int N, int L, nmc_precision p) {
   lo.b_full = align_up((size_t)N * P * (P / 2) * lo.c);
   lo.a_sec = align_up(ns * ns * (P / 2) * lo.c);
   lo.b_sec = align_up(ns * P * (P / 2) * lo.c);
-  lo.rc_bytes = align_up((size_t)(N / 2) * (N / 2) * (N / 2) * lo.r);
+  lo.rc_bytes = align_up((size_t)nmc::pyramid_slab(N, L) * lo.r);
   lo.box_bytes = align_up(NC * NC * NC * lo.r);
   lo.total = lo.Shi(0) + (size_t)(L - 1) * 2 * lo.box_bytes;
   lo.total = std::max(lo.total, kAlign);
@@ -442,13 +444,11 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     const R* fine_rc;
     R* out;
   };
-  std::vector<RestrictStep> restricts;
-  struct CarryStep {
-    const R *shi, *slo, *hole;
-    R *ohi, *olo;
-    int comp;
-  };
-  std::vector<CarryStep> carries;
+  std::vector<RestrictStep> restricts;  // cascaded restriction (N not a multiple of 2^L)
+  std::vector<nmc::PyramidDesc> pyramids;
+  int pyr_maxL = 0;
+  std::vector<nmc::CarryDesc> carries;  // hole pipeline: S_n, n = 1 .. L-2
+  std::vector<int> carry_levels;
   int maxL = 0;
   size_t off = 0;
   for (int i = 0; i < count; ++i) {
@@ -461,11 +461,22 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     R* phi = (R*)q.phi;
     const bool restrict_on = !(q.flags & NMC_NO_RESTRICT);
     const bool comp = sizeof(R) == 4 && !(q.flags & NMC_F32_UNCOMPENSATED);
-    if (restrict_on) {
-      for (int l = q.L - 2; l >= 0; --l) {
-        const R* fine_rc = (l + 1 <= q.L - 2) ? (const R*)(base + lo.Rc(l + 1)) : nullptr;
-        restricts.push_back({rho + (size_t)(l + 1) * lvl, fine_rc, (R*)(base + lo.Rc(l))});
+    const bool pyramid = nmc::pyramid_exact(N, q.L);
+    const long long rslab = (long long)(lo.rc_bytes / sizeof(R));
+    if (restrict_on && q.L >= 2) {
+      if (pyramid) {
+        pyramids.push_back({rho, base + lo.Rc(0), rslab, q.L});
+        pyr_maxL = std::max(pyr_maxL, q.L);
+      } else {
+        for (int l = q.L - 2; l >= 0; --l) {
+          const R* fine_rc = (l + 1 <= q.L - 2) ? (const R*)(base + lo.Rc(l + 1)) : nullptr;
+          restricts.push_back({rho + (size_t)(l + 1) * lvl, fine_rc, (R*)(base + lo.Rc(l))});
+        }
       }
+    }
+    if (!boxes && q.L >= 3) {
+      carries.push_back({base + lo.Box(0), base + lo.Shi(0), (long long)(lo.box_bytes / sizeof(R)), comp ? 1 : 0});
+      carry_levels.push_back(q.L - 2);
     }
     const double P3 = (double)P * P * P;
     for (int l = 0; l < q.L; ++l) {
@@ -474,6 +485,8 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
       FieldDesc f{};
       f.rho = rho + (size_t)l * lvl;
       f.rc = (restrict_on && finer) ? (const void*)(base + lo.Rc(l)) : nullptr;
+      f.rslab = rslab;
+      f.rdepth = pyramid ? q.L - 1 - l : 1;
       f.A = base + lo.A(l);
       f.B = base + lo.B(l);
       f.out = phi + (size_t)l * lvl;
@@ -496,6 +509,8 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
         FieldDesc c{};
         c.rho = f.rho;
         c.rc = boxes ? f.rc : nullptr;
+        c.rslab = f.rslab;
+        c.rdepth = f.rdepth;
         c.A = base + lo.As(l);
         c.B = base + lo.Bs(l);
         c.out = base + lo.Box(l);
@@ -503,12 +518,6 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
         c.kind = boxes ? 1 : 2;
         c.comp = f.comp;
         secs.push_back(c);
-      }
-      if (!boxes && l >= 1 && finer) {  // S_l = Prolong(S_{l-1}) + Phi^l_hole
-        carries.push_back({(const R*)(base + (l == 1 ? lo.Box(0) : lo.Shi(l - 1))),
-                           (l == 1 || !comp) ? nullptr : (const R*)(base + lo.Slo(l - 1)),
-                           (const R*)(base + lo.Box(l)), (R*)(base + lo.Shi(l)),
-                           comp ? (R*)(base + lo.Slo(l)) : nullptr, comp ? 1 : 0});
       }
     }
   }
@@ -538,6 +547,17 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   };
   auto restrict_cascade = [&](hipStream_t st) -> int {
     const double nn = (double)N * N * N;
+    for (size_t a = 0; a < pyramids.size(); a += nmc::kMaxPyramidsPerLaunch) {
+      nmc::PyramidTable tab{};
+      const int cnt = (int)std::min<size_t>(nmc::kMaxPyramidsPerLaunch, pyramids.size() - a);
+      double bytes = 0;
+      for (int k = 0; k < cnt; ++k) {
+        tab.r[k] = pyramids[a + k];
+        bytes += (double)(tab.r[k].L - 1) * (nn + (double)nmc::pyramid_slab(N, tab.r[k].L)) * sizeof(R);
+      }
+      ProfScope ps(ctx, st, NMC_PASS_RESTRICT, bytes);
+      NMC_HIP(ctx, nmc::launch_pyramid<R>(tab, cnt, N, pyr_maxL, st));
+    }
     for (const auto& r : restricts) {
       ProfScope ps(ctx, st, NMC_PASS_RESTRICT, (nn + nn / 8) * sizeof(R));
       NMC_HIP(ctx, nmc::launch_restrict<R>(r.fine, r.fine_rc, r.out, N, st));
@@ -546,9 +566,24 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   };
   auto carry_cascade = [&](hipStream_t st) -> int {
     const double ns3 = std::pow((double)NC, 3);
-    for (const auto& c : carries) {
-      ProfScope ps(ctx, st, NMC_PASS_CARRY, ns3 * sizeof(R) * (c.comp ? 6 : 3));
-      NMC_HIP(ctx, nmc::launch_carry<R>(c.shi, c.slo, c.hole, c.ohi, c.olo, N, c.comp, st));
+    for (size_t a = 0; a < carries.size(); a += nmc::kMaxCarriesPerLaunch) {
+      const int cnt = (int)std::min<size_t>(nmc::kMaxCarriesPerLaunch, carries.size() - a);
+      for (int n0 = 1;; n0 += nmc::kMaxCarryDepth) {
+        nmc::CarryTable tab{};
+        int any = 0;
+        double bytes = 0;
+        for (int k = 0; k < cnt; ++k) {
+          tab.r[k] = carries[a + k];
+          const int left = carry_levels[a + k] - (n0 - 1);
+          tab.nlev[k] = std::max(0, std::min(nmc::kMaxCarryDepth, left));
+          any += tab.nlev[k];
+          // per level: the hole potential read, S written (hi, lo)
+          bytes += tab.nlev[k] * ns3 * sizeof(R) * (tab.r[k].comp ? 3 : 2);
+        }
+        if (!any) break;
+        ProfScope ps(ctx, st, NMC_PASS_CARRY, bytes);
+        NMC_HIP(ctx, nmc::launch_carry<R>(tab, cnt, N, n0, st));
+      }
     }
     return NMC_OK;
   };

@@ -73,14 +73,45 @@ def test_green_spectrum_matches_oracle(ctx, N):
 
 # --- single and nested solves, FP64 -----------------------------------------
 
-@pytest.mark.parametrize("N,L", [(4, 1), (4, 2), (4, 3), (8, 1), (8, 3), (12, 1), (12, 2),
-                                 (16, 3), (20, 2), (32, 4)])
+# (N, L) with N a multiple of 2^L take the block-mean pyramid restriction,
+# the others the cascaded one; L >= 7 below N = 128 needs two carry launches.
+@pytest.mark.parametrize("N,L", [(4, 1), (4, 2), (4, 3), (8, 1), (8, 3), (8, 4), (12, 1), (12, 2),
+                                 (16, 3), (16, 5), (16, 7), (20, 2), (32, 4), (32, 5)])
 def test_random_levels_fp64(ctx, N, L):
     w = inputs.random_levels(N, L, seed=100 + N + L)
     rho = w.rho.numpy()
     ref = oracle.solve(rho, w.h0, G=1.3)
     got = run(ctx, rho, w.h0, G=1.3)
     assert np.max(rel_err(got, ref)) < F64_TOL
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_restriction_modes_in_one_batch(ctx, dtype):
+    """One group mixing pyramid (L = 3, 4) and cascaded (L = 5, 6)
+    restrictions and one or two carry launches: each request matches the
+    oracle and its own solve alone."""
+    items, refs = [], []
+    for i, L in enumerate((3, 5, 4, 6)):
+        w = inputs.random_levels(16, L, seed=300 + i)
+        items.append((w.rho.to("cuda", dtype), w.h0, 1.0 + 0.1 * i))
+        refs.append(oracle.solve(w.rho.numpy(), w.h0, G=1.0 + 0.1 * i))
+    alone = [ctx.solve(r, h, G).clone() for r, h, G in items]
+    batch = ctx.solve_batch(items)
+    torch.cuda.synchronize()
+    tol = F64_TOL if dtype == torch.float64 else F32_TOL
+    for a, b, ref in zip(alone, batch, refs):
+        assert torch.equal(a, b)
+        assert np.max(rel_err(b.double().cpu().numpy(), ref)) < tol
+
+
+def test_deep_hierarchy_fp32(ctx):
+    """Seven levels of 32^3 in FP32: cascaded restriction and a carry
+    cascade split over two launches, with compensated sums."""
+    w = inputs.random_levels(32, 7, seed=17)
+    rho = w.rho.numpy()
+    ref = oracle.solve(rho, w.h0)
+    got = run(ctx, rho, w.h0, dtype=torch.float32)
+    assert np.max(rel_err(got, ref)) < F32_TOL
 
 
 def test_random12_brute_force(ctx):
