@@ -133,6 +133,7 @@ template <class R>
 hipError_t launch_pyramid(const PyramidTable&, int count, int N, int maxL, hipStream_t);
 // S_n for n = n0 .. n0 + nlev - 1 (nlev <= kMaxCarryDepth), each from S_{n0-1}
 // (S_0 = Phi^0_hole when n0 = 1) by unrolling the cascade, in one launch.
+// Every request of the table has the same comp.
 template <class R>
 hipError_t launch_carry(const CarryTable&, int count, int N, int n0, hipStream_t);
 

@@ -531,12 +531,15 @@ __global__ void k_restrict(const R* __restrict__ fine, const R* __restrict__ fin
 
 // Block-mean pyramids (the unrolled restriction, kernels.h).  A workgroup
 // owns an aligned cube of S = pyramid_cube(N, k) cells per axis of one
-// level k >= 1:
-// it forms the 2x2x2 means of m_k (the density with the level's child region
-// zeroed, except on the finest level), then the means of those means, up to
-// blocks of 2^k cells, writing every size to the level's slab.
+// level k >= 1: every thread forms the 2x2x2 means of m_k (the density with
+// the level's child region zeroed, except on the finest level) of its
+// sub-blocks, all loads issued together, then the means of those means up
+// to blocks of 2^k cells are formed in LDS, every size written to the
+// level's slab.
+constexpr int kPyramidThreads = 512;
 template <class R>
-__global__ void __launch_bounds__(256) k_pyramid(PyramidTable tab, int N, int maxL) {
+__global__ void __launch_bounds__(kPyramidThreads) k_pyramid(PyramidTable tab, int N, int maxL) {
+  using T2 = cplx<R>;
   const PyramidDesc& D = tab.r[blockIdx.y];
   int b = blockIdx.x, k = 1, S = 0, nc = 0;
   for (; k < maxL; ++k) {
@@ -552,28 +555,40 @@ __global__ void __launch_bounds__(256) k_pyramid(PyramidTable tab, int N, int ma
   const bool mask = k < D.L - 1;
   const int lo = N / 4, hi = 3 * N / 4;
   constexpr int S0 = 1 << kMaxPyramidDepth;
-  __shared__ R buf[(S0 / 2) * (S0 / 2) * (S0 / 2) + (S0 / 4) * (S0 / 4) * (S0 / 4)];
+  constexpr int NSUB = (S0 / 2) * (S0 / 2) * (S0 / 2);
+  constexpr int IT = NSUB / kPyramidThreads;  // sub-blocks per thread at the largest cube
+  __shared__ R buf[NSUB + (S0 / 4) * (S0 / 4) * (S0 / 4)];
   R* src = buf;
-  R* dst = buf + (S0 / 2) * (S0 / 2) * (S0 / 2);
+  R* dst = buf + NSUB;
   int e = S / 2;  // blocks per axis of the cube at the current size
+  const int ne = e * e * e;
   {
+    // x pairs (even x) as one vector load; a masked cell or a thread past
+    // the cube reads a valid pair and drops it
+    T2 val[IT][4];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      if (it * kPyramidThreads >= ne) break;  // uniform
+      const int j = min((int)threadIdx.x + it * kPyramidThreads, ne - 1);
+      const int gx = ox + 2 * (j % e), gy = oy + 2 * (j / e % e), gz = oz + 2 * (j / (e * e));
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        val[it][a] = *reinterpret_cast<const T2*>(rho + ((size_t)(gz + (a >> 1)) * N + gy + (a & 1)) * N + gx);
+    }
     const int nd = N >> 1;
-    for (int j = threadIdx.x; j < e * e * e; j += blockDim.x) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int j = (int)threadIdx.x + it * kPyramidThreads;
+      if (j >= ne) break;
       const int gx = ox + 2 * (j % e), gy = oy + 2 * (j / e % e), gz = oz + 2 * (j / (e * e));
       R s = 0;
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int zz = gz + a, yy = gy + c;
-          const bool yz_in = mask && zz >= lo && zz < hi && yy >= lo && yy < hi;
-          const R* row = rho + ((size_t)zz * N + yy) * N;
-#pragma unroll
-          for (int x = 0; x < 2; ++x) {
-            const int xx = gx + x;
-            if (!(yz_in && xx >= lo && xx < hi)) s += row[xx];
-          }
-        }
+      for (int a = 0; a < 4; ++a) {
+        const int zz = gz + (a >> 1), yy = gy + (a & 1);
+        const bool yz_in = mask && zz >= lo && zz < hi && yy >= lo && yy < hi;
+        if (!(yz_in && gx >= lo && gx < hi)) s += val[it][a].x;
+        if (!(yz_in && gx + 1 >= lo && gx + 1 < hi)) s += val[it][a].y;
+      }
       const R m = s * (R)0.125;
       pyr[((size_t)(gz >> 1) * nd + (gy >> 1)) * nd + (gx >> 1)] = m;
       if (k >= 2) src[j] = m;
@@ -607,9 +622,9 @@ __global__ void __launch_bounds__(256) k_pyramid(PyramidTable tab, int N, int ma
 // One step of the carry cascade, S = (3/4 A + 1/4 B) + Phi_hole (the diagonal
 // rule of Eqs. 3-6); with comp, (hi, lo) pairs carry the rounding error of
 // every operation (TwoSum, and an FMA for the product by 3/4).
-template <class R>
-__device__ __forceinline__ void carry_step(R ahi, R alo, R bhi, R blo, R h, bool comp, R& hi, R& lo) {
-  if (sizeof(R) == 8 || !comp) {
+template <class R, bool COMP>
+__device__ __forceinline__ void carry_step(R ahi, R alo, R bhi, R blo, R h, R& hi, R& lo) {
+  if constexpr (sizeof(R) == 8 || !COMP) {
     hi = ((R)0.75 * ahi + (R)0.25 * bhi) + h;
     lo = 0;
   } else {
@@ -627,40 +642,36 @@ __device__ __forceinline__ void carry_step(R ahi, R alo, R bhi, R blo, R h, bool
   }
 }
 
-// S_n at box cell (bz, by, bx), unrolling the cascade down to S_base.  Box
-// cell b is level cell b + N/4 - 1; a fine cell f takes its parent
-// f/2 + 1 (box coordinates of the coarser level) and the diagonal neighbour
-// one further in every axis, towards f's side of the parent.
-template <class R, int D>
-__device__ __forceinline__ void carry_tree(const CarryDesc& C, int N, int n, int base, int bz, int by,
-                                           int bx, R& hi, R& lo) {
+// S_n at box cell (bz, by, bx), unrolling D steps of the cascade down to
+// S_{n-D}, read from (lhi, llo) (llo null: no compensation term).  Box cell
+// b is level cell b + N/4 - 1; a fine cell f takes its parent f/2 + 1 (box
+// coordinates of the coarser level) and the diagonal neighbour one further
+// in every axis, towards f's side of the parent.  D is a compile-time depth
+// so that every load of the tree is issued before the first is used.
+template <class R, bool COMP, int D>
+__device__ __forceinline__ void carry_tree(const CarryDesc& C, int N, int n, const R* lhi, const R* llo,
+                                           int bz, int by, int bx, R& hi, R& lo) {
   const int NB = N / 2 + 2;
   const size_t id = ((size_t)bz * NB + by) * NB + bx;
-  if constexpr (D > 0) {
-    if (n > base) {
-      const int off = N / 4 - 1;
-      const int z = bz + off, y = by + off, x = bx + off;
-      const int iz = z / 2 + 1, iy = y / 2 + 1, ix = x / 2 + 1;
-      R ahi, alo, bhi, blo;
-      carry_tree<R, D - 1>(C, N, n - 1, base, iz, iy, ix, ahi, alo);
-      carry_tree<R, D - 1>(C, N, n - 1, base, iz + ((z & 1) ? 1 : -1), iy + ((y & 1) ? 1 : -1),
-                           ix + ((x & 1) ? 1 : -1), bhi, blo);
-      const R h = static_cast<const R*>(C.hole)[(size_t)n * C.box + id];
-      carry_step(ahi, alo, bhi, blo, h, C.comp != 0, hi, lo);
-      return;
-    }
-  }
-  if (base == 0) {  // S_0 is the hole potential of level 0
-    hi = static_cast<const R*>(C.hole)[id];
-    lo = 0;
+  if constexpr (D == 0) {
+    hi = lhi[id];
+    const R l = (llo ? llo : lhi)[id];  // no branch around the load
+    lo = llo ? l : (R)0;
   } else {
-    const R* S = static_cast<const R*>(C.S) + (size_t)base * 2 * C.box;
-    hi = S[id];
-    lo = C.comp ? S[C.box + id] : (R)0;
+    const int off = N / 4 - 1;
+    const int z = bz + off, y = by + off, x = bx + off;
+    const int iz = z / 2 + 1, iy = y / 2 + 1, ix = x / 2 + 1;
+    R ahi, alo, bhi, blo;
+    carry_tree<R, COMP, D - 1>(C, N, n - 1, lhi, llo, iz, iy, ix, ahi, alo);
+    carry_tree<R, COMP, D - 1>(C, N, n - 1, lhi, llo, iz + ((z & 1) ? 1 : -1), iy + ((y & 1) ? 1 : -1),
+                               ix + ((x & 1) ? 1 : -1), bhi, blo);
+    const R h = static_cast<const R*>(C.hole)[(size_t)n * C.box + id];
+    carry_step<R, COMP>(ahi, alo, bhi, blo, h, hi, lo);
   }
 }
 
-template <class R>
+// COMP: every request of the launch keeps (hi, lo) pairs (CarryDesc::comp).
+template <class R, bool COMP>
 __global__ void __launch_bounds__(256) k_carry(CarryTable tab, int N, int n0) {
   const int NB = N / 2 + 2, nb3 = NB * NB * NB, per = (nb3 + 255) / 256;
   const int r = blockIdx.y, lv = blockIdx.x / per;
@@ -669,11 +680,22 @@ __global__ void __launch_bounds__(256) k_carry(CarryTable tab, int N, int n0) {
   if (id >= nb3) return;
   const CarryDesc& C = tab.r[r];
   const int n = n0 + lv;
+  // S_{n0-1}: the hole potential of level 0 itself when n0 = 1
+  const R* S = static_cast<const R*>(C.S);
+  const R* lhi = n0 == 1 ? static_cast<const R*>(C.hole) : S + (size_t)(n0 - 1) * 2 * C.box;
+  const R* llo = (n0 == 1 || !COMP) ? nullptr : lhi + C.box;
+  const int bz = id / (NB * NB), by = id / NB % NB, bx = id % NB;
   R hi, lo;
-  carry_tree<R, kMaxCarryDepth>(C, N, n, n0 - 1, id / (NB * NB), id / NB % NB, id % NB, hi, lo);
-  R* S = static_cast<R*>(C.S) + (size_t)n * 2 * C.box;
-  S[id] = hi;
-  if (C.comp) S[C.box + id] = lo;
+  static_assert(kMaxCarryDepth == 4, "one case per depth");
+  switch (lv) {
+    case 0: carry_tree<R, COMP, 1>(C, N, n, lhi, llo, bz, by, bx, hi, lo); break;
+    case 1: carry_tree<R, COMP, 2>(C, N, n, lhi, llo, bz, by, bx, hi, lo); break;
+    case 2: carry_tree<R, COMP, 3>(C, N, n, lhi, llo, bz, by, bx, hi, lo); break;
+    default: carry_tree<R, COMP, 4>(C, N, n, lhi, llo, bz, by, bx, hi, lo); break;
+  }
+  R* out = static_cast<R*>(C.S) + (size_t)n * 2 * C.box;
+  out[id] = hi;
+  if (COMP) out[C.box + id] = lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -867,7 +889,7 @@ hipError_t launch_pyramid(const PyramidTable& tab, int count, int N, int maxL, h
     const int S = pyramid_cube(N, k), nc = N / S;
     blocks += nc * nc * nc;
   }
-  hipLaunchKernelGGL(k_pyramid<R>, dim3(blocks, count), dim3(256), 0, s, tab, N, maxL);
+  hipLaunchKernelGGL(k_pyramid<R>, dim3(blocks, count), dim3(kPyramidThreads), 0, s, tab, N, maxL);
   return hipGetLastError();
 }
 
@@ -877,7 +899,11 @@ hipError_t launch_carry(const CarryTable& tab, int count, int N, int n0, hipStre
   int nl = 0;
   for (int i = 0; i < count; ++i) nl = std::max(nl, tab.nlev[i]);
   if (nl <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_carry<R>, dim3(per * nl, count), dim3(256), 0, s, tab, N, n0);
+  // a launch is either all compensated or all plain (runtime groups them)
+  if (sizeof(R) == 4 && tab.r[0].comp)
+    hipLaunchKernelGGL((k_carry<R, true>), dim3(per * nl, count), dim3(256), 0, s, tab, N, n0);
+  else
+    hipLaunchKernelGGL((k_carry<R, false>), dim3(per * nl, count), dim3(256), 0, s, tab, N, n0);
   return hipGetLastError();
 }
 

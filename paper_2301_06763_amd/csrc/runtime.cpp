@@ -566,15 +566,23 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   };
   auto carry_cascade = [&](hipStream_t st) -> int {
     const double ns3 = std::pow((double)NC, 3);
-    for (size_t a = 0; a < carries.size(); a += nmc::kMaxCarriesPerLaunch) {
-      const int cnt = (int)std::min<size_t>(nmc::kMaxCarriesPerLaunch, carries.size() - a);
+    // one launch sequence per kind of sum (compensated or plain)
+    std::vector<size_t> order;
+    for (int c = 1; c >= 0; --c)
+      for (size_t k = 0; k < carries.size(); ++k)
+        if (carries[k].comp == c) order.push_back(k);
+    for (size_t a = 0; a < order.size();) {
+      int cnt = 0;
+      while (a + cnt < order.size() && cnt < nmc::kMaxCarriesPerLaunch &&
+             carries[order[a + cnt]].comp == carries[order[a]].comp)
+        ++cnt;
       for (int n0 = 1;; n0 += nmc::kMaxCarryDepth) {
         nmc::CarryTable tab{};
         int any = 0;
         double bytes = 0;
         for (int k = 0; k < cnt; ++k) {
-          tab.r[k] = carries[a + k];
-          const int left = carry_levels[a + k] - (n0 - 1);
+          tab.r[k] = carries[order[a + k]];
+          const int left = carry_levels[order[a + k]] - (n0 - 1);
           tab.nlev[k] = std::max(0, std::min(nmc::kMaxCarryDepth, left));
           any += tab.nlev[k];
           // per level: the hole potential read, S written (hi, lo)
@@ -584,6 +592,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
         ProfScope ps(ctx, st, NMC_PASS_CARRY, bytes);
         NMC_HIP(ctx, nmc::launch_carry<R>(tab, cnt, N, n0, st));
       }
+      a += cnt;
     }
     return NMC_OK;
   };
