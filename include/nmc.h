@@ -69,10 +69,17 @@ enum {
    * precision and flags) replay a captured HIP graph that owns its own
    * workspace, which removes the per-kernel launch cost. */
   NMC_NO_GRAPH = 1u << 3,
-  /* Enqueue every grid on hip_stream only.  Default: the grids that need no
-   * restriction run on a second, library-owned stream forked from and joined
-   * back into hip_stream, overlapping the restriction cascade. */
-  NMC_ONE_STREAM = 1u << 4
+  /* Enqueue every grid on hip_stream only.  Default from N = 128 (where the
+   * hole potentials come from child-region boxes): the boxes run on a second,
+   * library-owned stream forked from and joined back into hip_stream,
+   * overlapping the full grids' passes. */
+  NMC_ONE_STREAM = 1u << 4,
+  /* Use the separate X, Y, I2 and I1 passes even where fused plane passes
+   * apply (P <= 64, hole-grid formulation; default there: one XY and one
+   * I2+I1 launch per kind of grid, each z plane kept in LDS).  For
+   * ablation.  In a batch, ONE_STREAM and NO_FUSED_PLANES are taken from the
+   * first request of each group of equal N and precision. */
+  NMC_NO_FUSED_PLANES = 1u << 5
 };
 
 /* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
@@ -205,7 +212,10 @@ enum {
   NMC_PASS_RESTRICT = 0, NMC_PASS_X = 1, NMC_PASS_Y = 2, NMC_PASS_Z = 3, NMC_PASS_IY = 4,
   NMC_PASS_IX_SECOND = 5, /* last pass of the hole grids or child-region boxes */
   NMC_PASS_CARRY = 6,     /* carry cascade (hole-grid formulation only) */
-  NMC_PASS_IX_FULL = 7, NMC_NUM_PASSES = 8
+  NMC_PASS_IX_FULL = 7,
+  /* fused plane passes (P <= 64, used in place of X+Y and I2+I1): */
+  NMC_PASS_XY = 8, NMC_PASS_IYX_SECOND = 9, NMC_PASS_IYX_FULL = 10,
+  NMC_NUM_PASSES = 11
 };
 
 typedef struct {

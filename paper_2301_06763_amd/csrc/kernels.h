@@ -123,6 +123,13 @@ template <class R> hipError_t launch_z(const FieldTable&, PassGeom, Tables<R>, h
 template <class R> hipError_t launch_inv_y(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 template <class R> hipError_t launch_inv_x(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 
+// Fused plane passes for P <= 64 when a plane fits the LDS
+// (plane_passes_fit): X+Y in one launch, I2+I1 in one launch; the A
+// workspace is not used.  g.n is the largest nin (fwd_xy) or nout (inv_yx).
+template <class R> bool plane_passes_fit(int P);
+template <class R> hipError_t launch_fwd_xy(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
+template <class R> hipError_t launch_inv_yx(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
+
 // Restriction of level l+1 onto the child region of level l, one level per
 // launch (any N); fine_rc is the finished restriction of level l+1 or null.
 template <class R>

@@ -138,29 +138,20 @@ __device__ __forceinline__ GridGeo grid_geo(int kind, int N) {
 
 // ---------------------------------------------------------------------------
 // X pass: R2C along x with zero padding (input index >= nin is zero).
+//
+// Inputs of the x line (z, y) of a grid: thread t's points x = t + TL q,
+// q < E/2 (the upper half is the zero padding).  Kind 0/2: the level's row
+// with the child region restricted (kind 0, rc set) or zeroed (kind 2);
+// kind 1: row of the child-region box.  An inactive line gives zeros.
 template <class R, int P, bool FULLN>
-__global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
-k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
-  using C = Cfg<R, P>;
+__device__ __forceinline__ void x_inputs(const FieldDesc& F, int N, int z, int y, bool active, int t,
+                                         cplx<R>* v) {
   using T = cplx<R>;
-  constexpr int E = C::E, TL = C::TL, W = C::WC;
-  __shared__ R sre[W * P], sim[W * P];
-  __shared__ cplx<R> stw[P];
-  const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
-  const FieldDesc& F = ft.f[blockIdx.y];
-  const int N = FULLN ? P / 2 : g.N, n = grid_geo(F.kind, N).nin;
-  if ((int)blockIdx.x * W >= n * n) return;  // uniform: a smaller grid of a mixed launch
-  const int t = threadIdx.x % TL, w = threadIdx.x / TL;
-  const int line = blockIdx.x * W + w;
-  const bool active = line < n * n;
-  const int z = active ? line / n : 0, y = active ? line % n : 0;
+  constexpr int E = Plan<R, P>::E, TL = P / E;
   const R* rho = static_cast<const R*>(F.rho);
   const bool rc = F.rc != nullptr;
   const int N2 = N / 2;
-  T v[E];
   if (F.kind != 1) {
-    // full level (child region restricted when rc is set) or level with the
-    // child region zeroed (kind 2)
     const int lo = N / 4, hi = 3 * N / 4;
     const bool yz_in = z >= lo && z < hi && y >= lo && y < hi;
     const bool use_rc = F.kind == 0 && rc && yz_in;
@@ -196,18 +187,41 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
       v[q] = T{val, 0};
     }
   }
+}
+
+// Half spectrum of a transformed real x line, k = t + TL q < P/2, with the
+// real DC and Nyquist values packed into k = 0.
+template <class R, int P>
+__device__ __forceinline__ cplx<R> x_packed(const cplx<R>* v, int t, int q) {
+  constexpr int E = Plan<R, P>::E;
+  return (t == 0 && q == 0) ? cplx<R>{v[0].x, v[E / 2].x} : v[q];
+}
+
+template <class R, int P, bool FULLN>
+__global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
+k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using C = Cfg<R, P>;
+  using T = cplx<R>;
+  constexpr int E = C::E, TL = C::TL, W = C::WC;
+  __shared__ R sre[W * P], sim[W * P];
+  __shared__ cplx<R> stw[P];
+  const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = FULLN ? P / 2 : g.N, n = grid_geo(F.kind, N).nin;
+  if ((int)blockIdx.x * W >= n * n) return;  // uniform: a smaller grid of a mixed launch
+  const int t = threadIdx.x % TL, w = threadIdx.x / TL;
+  const int line = blockIdx.x * W + w;
+  const bool active = line < n * n;
+  const int z = active ? line / n : 0, y = active ? line % n : 0;
+  T v[E];
+  x_inputs<R, P, FULLN>(F, N, z, y, active, t, v);
   LdsView<R> lds{sre, sim, 1, P, w};
   tws.put(stw);
   fft_line<R, P, -1, true, false>(v, t, lds, stw);
   if (active) {
     T* A = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
 #pragma unroll
-    for (int q = 0; q < E / 2; ++q) {
-      const int k = t + TL * q;
-      T o = v[q];
-      if (k == 0) o = T{v[0].x, v[E / 2].x};  // DC and Nyquist are real: pack them
-      A[k] = o;
-    }
+    for (int q = 0; q < E / 2; ++q) A[t + TL * q] = x_packed<R, P>(v, t, q);
   }
 }
 
@@ -402,45 +416,36 @@ __device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
-template <class R, int P>
-__global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
-k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
-  using C = Cfg<R, P>;
+// Points x = t + TL q of the Hermitian extension of a packed half spectrum
+// (row[k], k < P/2, with the real DC and Nyquist values in row[0]); every
+// load is issued without a branch, an inactive line reads row 0 and drops it.
+template <class R, int P, class Row>
+__device__ __forceinline__ void hermitian_inputs(Row row, bool active, int t, cplx<R>* v) {
   using T = cplx<R>;
-  constexpr int E = C::E, TL = C::TL, W = C::WC;
-  __shared__ R sre[W * P], sim[W * P];
-  __shared__ cplx<R> stw[P];
-  const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
-  const FieldDesc& F = ft.f[blockIdx.y];
-  const int N = g.N;
-  const GridGeo gg = grid_geo(F.kind, N);
-  const int n = gg.nout;
-  if ((int)blockIdx.x * W >= n * n) return;  // uniform: a smaller grid of a mixed launch
-  const int t = threadIdx.x % TL, w = threadIdx.x / TL;
-  const int line = blockIdx.x * W + w;
-  const bool active = line < n * n;
-  const int zr = active ? line / n : 0, yr = active ? line % n : 0;  // within the output box
-  const int z = gg.olo + zr, y = gg.olo + yr;
-  const T* row = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
-  // Hermitian extension of the packed half spectrum; every load is issued
-  // without a branch (inactive lines read row 0 and drop it)
-  T v[E];
+  constexpr int E = Plan<R, P>::E, TL = P / E;
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int k = t + TL * q;  // < P/2; k = 0 holds the real DC value in .x
-    const T m = row[k];
+    const T m = row(k);
     v[q] = !active ? T{0, 0} : (k == 0 ? T{m.x, 0} : m);
   }
 #pragma unroll
   for (int q = E / 2; q < E; ++q) {
     const int kk = P - (t + TL * q);  // in (0, P/2]; P/2 is the Nyquist value in row[0].y
-    const T m = row[kk == P / 2 ? 0 : kk];
+    const T m = row(kk == P / 2 ? 0 : kk);
     v[q] = !active ? T{0, 0} : (kk == P / 2 ? T{m.y, 0} : T{m.x, -m.y});
   }
-  LdsView<R> lds{sre, sim, 1, P, w};
-  tws.put(stw);
-  fft_line<R, P, +1, false, true>(v, t, lds, stw);
-  if (!active) return;
+}
+
+// Outputs of the inverse-transformed x line (z, y) of a grid (zr, yr: its
+// row within the output box).  Kinds 1 and 2 write the box; kind 0 writes
+// Phi(Omega^l) = Phi^l + Prolong(S_{l-1}) and, on the stencil box of a level
+// with a finer one (child-region boxes), S_l = Phi(Omega^l) - C_l.
+template <class R, int P>
+__device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const GridGeo& gg, int z, int y,
+                                           int zr, int yr, int t, const cplx<R>* v) {
+  constexpr int E = Plan<R, P>::E, TL = P / E;
+  const int n = gg.nout;
   R* out = static_cast<R*>(F.out);
   if (F.kind != 0) {  // box output (C or the hole potential)
 #pragma unroll
@@ -501,6 +506,185 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
         So[bi] = dh;
         if (Slo) Slo[bi] = e - (dh - d);
       }
+    }
+  }
+}
+
+template <class R, int P>
+__global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
+k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using C = Cfg<R, P>;
+  using T = cplx<R>;
+  constexpr int E = C::E, TL = C::TL, W = C::WC;
+  __shared__ R sre[W * P], sim[W * P];
+  __shared__ cplx<R> stw[P];
+  const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = g.N;
+  const GridGeo gg = grid_geo(F.kind, N);
+  const int n = gg.nout;
+  if ((int)blockIdx.x * W >= n * n) return;  // uniform: a smaller grid of a mixed launch
+  const int t = threadIdx.x % TL, w = threadIdx.x / TL;
+  const int line = blockIdx.x * W + w;
+  const bool active = line < n * n;
+  const int zr = active ? line / n : 0, yr = active ? line % n : 0;  // within the output box
+  const int z = gg.olo + zr, y = gg.olo + yr;
+  const T* row = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
+  T v[E];
+  hermitian_inputs<R, P>([&](int k) { return row[k]; }, active, t, v);
+  LdsView<R> lds{sre, sim, 1, P, w};
+  tws.put(stw);
+  fft_line<R, P, +1, false, true>(v, t, lds, stw);
+  if (!active) return;
+  ix_outputs<R, P>(F, N, gg, z, y, zr, yr, t, v);
+}
+
+// ---------------------------------------------------------------------------
+// Fused plane passes (P <= 64): a workgroup owns one z plane of one grid and
+// keeps it in LDS between the x and y transforms, so the x-transformed plane
+// never goes through HBM and one launch does the work of two.  (Measured: at
+// P = 128 the one-workgroup-per-plane grid, e.g. 576 workgroups for 9 grids
+// of 64^3, leaves too little parallelism and the separate passes win.)
+//   XY  (fwd_xy): the x lines of the plane (as the X pass), then its y
+//                 columns (as the Y pass), written to B[z][ky][kx];
+//   IYX (inv_yx): the y columns of an output plane (as the I2 pass), then its
+//                 x lines (as the I1 pass, with the same outputs and carry).
+#ifndef NMC_PLANE_THREADS
+#define NMC_PLANE_THREADS 256
+#endif
+template <class R, int P>
+struct PlaneCfg {
+  static constexpr int E = Plan<R, P>::E;
+  static constexpr int TL = P / E;
+  static constexpr int H2 = P / 2;
+  static constexpr int WL = (NMC_PLANE_THREADS / TL < H2) ? NMC_PLANE_THREADS / TL : H2;  // lines per round
+  static constexpr int NTH = WL * TL;
+  static constexpr int PS = H2 + 1;  // plane row stride: odd, so column reads spread over banks
+  static constexpr int LDS = (2 * H2 * PS + 2 * WL * P) * (int)sizeof(R) + P * 2 * (int)sizeof(R);
+};
+constexpr int kPlaneLdsMax = 64 * 1024;
+constexpr int kPlaneMaxP = 64;
+
+template <class R, int P, bool FULLN>
+__global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_fwd_xy(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using PC = PlaneCfg<R, P>;
+  using T = cplx<R>;
+  constexpr int E = PC::E, TL = PC::TL, WL = PC::WL, PS = PC::PS, H2 = PC::H2;
+  __shared__ R pre[H2 * PS], pim[H2 * PS];
+  __shared__ R sre[WL * P], sim[WL * P];
+  __shared__ T stw[P];
+  const TwStage<R, P, PC::NTH> tws(tb.tw);
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = FULLN ? P / 2 : g.N;
+  const int n = grid_geo(F.kind, N).nin;
+  const int z = blockIdx.x;
+  if (z >= n) return;  // uniform: a smaller grid of a mixed launch
+  tws.put(stw);
+  {  // x lines y of the plane, t fastest (rows of the density are contiguous)
+    const int t = threadIdx.x % TL, w = threadIdx.x / TL;
+    const LdsView<R> lds{sre, sim, 1, P, w};
+    // the next round's inputs are loaded while this round is transformed
+    T vn[E];
+    x_inputs<R, P, FULLN>(F, N, z, w < n ? w : 0, w < n, t, vn);
+    for (int y0 = 0; y0 < n; y0 += WL) {
+      const int y = y0 + w;
+      const bool active = y < n;
+      T v[E];
+#pragma unroll
+      for (int q = 0; q < E / 2; ++q) v[q] = vn[q];
+      if (y0 + WL < n) {  // uniform
+        const int yn = y + WL;
+        x_inputs<R, P, FULLN>(F, N, z, yn < n ? yn : 0, yn < n, t, vn);
+      }
+      fft_line<R, P, -1, true, false>(v, t, lds, stw);
+      if (active) {
+#pragma unroll
+        for (int q = 0; q < E / 2; ++q) {
+          const T o = x_packed<R, P>(v, t, q);
+          pre[y * PS + t + TL * q] = o.x;
+          pim[y * PS + t + TL * q] = o.y;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  {  // y columns kx, w fastest (each store is a run of WL complex values)
+    const int w = threadIdx.x % WL, t = threadIdx.x / WL;
+    const LdsView<R> lds{sre, sim, WL, 1, w};
+    const bool full_in = FULLN && F.kind != 1;
+    T* Bz = static_cast<T*>(F.B) + (size_t)z * P * H2;
+    for (int k0 = 0; k0 < H2; k0 += WL) {
+      const int kx = k0 + w;
+      T v[E];
+#pragma unroll
+      for (int q = 0; q < E / 2; ++q) {
+        const int yy = t + TL * q;
+        v[q] = (full_in || yy < n) ? T{pre[yy * PS + kx], pim[yy * PS + kx]} : T{0, 0};
+      }
+      fft_line<R, P, -1, true, false>(v, t, lds, stw);
+#pragma unroll
+      for (int q = 0; q < E; ++q) Bz[(size_t)(t + TL * q) * H2 + kx] = v[q];
+    }
+  }
+}
+
+template <class R, int P, bool FULLN>
+__global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_inv_yx(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using PC = PlaneCfg<R, P>;
+  using T = cplx<R>;
+  constexpr int E = PC::E, TL = PC::TL, WL = PC::WL, PS = PC::PS, H2 = PC::H2;
+  __shared__ R pre[H2 * PS], pim[H2 * PS];
+  __shared__ R sre[WL * P], sim[WL * P];
+  __shared__ T stw[P];
+  const TwStage<R, P, PC::NTH> tws(tb.tw);
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = FULLN ? P / 2 : g.N;
+  const GridGeo gg = grid_geo(F.kind, N);
+  const int n = gg.nout;
+  const int zr = blockIdx.x;
+  if (zr >= n) return;  // uniform: a smaller grid of a mixed launch
+  const int z = gg.olo + zr;
+  tws.put(stw);
+  {  // y columns kx: inverse, keep the output rows [olo, olo + n)
+    const int w = threadIdx.x % WL, t = threadIdx.x / WL;
+    const LdsView<R> lds{sre, sim, WL, 1, w};
+    const T* Bz = static_cast<const T*>(F.B) + (size_t)z * P * H2;
+    // the next round's columns are loaded while this round is transformed
+    T vn[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) vn[q] = Bz[(size_t)(t + TL * q) * H2 + w];
+    for (int k0 = 0; k0 < H2; k0 += WL) {
+      const int kx = k0 + w;
+      T v[E];
+#pragma unroll
+      for (int q = 0; q < E; ++q) v[q] = vn[q];
+      if (k0 + WL < H2) {  // uniform
+#pragma unroll
+        for (int q = 0; q < E; ++q) vn[q] = Bz[(size_t)(t + TL * q) * H2 + kx + WL];
+      }
+      fft_line<R, P, +1, false, true>(v, t, lds, stw);
+#pragma unroll
+      for (int q = 0; q < E / 2; ++q) {
+        const int yr = t + TL * q - gg.olo;
+        if (yr >= 0 && yr < n) {
+          pre[yr * PS + kx] = v[q].x;
+          pim[yr * PS + kx] = v[q].y;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  {  // x lines of the output rows: C2R, then the outputs of the I1 pass
+    const int t = threadIdx.x % TL, w = threadIdx.x / TL;
+    const LdsView<R> lds{sre, sim, 1, P, w};
+    for (int y0 = 0; y0 < n; y0 += WL) {
+      const int yr = y0 + w;
+      const bool active = yr < n;
+      const int yc = active ? yr : 0;
+      T v[E];
+      hermitian_inputs<R, P>([&](int k) { return T{pre[yc * PS + k], pim[yc * PS + k]}; }, active, t, v);
+      fft_line<R, P, +1, false, true>(v, t, lds, stw);
+      if (active) ix_outputs<R, P>(F, N, gg, z, gg.olo + yr, zr, yr, t, v);
     }
   }
 }
@@ -876,6 +1060,46 @@ hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
 }
 
 template <class R>
+bool plane_passes_fit(int P) {
+  bool ok = false;
+  (void)dispatch_p(P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    ok = PP <= kPlaneMaxP && PlaneCfg<R, PP>::LDS <= kPlaneLdsMax;
+  });
+  return ok;
+}
+
+template <class R>
+hipError_t launch_fwd_xy(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  return dispatch_p(g.P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    using PC = PlaneCfg<R, PP>;
+    if constexpr (PP <= kPlaneMaxP && PC::LDS <= kPlaneLdsMax) {
+      dim3 grid(g.n, g.nf);
+      if (g.N == PP / 2)
+        hipLaunchKernelGGL((k_fwd_xy<R, PP, true>), grid, dim3(PC::NTH), 0, s, ft, g, tb);
+      else
+        hipLaunchKernelGGL((k_fwd_xy<R, PP, false>), grid, dim3(PC::NTH), 0, s, ft, g, tb);
+    }
+  });
+}
+
+template <class R>
+hipError_t launch_inv_yx(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  return dispatch_p(g.P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    using PC = PlaneCfg<R, PP>;
+    if constexpr (PP <= kPlaneMaxP && PC::LDS <= kPlaneLdsMax) {
+      dim3 grid(g.n, g.nf);
+      if (g.N == PP / 2)
+        hipLaunchKernelGGL((k_inv_yx<R, PP, true>), grid, dim3(PC::NTH), 0, s, ft, g, tb);
+      else
+        hipLaunchKernelGGL((k_inv_yx<R, PP, false>), grid, dim3(PC::NTH), 0, s, ft, g, tb);
+    }
+  });
+}
+
+template <class R>
 hipError_t launch_restrict(const R* fine, const R* fine_rc, R* rc, int N, hipStream_t s) {
   const int n = (N / 2) * (N / 2) * (N / 2);
   hipLaunchKernelGGL(k_restrict<R>, dim3((n + 255) / 256), dim3(256), 0, s, fine, fine_rc, rc, N);
@@ -969,6 +1193,9 @@ hipError_t launch_fft_lines(const void* in, void* out, int P, int nlines, int di
   template hipError_t launch_z<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);           \
   template hipError_t launch_inv_y<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
   template hipError_t launch_inv_x<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
+  template hipError_t launch_fwd_xy<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);      \
+  template hipError_t launch_inv_yx<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);      \
+  template bool plane_passes_fit<R>(int);                                                         \
   template hipError_t launch_restrict<R>(const R*, const R*, R*, int, hipStream_t);               \
   template hipError_t launch_pyramid<R>(const PyramidTable&, int, int, int, hipStream_t);          \
   template hipError_t launch_carry<R>(const CarryTable&, int, int, int, hipStream_t);              \

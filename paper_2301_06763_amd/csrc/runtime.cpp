@@ -410,6 +410,12 @@ struct PassBytes {
   double y() const { return nin * nin * half() * c + nin * P * half() * c; }
   double z() const { return (nin + nout) * P * half() * c + H * H * H * r; }
   double iy() const { return nout * P * half() * c + nout * nout * half() * c; }
+  // fused plane passes: the x-transformed plane stays on chip
+  double xy() const {
+    const double in = kind == 1 ? std::pow(N / 2, 3) : N * N * N;
+    return in * r + nin * P * half() * c;
+  }
+  double iyx(bool carry, bool next) const { return nout * P * half() * c + ix(carry, next) - nout * nout * half() * c; }
   double ix(bool carry, bool next) const {
     // the carried box S is read once per level; C is read and S_l written
     return nout * nout * half() * c + nout * nout * nout * r + (carry ? NS * NS * NS * r : 0.0) +
@@ -535,6 +541,9 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
           case NMC_PASS_Y: bytes += pb.y(); break;
           case NMC_PASS_Z: bytes += pb.z(); break;
           case NMC_PASS_IY: bytes += pb.iy(); break;
+          case NMC_PASS_XY: bytes += pb.xy(); break;
+          case NMC_PASS_IYX_SECOND:
+          case NMC_PASS_IYX_FULL: bytes += pb.iyx(ft.f[k].S != nullptr, ft.f[k].Sout != nullptr); break;
           default: bytes += pb.ix(ft.f[k].S != nullptr, ft.f[k].Sout != nullptr); break;
         }
       }
@@ -610,6 +619,14 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     if ((rc = restrict_cascade(s))) return rc;
     std::vector<FieldDesc> all(fulls);
     all.insert(all.end(), secs.begin(), secs.end());
+    if (nmc::plane_passes_fit<R>(P) && !(reqs[0].flags & NMC_NO_FUSED_PLANES)) {
+      NMC_HIP(ctx, for_chunks(all, N, nmc::launch_fwd_xy<R>, NMC_PASS_XY, s));
+      NMC_HIP(ctx, for_chunks(all, N, nmc::launch_z<R>, NMC_PASS_Z, s));
+      if (!secs.empty()) NMC_HIP(ctx, for_chunks(secs, NC, nmc::launch_inv_yx<R>, NMC_PASS_IYX_SECOND, s));
+      if ((rc = carry_cascade(s))) return rc;
+      NMC_HIP(ctx, for_chunks(fulls, N, nmc::launch_inv_yx<R>, NMC_PASS_IYX_FULL, s));
+      return NMC_OK;
+    }
     if ((rc = forward_to_iy(all, N, N, s))) return rc;
     if (!secs.empty()) NMC_HIP(ctx, for_chunks(secs, NC, nmc::launch_inv_x<R>, NMC_PASS_IX_SECOND, s));
     if ((rc = carry_cascade(s))) return rc;
@@ -1122,7 +1139,8 @@ int nmc_profile_read(nmc_ctx* ctx, nmc_pass_stat* out) {
 }
 
 const char* nmc_pass_name(int pass) {
-  static const char* names[NMC_NUM_PASSES] = {"restrict", "x", "y", "z", "inv_y", "inv_x_second", "carry", "inv_x_full"};
+  static const char* names[NMC_NUM_PASSES] = {"restrict", "x",     "y",  "z", "inv_y", "inv_x_second", "carry",
+                                              "inv_x_full", "xy", "inv_yx_second", "inv_yx_full"};
   return (pass >= 0 && pass < NMC_NUM_PASSES) ? names[pass] : "?";
 }
 

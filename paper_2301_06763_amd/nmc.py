@@ -22,6 +22,7 @@ NMC_NO_RESTRICT = 1 << 0
 NMC_F32_UNCOMPENSATED = 1 << 2
 NMC_NO_GRAPH = 1 << 3
 NMC_ONE_STREAM = 1 << 4
+NMC_NO_FUSED_PLANES = 1 << 5
 
 _CODES = {NMC_EINVAL: "EINVAL", NMC_ENOMEM: "ENOMEM", NMC_EDEVICE: "EDEVICE",
           NMC_EUNSUPPORTED: "EUNSUPPORTED", NMC_EAGAIN: "EAGAIN"}
@@ -43,7 +44,7 @@ class PassStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-NUM_PASSES = 8
+NUM_PASSES = 11
 
 
 class ServeStats(ctypes.Structure):

@@ -104,6 +104,26 @@ def test_restriction_modes_in_one_batch(ctx, dtype):
         assert np.max(rel_err(b.double().cpu().numpy(), ref)) < tol
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("N,L", [(4, 2), (8, 3), (12, 3), (16, 4), (32, 4)])
+def test_fused_plane_passes_match_separate(ctx, dtype, N, L):
+    """Up to P = 64 X+Y and I2+I1 run as fused plane passes (one z plane
+    per workgroup, kept in LDS); the separate passes (NMC_NO_FUSED_PLANES)
+    do the same line transforms, so both agree to rounding and both match
+    the oracle."""
+    from paper_2301_06763_amd import nmc
+    w = inputs.random_levels(N, L, seed=400 + N + L)
+    rho = w.rho.numpy()
+    ref = oracle.solve(rho, w.h0)
+    fused = run(ctx, rho, w.h0, dtype=dtype)
+    sep = run(ctx, rho, w.h0, dtype=dtype, flags=nmc.NMC_NO_FUSED_PLANES)
+    tol = F64_TOL if dtype == torch.float64 else F32_TOL
+    assert np.max(rel_err(fused, ref)) < tol
+    assert np.max(rel_err(sep, ref)) < tol
+    agree = 1e-14 if dtype == torch.float64 else 1e-6
+    assert np.max(np.abs(fused - sep) / np.abs(sep)) < agree
+
+
 def test_deep_hierarchy_fp32(ctx):
     """Seven levels of 32^3 in FP32: cascaded restriction and a carry
     cascade split over two launches, with compensated sums."""
