@@ -17,6 +17,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <utility>
 
 namespace nmc {
@@ -174,54 +175,38 @@ __device__ __forceinline__ void fft_stages(cplx<R>* v, int t, const LdsView<R>& 
     fft_stages<R, P, E, DIR, NS * RAD, false, false, POUT, REST...>(v, t, lds, tw);
 }
 
-// Per-length plan: points per thread E and the radix sequence.  FP64 keeps
-// E = 8 (fewer registers per thread, more resident waves); FP32 uses E = 16
-// where it saves an LDS exchange.
-#ifndef NMC_F64_E16
-#define NMC_F64_E16 0
-#endif
-template <class R, int P> struct Plan;
-template <class R> struct Plan<R, 8> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8>(); } };
-template <class R> struct Plan<R, 16> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 2>(); } };
-template <class R> struct Plan<R, 32> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4>(); } };
-template <class R> struct Plan<R, 64> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8>(); } };
-#ifndef NMC_F32_E8
-#define NMC_F32_E8 1
-#endif
-#ifndef NMC_F32_P512_E16
-#define NMC_F32_P512_E16 0
-#endif
-#ifndef NMC_F64_P512_E16
-#define NMC_F64_P512_E16 0
-#endif
-#if NMC_F32_E8
-template <> struct Plan<float, 128> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4, 4>(); } };
-template <> struct Plan<float, 256> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 4>(); } };
-#if NMC_F32_P512_E16
-template <> struct Plan<float, 512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
-#else
-template <> struct Plan<float, 512> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
-#endif
-#else
-template <> struct Plan<float, 128> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8>(); } };
-template <> struct Plan<float, 256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
-template <> struct Plan<float, 512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
-#endif
-#if NMC_F64_E16
-template <> struct Plan<double, 128> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8>(); } };
-template <> struct Plan<double, 256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
-template <> struct Plan<double, 512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
-#else
-template <> struct Plan<double, 128> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4, 4>(); } };
-template <> struct Plan<double, 256> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 4>(); } };
-#if NMC_F64_P512_E16
-template <> struct Plan<double, 512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
-#else
-template <> struct Plan<double, 512> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
-#endif
+// Per-length plans: points per thread E and the radix sequence.  Narrow
+// plans hold E = 8 points per thread.  Wide plans (FP32, P >= 128) hold 16:
+// one LDS exchange fewer and fewer twiddle products per point, for more
+// registers per thread.  Which passes take the wide plan was measured pass
+// by pass (kernels.hip); NMC_WIDE_PASSES is a bit mask over PassKind.
+enum PassKind { kPassX = 0, kPassY = 1, kPassZ = 2, kPassIY = 3, kPassIX = 4, kPassOther = 5 };
+#ifndef NMC_WIDE_PASSES
+#define NMC_WIDE_PASSES ((1 << kPassY) | (1 << kPassZ))
 #endif
 
-template <class R, int P, int DIR, bool PIN, bool POUT>
+template <int P> struct NarrowPlan;
+template <> struct NarrowPlan<8> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8>(); } };
+template <> struct NarrowPlan<16> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 2>(); } };
+template <> struct NarrowPlan<32> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4>(); } };
+template <> struct NarrowPlan<64> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8>(); } };
+template <> struct NarrowPlan<128> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 4, 4>(); } };
+template <> struct NarrowPlan<256> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 4>(); } };
+template <> struct NarrowPlan<512> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+
+template <int P> struct WidePlan;
+template <> struct WidePlan<128> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8>(); } };
+template <> struct WidePlan<256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
+template <> struct WidePlan<512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+
+template <class R, int P, int K>
+constexpr bool wide_plan() {
+  return sizeof(R) == 4 && P >= 128 && ((NMC_WIDE_PASSES >> K) & 1) != 0;
+}
+template <class R, int P, int K = kPassOther>
+struct Plan : std::conditional_t<wide_plan<R, P, K>(), WidePlan<P>, NarrowPlan<P>> {};
+
+template <class R, int P, int DIR, bool PIN, bool POUT, int K>
 struct FftRun {
   cplx<R>* v;
   int t;
@@ -229,15 +214,16 @@ struct FftRun {
   const cplx<R>* tw;
   template <int... RS>
   __device__ __forceinline__ void go() const {
-    fft_stages<R, P, Plan<R, P>::E, DIR, 1, true, PIN, POUT, RS...>(v, t, *lds, tw);
+    fft_stages<R, P, Plan<R, P, K>::E, DIR, 1, true, PIN, POUT, RS...>(v, t, *lds, tw);
   }
 };
 
-// Transform one line held as v[q] = x[t + TL q] in place (natural order out).
-template <class R, int P, int DIR, bool PIN, bool POUT>
+// Transform one line held as v[q] = x[t + TL q] in place (natural order out),
+// TL = P / Plan<R, P, K>::E.
+template <class R, int P, int DIR, bool PIN, bool POUT, int K = kPassOther>
 __device__ __forceinline__ void fft_line(cplx<R>* v, int t, const LdsView<R>& lds,
                                          const cplx<R>* __restrict__ tw) {
-  Plan<R, P>::run(FftRun<R, P, DIR, PIN, POUT>{v, t, &lds, tw});
+  Plan<R, P, K>::run(FftRun<R, P, DIR, PIN, POUT, K>{v, t, &lds, tw});
 }
 
 }  // namespace nmc

@@ -39,9 +39,9 @@ namespace nmc {
 #ifndef NMC_MIN_WAVES_F64
 #define NMC_MIN_WAVES_F64 4
 #endif
-template <class R, int P>
+template <class R, int P, int K>
 struct Cfg {
-  static constexpr int E = Plan<R, P>::E;
+  static constexpr int E = Plan<R, P, K>::E;
   static constexpr int TL = P / E;
   static constexpr int BYTES_PT = 2 * (int)sizeof(R);
   static constexpr int LDS = 65536;
@@ -143,11 +143,11 @@ __device__ __forceinline__ GridGeo grid_geo(int kind, int N) {
 // q < E/2 (the upper half is the zero padding).  Kind 0/2: the level's row
 // with the child region restricted (kind 0, rc set) or zeroed (kind 2);
 // kind 1: row of the child-region box.  An inactive line gives zeros.
-template <class R, int P, bool FULLN>
+template <class R, int P, bool FULLN, int K>
 __device__ __forceinline__ void x_inputs(const FieldDesc& F, int N, int z, int y, bool active, int t,
                                          cplx<R>* v) {
   using T = cplx<R>;
-  constexpr int E = Plan<R, P>::E, TL = P / E;
+  constexpr int E = Plan<R, P, K>::E, TL = P / E;
   const R* rho = static_cast<const R*>(F.rho);
   const bool rc = F.rc != nullptr;
   const int N2 = N / 2;
@@ -191,16 +191,16 @@ __device__ __forceinline__ void x_inputs(const FieldDesc& F, int N, int z, int y
 
 // Half spectrum of a transformed real x line, k = t + TL q < P/2, with the
 // real DC and Nyquist values packed into k = 0.
-template <class R, int P>
+template <class R, int P, int K>
 __device__ __forceinline__ cplx<R> x_packed(const cplx<R>* v, int t, int q) {
-  constexpr int E = Plan<R, P>::E;
+  constexpr int E = Plan<R, P, K>::E;
   return (t == 0 && q == 0) ? cplx<R>{v[0].x, v[E / 2].x} : v[q];
 }
 
 template <class R, int P, bool FULLN>
-__global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
+__global__ void __launch_bounds__((Cfg<R, P, kPassX>::WC * Cfg<R, P, kPassX>::TL))
 k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
-  using C = Cfg<R, P>;
+  using C = Cfg<R, P, kPassX>;
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WC;
   __shared__ R sre[W * P], sim[W * P];
@@ -214,23 +214,23 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const bool active = line < n * n;
   const int z = active ? line / n : 0, y = active ? line % n : 0;
   T v[E];
-  x_inputs<R, P, FULLN>(F, N, z, y, active, t, v);
+  x_inputs<R, P, FULLN, kPassX>(F, N, z, y, active, t, v);
   LdsView<R> lds{sre, sim, 1, P, w};
   tws.put(stw);
-  fft_line<R, P, -1, true, false>(v, t, lds, stw);
+  fft_line<R, P, -1, true, false, kPassX>(v, t, lds, stw);
   if (active) {
     T* A = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
 #pragma unroll
-    for (int q = 0; q < E / 2; ++q) A[t + TL * q] = x_packed<R, P>(v, t, q);
+    for (int q = 0; q < E / 2; ++q) A[t + TL * q] = x_packed<R, P, kPassX>(v, t, q);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Y pass: C2C along y, inputs y >= n zero, all P outputs kept.
 template <class R, int P, bool FULLN>
-__global__ void __launch_bounds__((Cfg<R, P>::WS * Cfg<R, P>::TL), (Cfg<R, P>::MINW))
+__global__ void __launch_bounds__((Cfg<R, P, kPassY>::WS * Cfg<R, P, kPassY>::TL), (Cfg<R, P, kPassY>::MINW))
 k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
-  using C = Cfg<R, P>;
+  using C = Cfg<R, P, kPassY>;
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WS, NT = (P / 2) / W;
   __shared__ R sre[W * P], sim[W * P];
@@ -255,7 +255,7 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   }
   LdsView<R> lds{sre, sim, W, 1, w};
   tws.put(stw);
-  fft_line<R, P, -1, true, false>(v, t, lds, stw);
+  fft_line<R, P, -1, true, false, kPassY>(v, t, lds, stw);
 #pragma unroll
   for (int q = 0; q < E; ++q) B[(size_t)(t + TL * q) * (P / 2)] = v[q];
 }
@@ -267,9 +267,9 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
 // packed DC/Nyquist column needs the value at (-ky, -kz) to separate the two
 // real planes before they are multiplied by different spectra.
 template <class R, int P, bool FULLN>
-__global__ void __launch_bounds__((2 * Cfg<R, P>::WZ * Cfg<R, P>::TL), (Cfg<R, P>::MINW))
+__global__ void __launch_bounds__((2 * Cfg<R, P, kPassZ>::WZ * Cfg<R, P, kPassZ>::TL), (Cfg<R, P, kPassZ>::MINW))
 k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
-  using C = Cfg<R, P>;
+  using C = Cfg<R, P, kPassZ>;
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WZ, NT = (P / 2) / W, H = P / 2 + 1;
   __shared__ R sre[2 * W * P], sim[2 * W * P];
@@ -320,7 +320,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   if constexpr (!late) fetch_spectrum();
   LdsView<R> lds{sre, sim, 2 * W, 1, w + W * side};
   tws.put(stw);
-  fft_line<R, P, -1, true, false>(v, t, lds, stw);
+  fft_line<R, P, -1, true, false, kPassZ>(v, t, lds, stw);
   if constexpr (late) fetch_spectrum();
 
   const R sc = (R)F.scale;
@@ -360,7 +360,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
       v[q] = T{a * v[q].x + b * cm.x, a * v[q].y + b * cm.y};
     }
   }
-  fft_line<R, P, +1, false, true>(v, t, lds, stw);
+  fft_line<R, P, +1, false, true, kPassZ>(v, t, lds, stw);
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int zz = t + TL * q;
@@ -371,9 +371,9 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
 // ---------------------------------------------------------------------------
 // I2 pass: inverse along y over rows z < n; keep rows y < n.
 template <class R, int P, bool FULLN>
-__global__ void __launch_bounds__((Cfg<R, P>::WS * Cfg<R, P>::TL), (Cfg<R, P>::MINW))
+__global__ void __launch_bounds__((Cfg<R, P, kPassIY>::WS * Cfg<R, P, kPassIY>::TL), (Cfg<R, P, kPassIY>::MINW))
 k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
-  using C = Cfg<R, P>;
+  using C = Cfg<R, P, kPassIY>;
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WS, NT = (P / 2) / W;
   __shared__ R sre[W * P], sim[W * P];
@@ -394,7 +394,7 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   for (int q = 0; q < E; ++q) v[q] = B[(size_t)(t + TL * q) * (P / 2)];
   LdsView<R> lds{sre, sim, W, 1, w};
   tws.put(stw);
-  fft_line<R, P, +1, false, true>(v, t, lds, stw);
+  fft_line<R, P, +1, false, true, kPassIY>(v, t, lds, stw);
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int yy = t + TL * q;
@@ -419,10 +419,10 @@ __device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
 // Points x = t + TL q of the Hermitian extension of a packed half spectrum
 // (row[k], k < P/2, with the real DC and Nyquist values in row[0]); every
 // load is issued without a branch, an inactive line reads row 0 and drops it.
-template <class R, int P, class Row>
+template <class R, int P, int K, class Row>
 __device__ __forceinline__ void hermitian_inputs(Row row, bool active, int t, cplx<R>* v) {
   using T = cplx<R>;
-  constexpr int E = Plan<R, P>::E, TL = P / E;
+  constexpr int E = Plan<R, P, K>::E, TL = P / E;
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int k = t + TL * q;  // < P/2; k = 0 holds the real DC value in .x
@@ -441,10 +441,10 @@ __device__ __forceinline__ void hermitian_inputs(Row row, bool active, int t, cp
 // row within the output box).  Kinds 1 and 2 write the box; kind 0 writes
 // Phi(Omega^l) = Phi^l + Prolong(S_{l-1}) and, on the stencil box of a level
 // with a finer one (child-region boxes), S_l = Phi(Omega^l) - C_l.
-template <class R, int P>
+template <class R, int P, int K>
 __device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const GridGeo& gg, int z, int y,
                                            int zr, int yr, int t, const cplx<R>* v) {
-  constexpr int E = Plan<R, P>::E, TL = P / E;
+  constexpr int E = Plan<R, P, K>::E, TL = P / E;
   const int n = gg.nout;
   R* out = static_cast<R*>(F.out);
   if (F.kind != 0) {  // box output (C or the hole potential)
@@ -511,9 +511,9 @@ __device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const Grid
 }
 
 template <class R, int P>
-__global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
+__global__ void __launch_bounds__((Cfg<R, P, kPassIX>::WC * Cfg<R, P, kPassIX>::TL))
 k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
-  using C = Cfg<R, P>;
+  using C = Cfg<R, P, kPassIX>;
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WC;
   __shared__ R sre[W * P], sim[W * P];
@@ -531,12 +531,12 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int z = gg.olo + zr, y = gg.olo + yr;
   const T* row = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
   T v[E];
-  hermitian_inputs<R, P>([&](int k) { return row[k]; }, active, t, v);
+  hermitian_inputs<R, P, kPassIX>([&](int k) { return row[k]; }, active, t, v);
   LdsView<R> lds{sre, sim, 1, P, w};
   tws.put(stw);
-  fft_line<R, P, +1, false, true>(v, t, lds, stw);
+  fft_line<R, P, +1, false, true, kPassIX>(v, t, lds, stw);
   if (!active) return;
-  ix_outputs<R, P>(F, N, gg, z, y, zr, yr, t, v);
+  ix_outputs<R, P, kPassIX>(F, N, gg, z, y, zr, yr, t, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -554,7 +554,7 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
 #endif
 template <class R, int P>
 struct PlaneCfg {
-  static constexpr int E = Plan<R, P>::E;
+  static constexpr int E = Plan<R, P, kPassOther>::E;
   static constexpr int TL = P / E;
   static constexpr int H2 = P / 2;
   static constexpr int WL = (NMC_PLANE_THREADS / TL < H2) ? NMC_PLANE_THREADS / TL : H2;  // lines per round
@@ -585,7 +585,7 @@ __global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_fwd_xy(FieldTable ft,
     const LdsView<R> lds{sre, sim, 1, P, w};
     // the next round's inputs are loaded while this round is transformed
     T vn[E];
-    x_inputs<R, P, FULLN>(F, N, z, w < n ? w : 0, w < n, t, vn);
+    x_inputs<R, P, FULLN, kPassOther>(F, N, z, w < n ? w : 0, w < n, t, vn);
     for (int y0 = 0; y0 < n; y0 += WL) {
       const int y = y0 + w;
       const bool active = y < n;
@@ -594,13 +594,13 @@ __global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_fwd_xy(FieldTable ft,
       for (int q = 0; q < E / 2; ++q) v[q] = vn[q];
       if (y0 + WL < n) {  // uniform
         const int yn = y + WL;
-        x_inputs<R, P, FULLN>(F, N, z, yn < n ? yn : 0, yn < n, t, vn);
+        x_inputs<R, P, FULLN, kPassOther>(F, N, z, yn < n ? yn : 0, yn < n, t, vn);
       }
-      fft_line<R, P, -1, true, false>(v, t, lds, stw);
+      fft_line<R, P, -1, true, false, kPassOther>(v, t, lds, stw);
       if (active) {
 #pragma unroll
         for (int q = 0; q < E / 2; ++q) {
-          const T o = x_packed<R, P>(v, t, q);
+          const T o = x_packed<R, P, kPassOther>(v, t, q);
           pre[y * PS + t + TL * q] = o.x;
           pim[y * PS + t + TL * q] = o.y;
         }
@@ -621,7 +621,7 @@ __global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_fwd_xy(FieldTable ft,
         const int yy = t + TL * q;
         v[q] = (full_in || yy < n) ? T{pre[yy * PS + kx], pim[yy * PS + kx]} : T{0, 0};
       }
-      fft_line<R, P, -1, true, false>(v, t, lds, stw);
+      fft_line<R, P, -1, true, false, kPassOther>(v, t, lds, stw);
 #pragma unroll
       for (int q = 0; q < E; ++q) Bz[(size_t)(t + TL * q) * H2 + kx] = v[q];
     }
@@ -662,7 +662,7 @@ __global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_inv_yx(FieldTable ft,
 #pragma unroll
         for (int q = 0; q < E; ++q) vn[q] = Bz[(size_t)(t + TL * q) * H2 + kx + WL];
       }
-      fft_line<R, P, +1, false, true>(v, t, lds, stw);
+      fft_line<R, P, +1, false, true, kPassOther>(v, t, lds, stw);
 #pragma unroll
       for (int q = 0; q < E / 2; ++q) {
         const int yr = t + TL * q - gg.olo;
@@ -682,9 +682,9 @@ __global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_inv_yx(FieldTable ft,
       const bool active = yr < n;
       const int yc = active ? yr : 0;
       T v[E];
-      hermitian_inputs<R, P>([&](int k) { return T{pre[yc * PS + k], pim[yc * PS + k]}; }, active, t, v);
-      fft_line<R, P, +1, false, true>(v, t, lds, stw);
-      if (active) ix_outputs<R, P>(F, N, gg, z, gg.olo + yr, zr, yr, t, v);
+      hermitian_inputs<R, P, kPassOther>([&](int k) { return T{pre[yc * PS + k], pim[yc * PS + k]}; }, active, t, v);
+      fft_line<R, P, +1, false, true, kPassOther>(v, t, lds, stw);
+      if (active) ix_outputs<R, P, kPassOther>(F, N, gg, z, gg.olo + yr, zr, yr, t, v);
     }
   }
 }
@@ -888,10 +888,10 @@ __global__ void __launch_bounds__(256) k_carry(CarryTable tab, int N, int n0) {
 // octant [0, P/2]^3 suffice: each line of P values is rebuilt by even
 // extension, transformed, and the real parts of k = 0..P/2 are kept.
 template <int P>
-__global__ void __launch_bounds__((Cfg<double, P>::WC * Cfg<double, P>::TL))
+__global__ void __launch_bounds__((Cfg<double, P, kPassOther>::WC * Cfg<double, P, kPassOther>::TL))
 k_green(int pass, double beta, const double2* tw, const double* __restrict__ src,
         double* __restrict__ dst) {
-  using C = Cfg<double, P>;
+  using C = Cfg<double, P, kPassOther>;
   constexpr int E = C::E, TL = C::TL, W = C::WC, H = P / 2 + 1;
   __shared__ double sre[W * P], sim[W * P];
   __shared__ double2 stw[P];
@@ -919,7 +919,7 @@ k_green(int pass, double beta, const double2* tw, const double* __restrict__ src
     v[q] = double2{val, 0};
   }
   LdsView<double> lds{sre, sim, 1, P, w};
-  fft_line<double, P, -1, false, false>(v, t, lds, stw);
+  fft_line<double, P, -1, false, false, kPassOther>(v, t, lds, stw);
   if (!active) return;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
@@ -942,7 +942,7 @@ __global__ void k_round_f32(const double* __restrict__ in, float* __restrict__ o
 // Reorder the octant [kz][ky][kx] into gz[kyp][tile][kzp][w] and gn[kyp][kzp].
 template <class R, int P>
 __global__ void k_green_layout(const double* __restrict__ oct, R* __restrict__ gz, R* __restrict__ gn) {
-  constexpr int H = P / 2 + 1, W = Cfg<R, P>::WZ, NT = (P / 2) / W;
+  constexpr int H = P / 2 + 1, W = Cfg<R, P, kPassZ>::WZ, NT = (P / 2) / W;
   const size_t n = (size_t)H * NT * H * W;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -957,10 +957,10 @@ __global__ void k_green_layout(const double* __restrict__ oct, R* __restrict__ g
 
 // Diagnostic: batched unpruned 1-D FFT of contiguous lines.
 template <class R, int P, int DIR>
-__global__ void __launch_bounds__((Cfg<R, P>::WC * Cfg<R, P>::TL))
+__global__ void __launch_bounds__((Cfg<R, P, kPassOther>::WC * Cfg<R, P, kPassOther>::TL))
 k_fft_lines(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out, int nlines,
             const cplx<R>* tw) {
-  using C = Cfg<R, P>;
+  using C = Cfg<R, P, kPassOther>;
   constexpr int E = C::E, TL = C::TL, W = C::WC;
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
@@ -973,7 +973,7 @@ k_fft_lines(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out, int nline
   for (int q = 0; q < E; ++q)
     v[q] = active ? in[(size_t)line * P + t + TL * q] : cplx<R>{0, 0};
   LdsView<R> lds{sre, sim, 1, P, w};
-  fft_line<R, P, DIR, false, false>(v, t, lds, stw);
+  fft_line<R, P, DIR, false, false, kPassOther>(v, t, lds, stw);
   if (!active) return;
 #pragma unroll
   for (int q = 0; q < E; ++q) out[(size_t)line * P + t + TL * q] = v[q];
@@ -1001,7 +1001,7 @@ template <class R>
 hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
-    using C = Cfg<R, PP>;
+    using C = Cfg<R, PP, kPassX>;
     dim3 grid((g.n * g.n + C::WC - 1) / C::WC, g.nf);
     if (g.N == PP / 2)
       hipLaunchKernelGGL((k_fwd_x<R, PP, true>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
@@ -1014,7 +1014,7 @@ template <class R>
 hipError_t launch_fwd_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
-    using C = Cfg<R, PP>;
+    using C = Cfg<R, PP, kPassY>;
     dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
     if (g.N == PP / 2)
       hipLaunchKernelGGL((k_fwd_y<R, PP, true>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
@@ -1027,7 +1027,7 @@ template <class R>
 hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
-    using C = Cfg<R, PP>;
+    using C = Cfg<R, PP, kPassZ>;
     dim3 grid(((PP / 2) / C::WZ) * (PP / 2), g.nf);
     if (g.N == PP / 2)
       hipLaunchKernelGGL((k_z<R, PP, true>), grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
@@ -1040,7 +1040,7 @@ template <class R>
 hipError_t launch_inv_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
-    using C = Cfg<R, PP>;
+    using C = Cfg<R, PP, kPassIY>;
     dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
     if (g.N == PP / 2)
       hipLaunchKernelGGL((k_inv_y<R, PP, true>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
@@ -1053,7 +1053,7 @@ template <class R>
 hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
-    using C = Cfg<R, PP>;
+    using C = Cfg<R, PP, kPassIX>;
     dim3 grid((g.n * g.n + C::WC - 1) / C::WC, g.nf);
     hipLaunchKernelGGL((k_inv_x<R, PP>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
   });
@@ -1135,7 +1135,7 @@ hipError_t launch_green(int P, double beta, const double2* tw, double* t1, doubl
                         hipStream_t s) {
   return dispatch_p(P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
-    using C = Cfg<double, PP>;
+    using C = Cfg<double, PP, kPassOther>;
     constexpr int H = PP / 2 + 1;
     dim3 grid((H * H + C::WC - 1) / C::WC);
     dim3 block(C::WC * C::TL);
@@ -1176,7 +1176,7 @@ hipError_t launch_fft_lines(const void* in, void* out, int P, int nlines, int di
   using T = cplx<R>;
   return dispatch_p(P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
-    using C = Cfg<R, PP>;
+    using C = Cfg<R, PP, kPassOther>;
     dim3 grid((nlines + C::WC - 1) / C::WC), block(C::WC * C::TL);
     if (dir < 0)
       hipLaunchKernelGGL((k_fft_lines<R, PP, -1>), grid, block, 0, s, (const T*)in, (T*)out,
