@@ -197,31 +197,88 @@ __device__ __forceinline__ cplx<R> x_packed(const cplx<R>* v, int t, int q) {
   return (t == 0 && q == 0) ? cplx<R>{v[0].x, v[E / 2].x} : v[q];
 }
 
-template <class R, int P, bool FULLN>
+// Value x of the lane `src` of this wavefront (a 32-bit lane permute through
+// the LDS crossbar; no LDS allocation, no barrier).
+__device__ __forceinline__ float lane_read(float x, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(x)));
+}
+__device__ __forceinline__ double lane_read(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// PAIRS: two real lines a, b per complex transform: z = a + i b,
+// Z = FFT(z), A[k] = (Z[k] + conj Z[P-k]) / 2, B[k] = (Z[k] - conj Z[P-k]) / (2i).
+// The point P - k of thread t's point k = t + TL q sits in thread TL - t,
+// slot E-1-q (thread 0 holds its own), read across lanes; the TL threads of a
+// line are consecutive lanes of one wavefront.  Otherwise one line per
+// transform (more workgroups; measured faster for FP32 below N = 128).
+template <class R, int P, bool FULLN, bool PAIRS>
 __global__ void __launch_bounds__((Cfg<R, P, kPassX>::WC * Cfg<R, P, kPassX>::TL))
 k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassX>;
   using T = cplx<R>;
-  constexpr int E = C::E, TL = C::TL, W = C::WC;
+  constexpr int E = C::E, TL = C::TL, W = C::WC, LPW = PAIRS ? 2 : 1;
+  static_assert(64 % TL == 0, "a line's threads must share a wavefront");
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
   const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = FULLN ? P / 2 : g.N, n = grid_geo(F.kind, N).nin;
-  if ((int)blockIdx.x * W >= n * n) return;  // uniform: a smaller grid of a mixed launch
+  const int nunits = n * n / LPW;  // n is even: the two lines of a pair share z
+  if ((int)blockIdx.x * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
-  const int line = blockIdx.x * W + w;
-  const bool active = line < n * n;
-  const int z = active ? line / n : 0, y = active ? line % n : 0;
-  T v[E];
-  x_inputs<R, P, FULLN, kPassX>(F, N, z, y, active, t, v);
+  const int unit = blockIdx.x * W + w;
+  const bool active = unit < nunits;
+  const int line = active ? LPW * unit : 0;
+  const int z = line / n, y = line % n;
+  T va[E], v[E];
+  x_inputs<R, P, FULLN, kPassX>(F, N, z, y, active, t, va);
+  if constexpr (PAIRS) {
+    T vb[E];
+    x_inputs<R, P, FULLN, kPassX>(F, N, z, y + 1, active, t, vb);
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) v[q] = T{va[q].x, vb[q].x};
+  } else {
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) v[q] = va[q];
+  }
   LdsView<R> lds{sre, sim, 1, P, w};
   tws.put(stw);
   fft_line<R, P, -1, true, false, kPassX>(v, t, lds, stw);
-  if (active) {
-    T* A = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
+  if constexpr (!PAIRS) {
+    if (active) {
+      T* A = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
 #pragma unroll
-    for (int q = 0; q < E / 2; ++q) A[t + TL * q] = x_packed<R, P, kPassX>(v, t, q);
+      for (int q = 0; q < E / 2; ++q) A[t + TL * q] = x_packed<R, P, kPassX>(v, t, q);
+    }
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const int partner = (lane - t) + ((TL - t) & (TL - 1));
+  T zm[E / 2];
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const T o = v[E - 1 - q];
+    const T p = T{lane_read(o.x, partner), lane_read(o.y, partner)};
+    zm[q] = t == 0 ? v[(E - q) % E] : p;
+  }
+  if (!active) return;
+  T* Aa = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
+  T* Ab = Aa + P / 2;
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const T zk = v[q], m = zm[q];
+    T a = T{(R)0.5 * (zk.x + m.x), (R)0.5 * (zk.y - m.y)};
+    T b = T{(R)0.5 * (zk.y + m.y), (R)0.5 * (m.x - zk.x)};
+    if (t == 0 && q == 0) {  // DC and Nyquist are real: pack them
+      a = T{v[0].x, v[E / 2].x};
+      b = T{v[0].y, v[E / 2].y};
+    }
+    Aa[t + TL * q] = a;
+    Ab[t + TL * q] = b;
   }
 }
 
@@ -510,12 +567,17 @@ __device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const Grid
   }
 }
 
-template <class R, int P>
+// PAIRS: two output lines a, b per complex transform: with A, B their half
+// spectra (Hermitian), Z[k] = A[k] + i B[k] for all k and IFFT(Z) = a + i b.
+// Otherwise one line per transform (its imaginary part unused), which keeps
+// twice the workgroups and half the epilogue per thread (measured faster for
+// the full grids' carry epilogue below N = 256).
+template <class R, int P, bool PAIRS>
 __global__ void __launch_bounds__((Cfg<R, P, kPassIX>::WC * Cfg<R, P, kPassIX>::TL))
 k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassIX>;
   using T = cplx<R>;
-  constexpr int E = C::E, TL = C::TL, W = C::WC;
+  constexpr int E = C::E, TL = C::TL, W = C::WC, LPW = PAIRS ? 2 : 1;  // lines per transform
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
   const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
@@ -523,20 +585,51 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int N = g.N;
   const GridGeo gg = grid_geo(F.kind, N);
   const int n = gg.nout;
-  if ((int)blockIdx.x * W >= n * n) return;  // uniform: a smaller grid of a mixed launch
+  const int nunits = n * n / LPW;  // n is even: the two lines of a pair share z
+  if ((int)blockIdx.x * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
-  const int line = blockIdx.x * W + w;
-  const bool active = line < n * n;
-  const int zr = active ? line / n : 0, yr = active ? line % n : 0;  // within the output box
+  const int unit = blockIdx.x * W + w;
+  const bool active = unit < nunits;
+  const int line = active ? LPW * unit : 0;
+  const int zr = line / n, yr = line % n;  // within the output box
   const int z = gg.olo + zr, y = gg.olo + yr;
-  const T* row = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
+  const T* ra = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
+  const T* rb = ra + P / 2;
+  // packed half spectra: k = 0 holds the real DC (.x) and Nyquist (.y) values;
+  // every load is issued without a branch (inactive units read row 0 and drop it)
   T v[E];
-  hermitian_inputs<R, P, kPassIX>([&](int k) { return row[k]; }, active, t, v);
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int k = t + TL * q;
+    T a = ra[k], b = PAIRS ? rb[k] : T{0, 0};
+    if (k == 0) {
+      a.y = 0;
+      b.y = 0;
+    }
+    v[q] = active ? T{a.x - b.y, a.y + b.x} : T{0, 0};
+  }
+#pragma unroll
+  for (int q = E / 2; q < E; ++q) {
+    const int kk = P - (t + TL * q);  // in (0, P/2]
+    const int idx = kk == P / 2 ? 0 : kk;
+    T a = ra[idx], b = PAIRS ? rb[idx] : T{0, 0};
+    if (kk == P / 2) {
+      a = T{a.y, 0};
+      b = T{b.y, 0};
+    }
+    v[q] = active ? T{a.x + b.y, b.x - a.y} : T{0, 0};  // conj(A) + i conj(B)
+  }
   LdsView<R> lds{sre, sim, 1, P, w};
   tws.put(stw);
   fft_line<R, P, +1, false, true, kPassIX>(v, t, lds, stw);
   if (!active) return;
   ix_outputs<R, P, kPassIX>(F, N, gg, z, y, zr, yr, t, v);
+  if constexpr (PAIRS) {
+    T vb[E / 2];
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) vb[q] = T{v[q].y, 0};
+    ix_outputs<R, P, kPassIX>(F, N, gg, z, y + 1, zr, yr + 1, t, vb);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -997,16 +1090,26 @@ static hipError_t dispatch_p(int P, F&& f) {
   return hipGetLastError();
 }
 
+// Line pairs per transform in the x passes: not for FP32 below N = 128 (there
+// the twice larger grid of single-line workgroups measured faster).
+template <class R>
+bool x_pairs(int N) {
+  return sizeof(R) == 8 || N >= 128;
+}
+
 template <class R>
 hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  const bool pairs = x_pairs<R>(g.N);
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassX>;
-    dim3 grid((g.n * g.n + C::WC - 1) / C::WC, g.nf);
-    if (g.N == PP / 2)
-      hipLaunchKernelGGL((k_fwd_x<R, PP, true>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
-    else
-      hipLaunchKernelGGL((k_fwd_x<R, PP, false>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+    const int units = pairs ? g.n * g.n / 2 : g.n * g.n;
+    dim3 grid((units + C::WC - 1) / C::WC, g.nf), block(C::WC * C::TL);
+    const bool full = g.N == PP / 2;
+    if (pairs && full) hipLaunchKernelGGL((k_fwd_x<R, PP, true, true>), grid, block, 0, s, ft, g, tb);
+    else if (pairs) hipLaunchKernelGGL((k_fwd_x<R, PP, false, true>), grid, block, 0, s, ft, g, tb);
+    else if (full) hipLaunchKernelGGL((k_fwd_x<R, PP, true, false>), grid, block, 0, s, ft, g, tb);
+    else hipLaunchKernelGGL((k_fwd_x<R, PP, false, false>), grid, block, 0, s, ft, g, tb);
   });
 }
 
@@ -1051,11 +1154,22 @@ hipError_t launch_inv_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
 
 template <class R>
 hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  // pairs of lines per transform, except for full grids below N = 256 (their
+  // carry epilogue) and where x_pairs says no
+  bool pairs = g.N >= 256;
+  if (!pairs && x_pairs<R>(g.N)) {
+    pairs = true;
+    for (int k = 0; k < g.nf; ++k) pairs = pairs && ft.f[k].kind != 0;
+  }
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassIX>;
-    dim3 grid((g.n * g.n + C::WC - 1) / C::WC, g.nf);
-    hipLaunchKernelGGL((k_inv_x<R, PP>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+    const int units = pairs ? g.n * g.n / 2 : g.n * g.n;
+    dim3 grid((units + C::WC - 1) / C::WC, g.nf);
+    if (pairs)
+      hipLaunchKernelGGL((k_inv_x<R, PP, true>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+    else
+      hipLaunchKernelGGL((k_inv_x<R, PP, false>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
   });
 }
 
