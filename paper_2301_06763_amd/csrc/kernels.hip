@@ -317,6 +317,24 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   for (int q = 0; q < E; ++q) B[(size_t)(t + TL * q) * (P / 2)] = v[q];
 }
 
+// Work unit (row pair p, tile) and grid f of z-pass block b.  Consecutive
+// blocks are dispatched to the 8 XCDs in turn, each with its own L2; the
+// remap gives every XCD all grids of a unit back to back (the unit's spectrum
+// values are then read from HBM once per XCD, not once per grid) and, where
+// a tile's column run is half a 128-byte line (TP = 2), both tiles of the
+// line.  Needs U (units per grid) to be a multiple of 8 TP; else identity.
+__device__ __forceinline__ void z_unit(int b, int U, int nf, int TP, int& u, int& f) {
+  if (U % (8 * TP) != 0) {
+    u = b % U;
+    f = b / U;
+    return;
+  }
+  const int x = b % 8, s = b / 8;
+  f = s % nf;
+  const int j = s / nf;
+  u = ((j / TP) * 8 + x) * TP + j % TP;
+}
+
 // ---------------------------------------------------------------------------
 // Z pass: forward along z (inputs z >= n zero), multiply by the real Green
 // spectrum times the level scale, inverse along z, keep rows z < n.
@@ -332,13 +350,16 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ R sre[2 * W * P], sim[2 * W * P];
   __shared__ cplx<R> stw[P];
   const TwStage<R, P, 2 * C::WZ * C::TL> tws(tb.tw);
-  const FieldDesc& F = ft.f[blockIdx.y];
+  constexpr int TP = W * (int)sizeof(T) < 128 ? 2 : 1;  // tiles sharing a 128-byte line
+  int unit, f;
+  z_unit(blockIdx.x, NT * (P / 2), g.nf, TP, unit, f);
+  const FieldDesc& F = ft.f[f];
   const bool full_in = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks on loads
   const bool full = FULLN && F.kind == 0;     // nout = N = P/2 as well
   const GridGeo gg = grid_geo(F.kind, FULLN ? P / 2 : g.N);
   const int n = gg.nin;
   const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
-  const int tile = blockIdx.x % NT, p = blockIdx.x / NT;
+  const int tile = unit % NT, p = unit / NT;
   const int ky = side == 0 ? p : (p == 0 ? P / 2 : P - p);
   const int kx = tile * W + w;
   const int kyp = ky <= P / 2 ? ky : P - ky;
@@ -1131,7 +1152,7 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassZ>;
-    dim3 grid(((PP / 2) / C::WZ) * (PP / 2), g.nf);
+    dim3 grid(((PP / 2) / C::WZ) * (PP / 2) * g.nf);  // one dimension: see z_unit
     if (g.N == PP / 2)
       hipLaunchKernelGGL((k_z<R, PP, true>), grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
     else
