@@ -176,7 +176,7 @@ __device__ __forceinline__ void fft_stages(cplx<R>* v, int t, const LdsView<R>& 
 }
 
 // Per-length plans: points per thread E and the radix sequence.  Narrow
-// plans hold E = 8 points per thread.  Wide plans (FP32, P >= 128) hold 16:
+// plans hold E = 8 points per thread.  Wide plans (P >= 128) hold 16:
 // one LDS exchange fewer and fewer twiddle products per point, for more
 // registers per thread.  Which passes take the wide plan was measured pass
 // by pass (kernels.hip); NMC_WIDE_PASSES is a bit mask over PassKind.
@@ -199,9 +199,15 @@ template <> struct WidePlan<128> { static constexpr int E = 16; template <class 
 template <> struct WidePlan<256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
 template <> struct WidePlan<512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
 
+#ifndef NMC_WIDE_PASSES_F64
+#define NMC_WIDE_PASSES_F64 ((1 << kPassY) | (1 << kPassZ))
+#endif
+// FP64 wide plans only up to P = 256: they need ~200 VGPRs (two waves per
+// SIMD), which the larger P = 512 tiles measured slower with.
 template <class R, int P, int K>
 constexpr bool wide_plan() {
-  return sizeof(R) == 4 && P >= 128 && ((NMC_WIDE_PASSES >> K) & 1) != 0;
+  if constexpr (sizeof(R) == 4) return P >= 128 && ((NMC_WIDE_PASSES >> K) & 1) != 0;
+  else return P >= 128 && P <= 256 && ((NMC_WIDE_PASSES_F64 >> K) & 1) != 0;
 }
 template <class R, int P, int K = kPassOther>
 struct Plan : std::conditional_t<wide_plan<R, P, K>(), WidePlan<P>, NarrowPlan<P>> {};

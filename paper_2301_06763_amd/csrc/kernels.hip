@@ -39,6 +39,9 @@ namespace nmc {
 #ifndef NMC_MIN_WAVES_F64
 #define NMC_MIN_WAVES_F64 4
 #endif
+#ifndef NMC_MIN_WAVES_F64_WIDE
+#define NMC_MIN_WAVES_F64_WIDE 1
+#endif
 template <class R, int P, int K>
 struct Cfg {
   static constexpr int E = Plan<R, P, K>::E;
@@ -57,7 +60,8 @@ struct Cfg {
   // resident waves per SIMD the register allocation must allow (FP32: 6,
   // i.e. 80 VGPRs and three z workgroups per CU, up to P = 128; at P = 256
   // the two-stream schedule ran faster with the unconstrained allocation)
-  static constexpr int MINW = sizeof(R) == 8 ? NMC_MIN_WAVES_F64 : P <= 128 ? NMC_MIN_WAVES_F32 : NMC_MIN_WAVES_F32_BIG;
+  static constexpr int MINW = sizeof(R) == 8 ? (E == 16 ? NMC_MIN_WAVES_F64_WIDE : NMC_MIN_WAVES_F64)
+                                             : P <= 128 ? NMC_MIN_WAVES_F32 : NMC_MIN_WAVES_F32_BIG;
   static_assert(WS >= 1 && WZ >= 1 && WC >= 1, "tile does not fit");
 };
 
