@@ -129,6 +129,16 @@ struct LdsView {
   }
 };
 
+// Twiddles of a stage from powers of the first one (FP64: trades LDS reads,
+// its limit, for vector products, which have room; FP32 keeps the table).
+#ifndef NMC_TWIDDLE_POWERS_F64
+#define NMC_TWIDDLE_POWERS_F64 1
+#endif
+template <class R>
+constexpr bool twiddle_powers() {
+  return sizeof(R) == 8 && NMC_TWIDDLE_POWERS_F64;
+}
+
 // One Stockham stage and, recursively, the following ones.
 //  P: line length, E: points per thread, DIR: -1 forward / +1 inverse,
 //  NS: product of radices already applied, FIRST: data comes from registers,
@@ -157,8 +167,22 @@ __device__ __forceinline__ void fft_stages(cplx<R>* v, int t, const LdsView<R>& 
     const int k = b & (NS - 1);
     if constexpr (NS > 1) {
       constexpr int STEP = P / (NS * RAD);
+      if constexpr (twiddle_powers<R>()) {
+        // w_i = w^i from w = w_1 by products of lower powers (depth
+        // log2 i + 1): one LDS read per butterfly instead of RAD - 1
+        cplx<R> w[RAD];
+        w[1] = tw[k * STEP];
 #pragma unroll
-      for (int i = 1; i < RAD; ++i) u[i] = c_mul_tw<DIR>(u[i], tw[i * k * STEP]);
+        for (int i = 2; i < RAD; ++i) {
+          const cplx<R> a = w[i / 2], b = w[i - i / 2];
+          w[i] = cplx<R>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+        }
+#pragma unroll
+        for (int i = 1; i < RAD; ++i) u[i] = c_mul_tw<DIR>(u[i], w[i]);
+      } else {
+#pragma unroll
+        for (int i = 1; i < RAD; ++i) u[i] = c_mul_tw<DIR>(u[i], tw[i * k * STEP]);
+      }
     }
     dft<RAD, DIR, (FIRST && PIN) ? RAD / 2 : RAD, (LAST && POUT) ? RAD / 2 : RAD>(u);
     if constexpr (LAST) {
