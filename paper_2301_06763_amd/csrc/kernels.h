@@ -115,6 +115,14 @@ struct Tables {
   const R* gn;
 };
 
+// Timing of the next kernel launch (profiling): when set, the next kernel a
+// launcher below enqueues records `start` as it begins and `stop` as it ends
+// (hipExtLaunchKernel), and the pair is cleared.  Per host thread.
+// take_next_launch_events clears a pair nothing consumed and says whether
+// there was one.
+void set_next_launch_events(hipEvent_t start, hipEvent_t stop);
+bool take_next_launch_events();
+
 // Forward passes and the fused z pass.
 template <class R> hipError_t launch_fwd_x(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 template <class R> hipError_t launch_fwd_y(const FieldTable&, PassGeom, Tables<R>, hipStream_t);

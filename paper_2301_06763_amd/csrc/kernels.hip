@@ -18,6 +18,7 @@
 // Layouts (complex, kx fastest): A[z][y][kx] (N x N x P/2), B[z][ky][kx]
 // (N x P x P/2).  Strided passes give each workgroup W adjacent kx columns,
 // so every global access is a run of W complex values.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1100,6 +1101,26 @@ k_fft_lines(const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out, int nline
 // ---------------------------------------------------------------------------
 // Host launchers.
 
+namespace {
+thread_local hipEvent_t g_next_start = nullptr, g_next_stop = nullptr;
+}
+void set_next_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_next_start = start;
+  g_next_stop = stop;
+}
+bool take_next_launch_events() {
+  const bool pending = g_next_start != nullptr;
+  g_next_start = g_next_stop = nullptr;
+  return pending;
+}
+// hipLaunchKernelGGL, with the pending timing events if any
+template <class K, class... Args>
+static void launch(K kernel, dim3 grid, dim3 block, unsigned shmem, hipStream_t s, Args... args) {
+  hipEvent_t a = g_next_start, b = g_next_stop;
+  g_next_start = g_next_stop = nullptr;
+  hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, a, b, 0, args...);
+}
+
 template <class F>
 static hipError_t dispatch_p(int P, F&& f) {
   switch (P) {
@@ -1131,10 +1152,10 @@ hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     const int units = pairs ? g.n * g.n / 2 : g.n * g.n;
     dim3 grid((units + C::WC - 1) / C::WC, g.nf), block(C::WC * C::TL);
     const bool full = g.N == PP / 2;
-    if (pairs && full) hipLaunchKernelGGL((k_fwd_x<R, PP, true, true>), grid, block, 0, s, ft, g, tb);
-    else if (pairs) hipLaunchKernelGGL((k_fwd_x<R, PP, false, true>), grid, block, 0, s, ft, g, tb);
-    else if (full) hipLaunchKernelGGL((k_fwd_x<R, PP, true, false>), grid, block, 0, s, ft, g, tb);
-    else hipLaunchKernelGGL((k_fwd_x<R, PP, false, false>), grid, block, 0, s, ft, g, tb);
+    if (pairs && full) launch(k_fwd_x<R, PP, true, true>, grid, block, 0, s, ft, g, tb);
+    else if (pairs) launch(k_fwd_x<R, PP, false, true>, grid, block, 0, s, ft, g, tb);
+    else if (full) launch(k_fwd_x<R, PP, true, false>, grid, block, 0, s, ft, g, tb);
+    else launch(k_fwd_x<R, PP, false, false>, grid, block, 0, s, ft, g, tb);
   });
 }
 
@@ -1145,9 +1166,9 @@ hipError_t launch_fwd_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     using C = Cfg<R, PP, kPassY>;
     dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
     if (g.N == PP / 2)
-      hipLaunchKernelGGL((k_fwd_y<R, PP, true>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+      launch(k_fwd_y<R, PP, true>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
     else
-      hipLaunchKernelGGL((k_fwd_y<R, PP, false>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+      launch(k_fwd_y<R, PP, false>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
   });
 }
 
@@ -1158,9 +1179,9 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
     using C = Cfg<R, PP, kPassZ>;
     dim3 grid(((PP / 2) / C::WZ) * (PP / 2) * g.nf);  // one dimension: see z_unit
     if (g.N == PP / 2)
-      hipLaunchKernelGGL((k_z<R, PP, true>), grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
+      launch(k_z<R, PP, true>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
     else
-      hipLaunchKernelGGL((k_z<R, PP, false>), grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
+      launch(k_z<R, PP, false>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
   });
 }
 
@@ -1171,9 +1192,9 @@ hipError_t launch_inv_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     using C = Cfg<R, PP, kPassIY>;
     dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
     if (g.N == PP / 2)
-      hipLaunchKernelGGL((k_inv_y<R, PP, true>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+      launch(k_inv_y<R, PP, true>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
     else
-      hipLaunchKernelGGL((k_inv_y<R, PP, false>), grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+      launch(k_inv_y<R, PP, false>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
   });
 }
 
@@ -1192,9 +1213,9 @@ hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     const int units = pairs ? g.n * g.n / 2 : g.n * g.n;
     dim3 grid((units + C::WC - 1) / C::WC, g.nf);
     if (pairs)
-      hipLaunchKernelGGL((k_inv_x<R, PP, true>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+      launch(k_inv_x<R, PP, true>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
     else
-      hipLaunchKernelGGL((k_inv_x<R, PP, false>), grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+      launch(k_inv_x<R, PP, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
   });
 }
 
@@ -1216,9 +1237,9 @@ hipError_t launch_fwd_xy(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStre
     if constexpr (PP <= kPlaneMaxP && PC::LDS <= kPlaneLdsMax) {
       dim3 grid(g.n, g.nf);
       if (g.N == PP / 2)
-        hipLaunchKernelGGL((k_fwd_xy<R, PP, true>), grid, dim3(PC::NTH), 0, s, ft, g, tb);
+        launch(k_fwd_xy<R, PP, true>, grid, dim3(PC::NTH), 0, s, ft, g, tb);
       else
-        hipLaunchKernelGGL((k_fwd_xy<R, PP, false>), grid, dim3(PC::NTH), 0, s, ft, g, tb);
+        launch(k_fwd_xy<R, PP, false>, grid, dim3(PC::NTH), 0, s, ft, g, tb);
     }
   });
 }
@@ -1231,9 +1252,9 @@ hipError_t launch_inv_yx(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStre
     if constexpr (PP <= kPlaneMaxP && PC::LDS <= kPlaneLdsMax) {
       dim3 grid(g.n, g.nf);
       if (g.N == PP / 2)
-        hipLaunchKernelGGL((k_inv_yx<R, PP, true>), grid, dim3(PC::NTH), 0, s, ft, g, tb);
+        launch(k_inv_yx<R, PP, true>, grid, dim3(PC::NTH), 0, s, ft, g, tb);
       else
-        hipLaunchKernelGGL((k_inv_yx<R, PP, false>), grid, dim3(PC::NTH), 0, s, ft, g, tb);
+        launch(k_inv_yx<R, PP, false>, grid, dim3(PC::NTH), 0, s, ft, g, tb);
     }
   });
 }
@@ -1241,7 +1262,7 @@ hipError_t launch_inv_yx(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStre
 template <class R>
 hipError_t launch_restrict(const R* fine, const R* fine_rc, R* rc, int N, hipStream_t s) {
   const int n = (N / 2) * (N / 2) * (N / 2);
-  hipLaunchKernelGGL(k_restrict<R>, dim3((n + 255) / 256), dim3(256), 0, s, fine, fine_rc, rc, N);
+  launch(k_restrict<R>, dim3((n + 255) / 256), dim3(256), 0, s, fine, fine_rc, rc, N);
   return hipGetLastError();
 }
 
@@ -1252,7 +1273,7 @@ hipError_t launch_pyramid(const PyramidTable& tab, int count, int N, int maxL, h
     const int S = pyramid_cube(N, k), nc = N / S;
     blocks += nc * nc * nc;
   }
-  hipLaunchKernelGGL(k_pyramid<R>, dim3(blocks, count), dim3(kPyramidThreads), 0, s, tab, N, maxL);
+  launch(k_pyramid<R>, dim3(blocks, count), dim3(kPyramidThreads), 0, s, tab, N, maxL);
   return hipGetLastError();
 }
 
@@ -1264,9 +1285,9 @@ hipError_t launch_carry(const CarryTable& tab, int count, int N, int n0, hipStre
   if (nl <= 0) return hipSuccess;
   // a launch is either all compensated or all plain (runtime groups them)
   if (sizeof(R) == 4 && tab.r[0].comp)
-    hipLaunchKernelGGL((k_carry<R, true>), dim3(per * nl, count), dim3(256), 0, s, tab, N, n0);
+    launch(k_carry<R, true>, dim3(per * nl, count), dim3(256), 0, s, tab, N, n0);
   else
-    hipLaunchKernelGGL((k_carry<R, false>), dim3(per * nl, count), dim3(256), 0, s, tab, N, n0);
+    launch(k_carry<R, false>, dim3(per * nl, count), dim3(256), 0, s, tab, N, n0);
   return hipGetLastError();
 }
 
@@ -1278,9 +1299,9 @@ hipError_t launch_green(int P, double beta, const double2* tw, double* t1, doubl
     constexpr int H = PP / 2 + 1;
     dim3 grid((H * H + C::WC - 1) / C::WC);
     dim3 block(C::WC * C::TL);
-    hipLaunchKernelGGL(k_green<PP>, grid, block, 0, s, 0, beta, tw, (const double*)nullptr, t1);
-    hipLaunchKernelGGL(k_green<PP>, grid, block, 0, s, 1, beta, tw, (const double*)t1, t2);
-    hipLaunchKernelGGL(k_green<PP>, grid, block, 0, s, 2, beta, tw, (const double*)t2, out);
+    launch(k_green<PP>, grid, block, 0, s, 0, beta, tw, (const double*)nullptr, t1);
+    launch(k_green<PP>, grid, block, 0, s, 1, beta, tw, (const double*)t1, t2);
+    launch(k_green<PP>, grid, block, 0, s, 2, beta, tw, (const double*)t2, out);
   });
 }
 
@@ -1299,13 +1320,13 @@ hipError_t launch_green_layout(int P, const double* octant, R* gz, R* gn, hipStr
   return dispatch_p(P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     const size_t n = (size_t)(PP / 2 + 1) * (PP / 2 + 1) * (PP / 2);
-    hipLaunchKernelGGL((k_green_layout<R, PP>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, octant,
+    launch(k_green_layout<R, PP>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, octant,
                        gz, gn);
   });
 }
 
 hipError_t launch_round_f32(const double* in, float* out, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_round_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+  launch(k_round_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
   return hipGetLastError();
 }
 
@@ -1318,10 +1339,10 @@ hipError_t launch_fft_lines(const void* in, void* out, int P, int nlines, int di
     using C = Cfg<R, PP, kPassOther>;
     dim3 grid((nlines + C::WC - 1) / C::WC), block(C::WC * C::TL);
     if (dir < 0)
-      hipLaunchKernelGGL((k_fft_lines<R, PP, -1>), grid, block, 0, s, (const T*)in, (T*)out,
+      launch(k_fft_lines<R, PP, -1>, grid, block, 0, s, (const T*)in, (T*)out,
                          nlines, (const T*)tw);
     else
-      hipLaunchKernelGGL((k_fft_lines<R, PP, +1>), grid, block, 0, s, (const T*)in, (T*)out,
+      launch(k_fft_lines<R, PP, +1>, grid, block, 0, s, (const T*)in, (T*)out,
                          nlines, (const T*)tw);
   });
 }

@@ -373,23 +373,31 @@ int validate(nmc_ctx* ctx, const Req& r, int refine) {
 // --- profiling -------------------------------------------------------------------
 
 struct ProfScope {
+  // The kernel of the enclosed launcher call records event a when it starts
+  // and b when it ends (nmc::set_next_launch_events), so the recorded time is
+  // the kernel's own duration; if the launcher launched nothing, the events
+  // are recorded on the stream around the call instead.
   nmc_ctx* ctx;
   hipStream_t s;
   int pass;
   double bytes;
-  hipEvent_t a = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
   ProfScope(nmc_ctx* c, hipStream_t st, int p, double by) : ctx(c), s(st), pass(p), bytes(by) {
-    if (ctx->profiling && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+    if (!ctx->profiling) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      if (a) (void)hipEventDestroy(a);
+      a = b = nullptr;
+      return;
+    }
+    nmc::set_next_launch_events(a, b);
   }
   ~ProfScope() {
     if (!a) return;
-    hipEvent_t b = nullptr;
-    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s) == hipSuccess) {
-      ctx->prof.push_back({pass, a, b, bytes});
-    } else {
-      (void)hipEventDestroy(a);
-      if (b) (void)hipEventDestroy(b);
+    if (nmc::take_next_launch_events()) {  // not consumed by a kernel launch
+      (void)hipEventRecord(a, s);
+      (void)hipEventRecord(b, s);
     }
+    ctx->prof.push_back({pass, a, b, bytes});
   }
 };
 
