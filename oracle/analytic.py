@@ -113,6 +113,25 @@ def ellipsoid(x, y, z, a, rho=1.0, centre=(0.0, 0.0, 0.0), G=1.0):
     return -math.pi * G * rho * a[0] * a[1] * a[2] * (I - x * x * Ax - y * y * Ay - z * z * Az)
 
 
+def ellipsoid_acceleration(x, y, z, a, rho=1.0, centre=(0.0, 0.0, 0.0), G=1.0):
+    """g = -grad Phi of the homogeneous ellipsoid of `ellipsoid`, as
+    (g_x, g_y, g_z).  Differentiating under the integral, the term from the
+    lower limit lam(x) vanishes (its integrand is zero on the confocal
+    surface), so g_i = -2 pi G rho a1 a2 a3 x_i (2/3) R_D(a_j^2+lam,
+    a_k^2+lam, a_i^2+lam)."""
+    x = np.asarray(x, dtype=np.float64) - centre[0]
+    y = np.asarray(y, dtype=np.float64) - centre[1]
+    z = np.asarray(z, dtype=np.float64) - centre[2]
+    x, y, z = np.broadcast_arrays(x, y, z)
+    lam = _ellipsoid_lambda(x, y, z, a)
+    A = [a[0] ** 2 + lam, a[1] ** 2 + lam, a[2] ** 2 + lam]
+    Ax = (2.0 / 3.0) * elliprd(A[1], A[2], A[0])
+    Ay = (2.0 / 3.0) * elliprd(A[2], A[0], A[1])
+    Az = (2.0 / 3.0) * elliprd(A[0], A[1], A[2])
+    k = -2.0 * math.pi * G * rho * a[0] * a[1] * a[2]
+    return k * x * Ax, k * y * Ay, k * z * Az
+
+
 def ellipsoid_index_sum(a):
     """Sum of the dimensionless interior coefficients a1 a2 a3 int du /((a_i^2+u) Delta)
     over i; equals 2 for any ellipsoid (a classical identity)."""

@@ -26,7 +26,7 @@ array index l = m - 1):
   Omega^n is Phi^n plus the hole potentials of all coarser grids interpolated
   onto it.
 
-Readings where the paper is silent or ambiguous (listed in the design doc too):
+Readings where the paper is silent or ambiguous:
 
 * R1 self-cell value: beta = 3 ln(2 + sqrt 3) - pi/2 (closed form of Eq. 13).
 * R2 off-diagonal kernel: point-to-point 1/|r_t - r_s| between centres.
@@ -41,6 +41,13 @@ Readings where the paper is silent or ambiguous (listed in the design doc too):
   parent c = N/4 + floor(f/2), neighbour offset s = +1 for odd f, -1 for
   even f, per axis; A(f) = 3/4 S(c) + 1/4 S(c + s) (c, s 3-vectors).
 * R11 carry: cascaded, A_n = Prolong(A_{n-1} + Phi^{n-1}_hole).
+* R16 acceleration at the outer faces of the coarsest grid: the paper takes
+  boundary potentials there from the analytic solution (Sect. 2, OiCG
+  tests); the convolution method has no ghost values, so the second-order
+  one-sided difference is used on those faces.
+* R17 acceleration at covered cells (inside the child region) uses the
+  level's own potential; method B applies to coarse cells outside the child
+  region whose stencil neighbour lies inside it.
 """
 from __future__ import annotations
 
@@ -318,3 +325,89 @@ def solve_points(rho: np.ndarray, h0: float, pts, G: float = 1.0, *, restrict: b
             v += carry(l, (z, y, x))
         res.append(v)
     return np.array(res)
+
+
+# ---------------------------------------------------------------------------
+# Gravitational acceleration (Sect. 2, the six-point central stencil for
+# g = -grad Phi, and Appendix A for the cells next to a coarse-fine
+# interface).
+
+
+def _ghost_from_coarse(Pc: np.ndarray, fz, fy, fx) -> np.ndarray:
+    """Potential at fine cells (fz, fy, fx) of the next finer level, which may
+    lie one cell outside that level, from the coarse level's potential Pc by
+    the diagonal 3/4-1/4 rule of Eqs. (3)-(6): per axis the parent
+    c = N/4 + floor(f/2) and the neighbour c + s, s = +1 for odd f, -1 for
+    even f."""
+    N = Pc.shape[0]
+
+    def axis(f):
+        f = np.asarray(f)
+        c = N // 4 + np.floor_divide(f, 2)
+        s = np.where(np.mod(f, 2) == 1, 1, -1)
+        return c, c + s
+
+    cz, sz = axis(fz)
+    cy, sy = axis(fy)
+    cx, sx = axis(fx)
+    return 0.75 * Pc[cz, cy, cx] + 0.25 * Pc[sz, sy, sx]
+
+
+def acceleration(phi: np.ndarray, h0: float) -> np.ndarray:
+    """g = -grad Phi on every level of a nested mesh, shape [L, 3, N, N, N]
+    with components (g_x, g_y, g_z) and x the fastest array axis.
+
+    Interior cells: g_x = -(Phi[i+1] - Phi[i-1]) / (2 dx) (Sect. 2).
+    Appendix A, method A: at a level's outermost cells (level >= 1) the
+    missing neighbour is the boundary value interpolated from the next
+    coarser level by Eqs. (3)-(6).  Method B: at a coarse cell next to the
+    finer grid, a neighbour inside the child region takes the arithmetic
+    mean of the finer level's potential over the 2^3 cells it covers.  The
+    coarsest level's outer faces use the second-order one-sided difference
+    (reading R16); covered cells use the level's own values (reading R17)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    L, N = phi.shape[0], phi.shape[1]
+    lo, hi = N // 4, 3 * N // 4
+    out = np.zeros((L, 3, N, N, N), dtype=np.float64)
+    idx = np.arange(N)
+    Z, Y, X = np.meshgrid(idx, idx, idx, indexing="ij")
+    inside = (Z >= lo) & (Z < hi) & (Y >= lo) & (Y < hi) & (X >= lo) & (X < hi)
+    for l in range(L):
+        h = level_spacing(h0, l)
+        P = phi[l]
+        mean_fine = None
+        if l + 1 < L:
+            n2 = N // 2
+            mean_fine = phi[l + 1].reshape(n2, 2, n2, 2, n2, 2).mean(axis=(1, 3, 5))
+        for comp, ax in ((0, 2), (1, 1), (2, 0)):
+            vals = []
+            for step in (+1, -1):
+                nb = [Z.copy(), Y.copy(), X.copy()]
+                nb[ax] = nb[ax] + step
+                inrange = (nb[ax] >= 0) & (nb[ax] < N)
+                cl = [np.clip(a, 0, N - 1) for a in nb]
+                v = P[cl[0], cl[1], cl[2]]
+                if l >= 1:  # method A: boundary value from the coarser level
+                    ghost = np.zeros_like(v)
+                    m = ~inrange
+                    ghost[m] = _ghost_from_coarse(phi[l - 1], nb[0][m], nb[1][m], nb[2][m])
+                    v = np.where(inrange, v, ghost)
+                if mean_fine is not None:  # method B
+                    nb_in = inrange & (cl[0] >= lo) & (cl[0] < hi) & (cl[1] >= lo) & (cl[1] < hi) & \
+                        (cl[2] >= lo) & (cl[2] < hi)
+                    use = nb_in & ~inside
+                    mf = mean_fine[np.clip(cl[0] - lo, 0, N // 2 - 1), np.clip(cl[1] - lo, 0, N // 2 - 1),
+                                   np.clip(cl[2] - lo, 0, N // 2 - 1)]
+                    v = np.where(use, mf, v)
+                vals.append(v)
+            g = -(vals[0] - vals[1]) / (2.0 * h)
+            if l == 0:  # outer faces of the coarsest grid: one-sided (R16)
+                sl0 = [slice(None)] * 3
+                sl1 = [slice(None)] * 3
+                sl2 = [slice(None)] * 3
+                sl0[ax], sl1[ax], sl2[ax] = 0, 1, 2
+                g[tuple(sl0)] = -(-3.0 * P[tuple(sl0)] + 4.0 * P[tuple(sl1)] - P[tuple(sl2)]) / (2.0 * h)
+                sl0[ax], sl1[ax], sl2[ax] = N - 1, N - 2, N - 3
+                g[tuple(sl0)] = -(3.0 * P[tuple(sl0)] - 4.0 * P[tuple(sl1)] + P[tuple(sl2)]) / (2.0 * h)
+            out[l, comp] = g
+    return out

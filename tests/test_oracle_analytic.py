@@ -95,14 +95,10 @@ def test_second_order_convergence():
     assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, (means, r1, r2)
 
 
-@pytest.mark.slow
-def test_paper_table3_ellipsoid_order_of_magnitude():
-    """Sect. 5, Table 3 (convolution row), loosely: oblate ellipsoid
-    0.5:1:1 on four nested grids of 128^3 in [-2.25, 2.25]^3.  The paper's
-    sampling and carry details are unstated, so only the order of magnitude
-    of the max and mean potential errors is checked."""
-    with open(os.path.join(GOLDEN, "table3_convolution.json")) as fh:
-        ref = json.load(fh)["ellipsoid_0.5_1_1"]
+@pytest.fixture(scope="module")
+def table_ellipsoid():
+    """Sect. 5 test problem: oblate ellipsoid 0.5:1:1 on four nested grids
+    of 128^3 in [-2.25, 2.25]^3, solved by the oracle."""
     N, L, B = 128, 4, 4.5
     h0 = B / N
     axes = (0.5, 1.0, 1.0)
@@ -110,7 +106,17 @@ def test_paper_table3_ellipsoid_order_of_magnitude():
     for l in range(L):
         Z, Y, X = _level_coords(N, h0 / 2 ** l)
         rho[l] = ((X / axes[0]) ** 2 + (Y / axes[1]) ** 2 + (Z / axes[2]) ** 2 <= 1.0).astype(float)
-    phi = oracle.solve(rho, h0)
+    return N, L, h0, axes, oracle.solve(rho, h0)
+
+
+@pytest.mark.slow
+def test_paper_table3_ellipsoid_order_of_magnitude(table_ellipsoid):
+    """Sect. 5, Table 3 (convolution row), loosely: the paper's sampling
+    and carry details are unstated, so only the order of magnitude of the
+    max and mean potential errors is checked."""
+    with open(os.path.join(GOLDEN, "table3_convolution.json")) as fh:
+        ref = json.load(fh)["ellipsoid_0.5_1_1"]
+    N, L, h0, axes, phi = table_ellipsoid
     errs = []
     for l in range(L):
         x = oracle.cell_centres(N, h0 / 2 ** l)
@@ -122,3 +128,38 @@ def test_paper_table3_ellipsoid_order_of_magnitude():
     e = np.concatenate(errs) * 100
     assert ref["max_percent"] / 10 < e.max() < ref["max_percent"] * 10, e.max()
     assert ref["mean_percent"] / 10 < e.mean() < ref["mean_percent"] * 10, e.mean()
+
+
+@pytest.mark.slow
+def test_paper_table4_ellipsoid_acceleration_order_of_magnitude(table_ellipsoid):
+    """Sect. 5, Table 4 (convolution row), loosely: err_g of the modulus of
+    the acceleration (six-point stencil, Appendix A methods A and B) on the
+    same plane as Table 3; order of magnitude of max and mean."""
+    with open(os.path.join(GOLDEN, "table4_convolution.json")) as fh:
+        ref = json.load(fh)["ellipsoid_0.5_1_1"]
+    N, L, h0, axes, phi = table_ellipsoid
+    g = oracle.acceleration(phi, h0)
+    errs = []
+    for l in range(L):
+        x = oracle.cell_centres(N, h0 / 2 ** l)
+        j = N // 2
+        Z, X = np.meshgrid(x, x, indexing="ij")
+        Y = np.full_like(X, x[j])
+        ga = np.sqrt(sum(c ** 2 for c in an.ellipsoid_acceleration(X, Y, Z, a=axes, rho=1.0)))
+        gn = np.sqrt((g[l][:, :, j, :] ** 2).sum(axis=0))
+        errs.append((np.abs(gn - ga) / ga).ravel())
+    e = np.concatenate(errs) * 100
+    assert ref["max_percent"] / 10 < e.max() < ref["max_percent"] * 10, e.max()
+    assert ref["mean_percent"] / 10 < e.mean() < ref["mean_percent"] * 10, e.mean()
+
+
+def test_ellipsoid_acceleration_is_the_gradient():
+    """The closed-form acceleration equals minus the central difference of
+    the closed-form potential, inside and outside the ellipsoid."""
+    axes = (0.3, 0.5, 0.7)
+    d = 1e-5
+    for p in RNG.uniform(-1.2, 1.2, size=(40, 3)):
+        g = np.array(an.ellipsoid_acceleration(*p, a=axes, rho=1.7, G=0.9))
+        num = np.array([-(an.ellipsoid(*(p + d * e), a=axes, rho=1.7, G=0.9)
+                          - an.ellipsoid(*(p - d * e), a=axes, rho=1.7, G=0.9)) / (2 * d) for e in np.eye(3)])
+        assert np.max(np.abs(g - num)) < 1e-7 * max(1.0, np.max(np.abs(g)))

@@ -296,3 +296,90 @@ def test_no_restrict_keeps_coarse_density():
     assert np.max(np.abs(a[0] - b[0])) > 1e-6
     # ... but the finest level's own convolution and the hole part do not
     assert np.max(np.abs(a[1] - b[1]) / np.abs(b[1])) < 1e-14
+
+
+# --- gravitational acceleration (Sect. 2 stencil, Appendix A methods A and B)
+
+def _field_on_levels(N, L, h0, f):
+    phi = np.zeros((L, N, N, N))
+    for l in range(L):
+        x = oracle.cell_centres(N, oracle.level_spacing(h0, l))
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        phi[l] = f(X, Y, Z)
+    return phi
+
+
+@pytest.mark.parametrize("N,L", [(8, 2), (12, 3), (16, 4)])
+def test_acceleration_exact_on_linear_potentials(N, L):
+    """A linear potential, sampled on every level at its cell centres, has
+    the constant acceleration -grad Phi on every cell of every level: the
+    central stencil, the one-sided outer faces, the method-A boundary values
+    (Eqs. 3-6 interpolate linear fields exactly) and the method-B averages
+    (the mean of the 2^3 finer cells is the value at the coarse centre) are
+    all exact for it."""
+    a, b, c = 0.3, -1.2, 0.7
+    h0 = 1.0 / N
+    g = oracle.acceleration(_field_on_levels(N, L, h0, lambda X, Y, Z: a * X + b * Y + c * Z + 2.0), h0)
+    assert np.max(np.abs(g[:, 0] + a)) < 1e-12
+    assert np.max(np.abs(g[:, 1] + b)) < 1e-12
+    assert np.max(np.abs(g[:, 2] + c)) < 1e-12
+
+
+def test_acceleration_exact_on_quadratics_away_from_interfaces():
+    """Central and second-order one-sided differences are exact for
+    quadratics, so away from the coarse-fine interfaces (where the
+    interpolations are only linear-exact) the stencil returns -grad Phi."""
+    N, L = 16, 3
+    h0 = 1.0 / N
+    g = oracle.acceleration(_field_on_levels(N, L, h0, lambda X, Y, Z: X ** 2 + 2 * Y ** 2 - 0.5 * Z ** 2 + X * Y), h0)
+    idx = np.arange(N)
+    Zi, Yi, Xi = np.meshgrid(idx, idx, idx, indexing="ij")
+    lo, hi = N // 4, 3 * N // 4
+    near_child = (Zi >= lo - 1) & (Zi <= hi) & (Yi >= lo - 1) & (Yi <= hi) & (Xi >= lo - 1) & (Xi <= hi)
+    inner = (Zi > 0) & (Zi < N - 1) & (Yi > 0) & (Yi < N - 1) & (Xi > 0) & (Xi < N - 1)
+    for l in range(L):
+        x = oracle.cell_centres(N, oracle.level_spacing(h0, l))
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        m = np.ones((N, N, N), bool)
+        if l < L - 1:
+            m &= ~near_child
+        if l >= 1:
+            m &= inner
+        assert m.sum() > 0
+        for got, want in ((g[l, 0], -(2 * X + Y)), (g[l, 1], -(4 * Y + X)), (g[l, 2], Z)):
+            assert np.max(np.abs(got - want)[m]) < 1e-11
+
+
+def test_acceleration_of_point_mass_is_newtonian():
+    """Unit mass split over the 8 finest cells around the origin (a cube of
+    eight point masses; restriction keeps it centred and cubic on every
+    level, so its potential is -G M / r up to O((h/r)^4)).  Away from faces
+    and interfaces the central stencil's relative error is (h/r)^2 at most
+    (Taylor bound for 1/r); at the outer faces (one-sided differences) and
+    the coarse-fine interfaces (methods A and B interpolate, so the
+    gradient there is first-order accurate) it stays below 12 % beyond six
+    cells from the mass."""
+    N, L = 16, 3
+    h0 = 1.0 / N
+    rho = np.zeros((L, N, N, N))
+    hL = oracle.level_spacing(h0, L - 1)
+    c = slice(N // 2 - 1, N // 2 + 1)
+    rho[L - 1, c, c, c] = 1.0 / 8 / hL ** 3
+    phi = oracle.solve(rho, h0, G=1.0)
+    g = oracle.acceleration(phi, h0)
+    idx = np.arange(N)
+    Zi, Yi, Xi = np.meshgrid(idx, idx, idx, indexing="ij")
+    lo, hi = N // 4, 3 * N // 4
+    near_child = (Zi >= lo - 1) & (Zi <= hi) & (Yi >= lo - 1) & (Yi <= hi) & (Xi >= lo - 1) & (Xi <= hi)
+    inner = (Zi > 0) & (Zi < N - 1) & (Yi > 0) & (Yi < N - 1) & (Xi > 0) & (Xi < N - 1)
+    for l in range(L):
+        h = oracle.level_spacing(h0, l)
+        x = oracle.cell_centres(N, h)
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        d = np.stack([X, Y, Z])
+        r = np.sqrt((d ** 2).sum(axis=0))
+        err = np.abs(g[l] + d / r ** 3).max(axis=0) * r ** 2
+        interior = inner & (~near_child if l < L - 1 else True) & (r > 4 * h)
+        assert interior.sum() > 0
+        assert np.all(err[interior] < 1.2 * (h / (r[interior] - h)) ** 2 + 2e-3), l
+        assert err[r > 6 * h].max() < 0.12, (l, err[r > 6 * h].max())
