@@ -82,6 +82,25 @@ def time_solves(ctx, rho, h0, steps, warmup, torch, flags=0):
     return out, (t1 - t0), prof, lat
 
 
+def time_acceleration(ctx, phi, h0, steps, torch):
+    """nmc_acceleration on a solved potential (a separate entry point, not part
+    of the solve step): kernel time per call from the library's per-pass
+    events, and its algorithmic bytes (potential read, three components
+    written)."""
+    g = ctx.acceleration(phi, h0)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(steps):
+        ctx.acceleration(phi, h0, out=g)
+    torch.cuda.synchronize()
+    st = ctx.profile_read()["acceleration"]
+    ctx.profile(False)
+    ms = st["total_ms"] / st["launches"]
+    gbs = st["bytes"] / st["launches"] / (ms * 1e-3) / 1e9
+    return {"avg_launch_ms": round(ms, 5), "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "algo_bytes_per_launch": int(st["bytes"] / st["launches"])}
+
+
 def pct(v, q):
     if not v:
         return None
@@ -259,9 +278,11 @@ def main():
     ctx = nmc.Context()
     res = {}
     outs = {}
+    accel = {}
     for tag, dt in (("f32", torch.float32), ("f64", torch.float64)):
         rho = w.rho.to(dt).contiguous()
         out, el, prof, lat = time_solves(ctx, rho, w.h0, args.steps, args.warmup, torch, args.flags)
+        accel[tag] = time_acceleration(ctx, out, w.h0, min(args.steps, 50), torch)
         outs[tag] = out.double()
         res[tag] = {"solves_per_s": args.steps / el, "ms_per_step": el / args.steps * 1e3,
                     "passes": pass_table(prof), "lat": lat, "prof": prof}
@@ -301,6 +322,9 @@ def main():
         "passes": prim["passes"],
         "fp32_vs_fp64": {"max_rel_err": err32["max"], "rms_rel_err": err32["rms"],
                          "per_level_max": err32["per_level_max"], "tolerance": 1e-5},
+        "acceleration": {"what": "nmc_acceleration on the solved potential (six-point stencil with the "
+                                 "interface rules of Appendix A); a separate call, not in the solve step",
+                         "f32": accel["f32"], "f64": accel["f64"]},
     }
     other = "f64" if args.dtype == "f32" else "f32"
     o = res[other]

@@ -181,6 +181,29 @@ int nmc_serve_stats_get(nmc_ctx* ctx, nmc_serve_stats* out);
 /* Block until every submitted request is complete. */
 int nmc_serve_drain(nmc_ctx* ctx);
 
+/* ---- Gravitational acceleration ------------------------------------------
+ * g = -grad Phi on every level of a nested-mesh potential (Sect. 2: the
+ * six-point central stencil, g_x = -(Phi[i+1] - Phi[i-1]) / (2 dx_m)), with
+ * the rules of Appendix A next to the coarse-fine interfaces: at a level's
+ * outermost cells (levels >= 2 in the paper's numbering) the missing
+ * neighbour is the boundary value interpolated from the next coarser level
+ * by Eqs. 3-6 (method A); at a coarse cell next to the finer grid, a
+ * neighbour inside the child region takes the arithmetic mean of the finer
+ * level's potential over the 2^3 cells it covers (method B).  The coarsest
+ * level's outer faces use the second-order one-sided difference; cells
+ * covered by a finer level use their own level's values.
+ *   phi: device, [L][N][N][N], x fastest, element type p (as written by
+ *        nmc_solve); read only.
+ *   g:   device, [L][3][N][N][N] (components x, y, z, each x fastest),
+ *        element type p; caller-owned; must not overlap phi.
+ *   N, L, h0: as for nmc_solve (h0 = coarsest cell width).
+ * Enqueued asynchronously on hip_stream; no workspace.  Errors: NMC_EINVAL
+ * (null or overlapping pointers, N % 4 != 0 or N < 4, L outside [1, 16],
+ * h0 not positive and finite, unknown precision), NMC_EUNSUPPORTED (N above
+ * 256), NMC_EDEVICE (launch failure). */
+int nmc_acceleration(nmc_ctx* ctx, const void* phi, void* g, int N, int L, double h0,
+                     nmc_precision p, void* hip_stream);
+
 /* ---- Diagnostics (same kernels as the solve path) --------------------- */
 
 /* Copy the cached real Green spectrum of period P = nmc_period(N) into
@@ -215,7 +238,8 @@ enum {
   NMC_PASS_IX_FULL = 7,
   /* fused plane passes (P <= 64, used in place of X+Y and I2+I1): */
   NMC_PASS_XY = 8, NMC_PASS_IYX_SECOND = 9, NMC_PASS_IYX_FULL = 10,
-  NMC_NUM_PASSES = 11
+  NMC_PASS_ACCEL = 11,    /* nmc_acceleration */
+  NMC_NUM_PASSES = 12
 };
 
 typedef struct {

@@ -152,6 +152,11 @@ hipError_t launch_pyramid(const PyramidTable&, int count, int N, int maxL, hipSt
 template <class R>
 hipError_t launch_carry(const CarryTable&, int count, int N, int n0, hipStream_t);
 
+// Gravitational acceleration of a solved nested potential phi [L][N][N][N]
+// into g [L][3][N][N][N] (six-point stencil, Appendix A methods A and B).
+template <class R>
+hipError_t launch_accel(const R* phi, R* g, int N, int L, double h0, hipStream_t);
+
 // Green spectrum, FP64: three separable passes over the even octant.
 hipError_t launch_green(int P, double beta, const double2* tw, double* t1, double* t2, double* out,
                         hipStream_t);

@@ -1002,6 +1002,86 @@ __global__ void __launch_bounds__(256) k_carry(CarryTable tab, int N, int n0) {
 }
 
 // ---------------------------------------------------------------------------
+// Gravitational acceleration g = -grad Phi on every level (Sect. 2, the
+// six-point central stencil), with the rules of Appendix A next to the
+// coarse-fine interfaces: a neighbour outside the level (level >= 1) is the
+// boundary value interpolated from the coarser level by Eqs. 3-6, diagonal
+// 3/4-1/4 rule (method A); a neighbour inside the child region of a cell
+// outside it takes the mean of the finer level's potential over the 2^3
+// cells it covers (method B).  The coarsest level's outer faces use the
+// second-order one-sided difference; covered cells use the level's own
+// values.  One thread per cell, all three components.
+template <class R>
+__device__ __forceinline__ R accel_neighbour(const R* __restrict__ P, const R* __restrict__ Pc,
+                                             const R* __restrict__ Pf, int N, int z, int y, int x,
+                                             bool centre_in) {
+  const int lo = N / 4, hi = 3 * N / 4;
+  const bool in_level = (unsigned)z < (unsigned)N && (unsigned)y < (unsigned)N && (unsigned)x < (unsigned)N;
+  if (!in_level) {  // method A (the caller never asks on the coarsest level)
+    auto par = [&](int f) { return N / 4 + (f >= 0 ? f / 2 : -1); };  // N/4 + floor(f/2), f >= -1
+    auto sgn = [&](int f) { return (f & 1) ? 1 : -1; };
+    const int cz = par(z), cy = par(y), cx = par(x);
+    const R a = Pc[((size_t)cz * N + cy) * N + cx];
+    const R b = Pc[((size_t)(cz + sgn(z)) * N + (cy + sgn(y))) * N + (cx + sgn(x))];
+    return (R)0.75 * a + (R)0.25 * b;
+  }
+  const bool n_in = z >= lo && z < hi && y >= lo && y < hi && x >= lo && x < hi;
+  if (Pf && n_in && !centre_in) {  // method B
+    const int fz = 2 * (z - lo), fy = 2 * (y - lo), fx = 2 * (x - lo);
+    R s = 0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) s += Pf[((size_t)(fz + a) * N + (fy + b)) * N + (fx + c)];
+    return s * (R)0.125;
+  }
+  return P[((size_t)z * N + y) * N + x];
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_accel(const R* __restrict__ phi, R* __restrict__ g, int N, int L,
+                                               double h0) {
+  const size_t n3 = (size_t)N * N * N;
+  const int l = blockIdx.y;
+  const size_t id = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n3) return;
+  const int x = (int)(id % N), y = (int)(id / N % N), z = (int)(id / ((size_t)N * N));
+  const R* P = phi + (size_t)l * n3;
+  const R* Pc = l > 0 ? P - n3 : nullptr;
+  const R* Pf = l + 1 < L ? P + n3 : nullptr;
+  const int lo = N / 4, hi = 3 * N / 4;
+  const bool centre_in = z >= lo && z < hi && y >= lo && y < hi && x >= lo && x < hi;
+  const R h = (R)ldexp(h0, -l);
+  const R inv2h = (R)1 / (2 * h);
+  const int c[3] = {x, y, z};
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) {
+    const int i = c[comp];
+    R gv;
+    if (l == 0 && (i == 0 || i == N - 1)) {  // coarsest outer face: one-sided
+      const int d = i == 0 ? 1 : -1;
+      int q1[3] = {x, y, z}, q2[3] = {x, y, z};
+      q1[comp] += d;
+      q2[comp] += 2 * d;
+      const R p0 = P[id];
+      const R p1 = P[((size_t)q1[2] * N + q1[1]) * N + q1[0]];
+      const R p2 = P[((size_t)q2[2] * N + q2[1]) * N + q2[0]];
+      gv = -(R)d * ((R)-3 * p0 + (R)4 * p1 - p2) * inv2h;
+    } else {
+      int qp[3] = {x, y, z}, qm[3] = {x, y, z};
+      qp[comp] += 1;
+      qm[comp] -= 1;
+      const R vp = accel_neighbour(P, Pc, Pf, N, qp[2], qp[1], qp[0], centre_in);
+      const R vm = accel_neighbour(P, Pc, Pf, N, qm[2], qm[1], qm[0], centre_in);
+      gv = -(vp - vm) * inv2h;
+    }
+    g[((size_t)l * 3 + comp) * n3 + id] = gv;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Green spectrum, FP64.  The kernel on the doubled mesh is even in every
 // axis, so its transform is real and even and separable passes over the
 // octant [0, P/2]^3 suffice: each line of P values is rebuilt by even
@@ -1260,6 +1340,13 @@ hipError_t launch_inv_yx(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStre
 }
 
 template <class R>
+hipError_t launch_accel(const R* phi, R* g, int N, int L, double h0, hipStream_t s) {
+  const size_t n3 = (size_t)N * N * N;
+  launch(k_accel<R>, dim3((unsigned)((n3 + 255) / 256), L), dim3(256), 0, s, phi, g, N, L, h0);
+  return hipGetLastError();
+}
+
+template <class R>
 hipError_t launch_restrict(const R* fine, const R* fine_rc, R* rc, int N, hipStream_t s) {
   const int n = (N / 2) * (N / 2) * (N / 2);
   launch(k_restrict<R>, dim3((n + 255) / 256), dim3(256), 0, s, fine, fine_rc, rc, N);
@@ -1359,6 +1446,7 @@ hipError_t launch_fft_lines(const void* in, void* out, int P, int nlines, int di
   template hipError_t launch_restrict<R>(const R*, const R*, R*, int, hipStream_t);               \
   template hipError_t launch_pyramid<R>(const PyramidTable&, int, int, int, hipStream_t);          \
   template hipError_t launch_carry<R>(const CarryTable&, int, int, int, hipStream_t);              \
+  template hipError_t launch_accel<R>(const R*, R*, int, int, double, hipStream_t);                \
   template hipError_t launch_fft_lines<R>(const void*, void*, int, int, int, const void*, hipStream_t); \
   template hipError_t launch_green_layout<R>(int, const double*, R*, R*, hipStream_t);                 \
   template size_t green_layout_elems<R>(int);

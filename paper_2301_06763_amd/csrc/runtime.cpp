@@ -983,6 +983,30 @@ int nmc_solve(nmc_ctx* ctx, const void* rho, void* phi, int N, int L, double h0,
   return lease_close(ctx, std::move(lease), s, &ctx->leases);
 }
 
+int nmc_acceleration(nmc_ctx* ctx, const void* phi, void* g, int N, int L, double h0, nmc_precision p,
+                     void* hip_stream) {
+  if (!ctx) return NMC_EINVAL;
+  // same checks as a solve, with g (three components per cell) as output
+  Req r{phi, g, N, L, h0, 1.0, p, 0};
+  int rc = validate(ctx, r, 2);
+  if (rc) return rc;
+  const size_t in = (size_t)L * N * N * N * real_size(p);
+  const char* a = (const char*)phi;
+  const char* b = (const char*)g;
+  if (a < b + 3 * in && b < a + in) return fail(ctx, NMC_EINVAL, "phi and g overlap");
+  if ((rc = set_device(ctx))) return rc;
+  hipStream_t s = (hipStream_t)hip_stream;
+  {
+    // algorithmic bytes: the level's potential read once, three components written
+    ProfScope ps(ctx, s, NMC_PASS_ACCEL, 4.0 * in);
+    if (p == NMC_F64)
+      NMC_HIP(ctx, nmc::launch_accel<double>((const double*)phi, (double*)g, N, L, h0, s));
+    else
+      NMC_HIP(ctx, nmc::launch_accel<float>((const float*)phi, (float*)g, N, L, h0, s));
+  }
+  return NMC_OK;
+}
+
 int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_stream) {
   if (!ctx) return NMC_EINVAL;
   if (count < 0 || (count > 0 && !reqs)) return fail(ctx, NMC_EINVAL, "bad request array");
@@ -1148,7 +1172,7 @@ int nmc_profile_read(nmc_ctx* ctx, nmc_pass_stat* out) {
 
 const char* nmc_pass_name(int pass) {
   static const char* names[NMC_NUM_PASSES] = {"restrict", "x",     "y",  "z", "inv_y", "inv_x_second", "carry",
-                                              "inv_x_full", "xy", "inv_yx_second", "inv_yx_full"};
+                                              "inv_x_full", "xy", "inv_yx_second", "inv_yx_full", "acceleration"};
   return (pass >= 0 && pass < NMC_NUM_PASSES) ? names[pass] : "?";
 }
 

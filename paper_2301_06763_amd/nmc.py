@@ -44,7 +44,7 @@ class PassStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-NUM_PASSES = 11
+NUM_PASSES = 12
 
 
 class ServeStats(ctypes.Structure):
@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
         "nmc_serve_stats_get": (i, [vp, ctypes.POINTER(ServeStats)]),
         "nmc_serve_drain": (i, [vp]),
         "nmc_serve_take_completed": (i, [vp, ctypes.POINTER(ctypes.c_uint64), i, ctypes.POINTER(i)]),
+        "nmc_acceleration": (i, [vp, vp, vp, i, i, d, i, vp]),
         "nmc_green_spectrum": (i, [vp, i, i, vp, vp]),
         "nmc_period": (i, [i]),
         "nmc_fft_lines": (i, [vp, vp, vp, i, i, i, i, vp]),
@@ -181,6 +182,22 @@ class Context:
                              float(G), precision_of(rho.dtype), flags, _stream_ptr(stream, self.device))
         if rc:
             self._err(rc, "nmc_solve")
+        return out
+
+    def acceleration(self, phi: torch.Tensor, h0: float, out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+        """g = -grad Phi on every level of a solved potential phi [L, N, N, N];
+        returns [L, 3, N, N, N] (components x, y, z)."""
+        _check_levels(phi, "phi")
+        L, N = phi.shape[0], phi.shape[1]
+        if out is None:
+            out = torch.empty((L, 3, N, N, N), dtype=phi.dtype, device=phi.device)
+        if out.shape != (L, 3, N, N, N) or out.dtype != phi.dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [L, 3, N, N, N] tensor of phi's dtype")
+        rc = lib().nmc_acceleration(self._h, phi.data_ptr(), out.data_ptr(), N, L, float(h0),
+                                    precision_of(phi.dtype), _stream_ptr(stream, self.device))
+        if rc:
+            self._err(rc, "nmc_acceleration")
         return out
 
     def _request(self, rho, h0, G, flags, out) -> Request:

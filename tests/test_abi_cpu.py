@@ -91,7 +91,7 @@ def test_create_without_gpu_fails_cleanly(lib):
 
 
 def test_pass_names(lib):
-    names = [lib.nmc_pass_name(i).decode() for i in range(11)]
+    names = [lib.nmc_pass_name(i).decode() for i in range(12)]
     assert names == ["restrict", "x", "y", "z", "inv_y", "inv_x_second", "carry", "inv_x_full",
-                     "xy", "inv_yx_second", "inv_yx_full"]
+                     "xy", "inv_yx_second", "inv_yx_full", "acceleration"]
     assert lib.nmc_pass_name(99) == b"?"

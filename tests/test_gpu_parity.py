@@ -370,3 +370,81 @@ def test_graph_replay_matches_direct(ctx):
         ctx.solve(rho, w.h0, out=out, stream=s)
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
+
+
+# --- gravitational acceleration (Sect. 2 stencil, Appendix A methods A, B) --
+
+def _accel_tol(phi_ref, h0, bound):
+    """Per-level bound on |g - g_ref| implied by a pointwise relative bound on
+    the potential: every stencil value is a convex combination of potential
+    values, so |dg| <= 2 * bound * max|Phi_l| / (2 h_l)."""
+    L = phi_ref.shape[0]
+    return [bound * np.max(np.abs(phi_ref[l])) / oracle.level_spacing(h0, l) for l in range(L)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("N,L", [(8, 1), (8, 3), (12, 3), (16, 4), (32, 3)])
+def test_acceleration_stencil_matches_oracle(ctx, dtype, N, L):
+    """The GPU stencil applied to the oracle's potential equals the oracle's
+    stencil of the same potential (FP64: rounding only; FP32: the input
+    rounded to FP32 once)."""
+    w = inputs.random_levels(N, L, seed=500 + N + L)
+    phi = oracle.solve(w.rho.numpy(), w.h0)
+    ref = oracle.acceleration(phi, w.h0)
+    g = ctx.acceleration(torch.from_numpy(phi).to("cuda", dtype), w.h0)
+    torch.cuda.synchronize()
+    g = g.double().cpu().numpy()
+    bound = 1e-13 if dtype == torch.float64 else 2e-7
+    for l, tol in enumerate(_accel_tol(phi, w.h0, bound)):
+        assert np.max(np.abs(g[l] - ref[l])) < tol, l
+
+
+def test_acceleration_exact_on_linear_potential(ctx):
+    """Every rule of the stencil (central, one-sided faces, methods A and
+    B) is exact for a linear potential sampled on all levels."""
+    N, L = 16, 4
+    h0 = 1.0 / N
+    a, b, c = 0.3, -1.2, 0.7
+    phi = np.zeros((L, N, N, N))
+    for l in range(L):
+        x = oracle.cell_centres(N, oracle.level_spacing(h0, l))
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        phi[l] = a * X + b * Y + c * Z + 2.0
+    g = ctx.acceleration(torch.from_numpy(phi).cuda(), h0).cpu().numpy()
+    assert np.max(np.abs(g[:, 0] + a)) < 1e-12
+    assert np.max(np.abs(g[:, 1] + b)) < 1e-12
+    assert np.max(np.abs(g[:, 2] + c)) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_solve_then_acceleration_matches_oracle(ctx, dtype):
+    """The whole path (GPU solve, GPU acceleration) against the oracle's,
+    within the bound the potential's tolerance implies through the stencil."""
+    w = inputs.ellipsoid64()
+    rho = w.rho.numpy()
+    phi_ref = oracle.solve(rho, w.h0)
+    ref = oracle.acceleration(phi_ref, w.h0)
+    phi = ctx.solve(w.rho.to("cuda", dtype), w.h0)
+    g = ctx.acceleration(phi, w.h0)
+    torch.cuda.synchronize()
+    g = g.double().cpu().numpy()
+    bound = F64_TOL if dtype == torch.float64 else F32_TOL
+    for l, tol in enumerate(_accel_tol(phi_ref, w.h0, bound)):
+        assert np.max(np.abs(g[l] - ref[l])) < tol, l
+
+
+def test_acceleration_rejects_bad_arguments(ctx):
+    from paper_2301_06763_amd import nmc
+    L = nmc.lib()
+    phi = torch.zeros((2, 8, 8, 8), dtype=torch.float64, device="cuda")
+    g = torch.full((2, 3, 8, 8, 8), 5.0, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    h = ctx._h
+    assert L.nmc_acceleration(h, phi.data_ptr(), g.data_ptr(), 6, 2, 0.1, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_acceleration(h, phi.data_ptr(), g.data_ptr(), 8, 0, 0.1, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_acceleration(h, phi.data_ptr(), g.data_ptr(), 8, 2, 0.0, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_acceleration(h, phi.data_ptr(), phi.data_ptr(), 8, 2, 0.1, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_acceleration(h, None, g.data_ptr(), 8, 2, 0.1, 0, s) == nmc.NMC_EINVAL
+    assert L.nmc_acceleration(h, phi.data_ptr(), g.data_ptr(), 260, 2, 0.1, 0, s) == nmc.NMC_EUNSUPPORTED
+    torch.cuda.synchronize()
+    assert torch.all(g == 5.0)
