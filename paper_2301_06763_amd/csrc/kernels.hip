@@ -1010,7 +1010,8 @@ __global__ void __launch_bounds__(256) k_carry(CarryTable tab, int N, int n0) {
 // outside it takes the mean of the finer level's potential over the 2^3
 // cells it covers (method B).  The coarsest level's outer faces use the
 // second-order one-sided difference; covered cells use the level's own
-// values.  One thread per cell, all three components.
+// values.  One thread per cell (blocks: runs of a z plane), all three
+// components.
 template <class R>
 __device__ __forceinline__ R accel_neighbour(const R* __restrict__ P, const R* __restrict__ Pc,
                                              const R* __restrict__ Pf, int N, int z, int y, int x,
@@ -1044,10 +1045,11 @@ template <class R>
 __global__ void __launch_bounds__(256) k_accel(const R* __restrict__ phi, R* __restrict__ g, int N, int L,
                                                double h0) {
   const size_t n3 = (size_t)N * N * N;
-  const int l = blockIdx.y;
-  const size_t id = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (id >= n3) return;
-  const int x = (int)(id % N), y = (int)(id / N % N), z = (int)(id / ((size_t)N * N));
+  const int l = blockIdx.z, z = blockIdx.y;
+  const int col = blockIdx.x * 256 + threadIdx.x;  // 32-bit: no 64-bit division
+  if (col >= N * N) return;
+  const int x = col % N, y = col / N;
+  const size_t id = (size_t)z * N * N + col;
   const R* P = phi + (size_t)l * n3;
   const R* Pc = l > 0 ? P - n3 : nullptr;
   const R* Pf = l + 1 < L ? P + n3 : nullptr;
@@ -1341,8 +1343,7 @@ hipError_t launch_inv_yx(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStre
 
 template <class R>
 hipError_t launch_accel(const R* phi, R* g, int N, int L, double h0, hipStream_t s) {
-  const size_t n3 = (size_t)N * N * N;
-  launch(k_accel<R>, dim3((unsigned)((n3 + 255) / 256), L), dim3(256), 0, s, phi, g, N, L, h0);
+  launch(k_accel<R>, dim3((unsigned)((N * N + 255) / 256), N, L), dim3(256), 0, s, phi, g, N, L, h0);
   return hipGetLastError();
 }
 
