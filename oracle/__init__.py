@@ -11,5 +11,6 @@ forms, invariants, an independent quadrature); see those tests.
 from .nested import (BETA, cell_centres, child_region, green_periodic, hole,  # noqa: F401
                      kernel_value, level_spacing, potential_at, potential_direct,
                      potential_fft, prolong, prolong_trilinear, restrict_cascade,
-                     solve, solve_points, acceleration)
+                     solve, solve_points, acceleration,
+                     doubled_potential, solve_modified)
 from . import analytic  # noqa: F401

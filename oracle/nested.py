@@ -45,6 +45,12 @@ Readings where the paper is silent or ambiguous:
   boundary potentials there from the analytic solution (Sect. 2, OiCG
   tests); the convolution method has no ghost values, so the second-order
   one-sided difference is used on those faces.
+* R18 modified (dipole-preserving) method, Sect. 7 and Appendix B: the
+  doubled grid of the pair (n, n+1) is level n+1's (restricted) density
+  embedded at the centre of a grid of 2N cells of level n+1's spacing, which
+  spans level n; its potential is brought to level n's cells ("tilde",
+  fine to coarse) as the mean over the 2^3 fine cells each coarse cell
+  covers, the same averaging as the acceleration's method B.
 * R17 acceleration at covered cells (inside the child region) uses the
   level's own potential; method B applies to coarse cells outside the child
   region whose stencil neighbour lies inside it.
@@ -277,6 +283,52 @@ def solve(rho: np.ndarray, h0: float, G: float = 1.0, *, restrict: bool = True,
             S = A + holes[n]
     if return_parts:
         return phi, dict(restricted=rr, full=full, holes=holes, carries=carries)
+    return phi
+
+
+def doubled_potential(mass_fine: np.ndarray, h_fine: float, G: float = 1.0, method: str = "fft") -> np.ndarray:
+    """Sect. 7 (Fig. 16, Eq. 15) and Appendix B: the potential of a fine
+    level's masses on its doubled grid (2N cells of the fine spacing covering
+    the next coarser level, the masses in the central N^3, zeros around),
+    reduced to the coarser level's N^3 cells by the mean over the 2^3 fine
+    cells each covers (reading R18)."""
+    N = mass_fine.shape[0]
+    Md = np.zeros((2 * N, 2 * N, 2 * N), dtype=np.float64)
+    a, b = N // 2, 3 * N // 2
+    Md[a:b, a:b, a:b] = mass_fine
+    Pd = _single_grid(method)(Md, h_fine, G)
+    return Pd.reshape(N, 2, N, 2, N, 2).mean(axis=(1, 3, 5))
+
+
+def solve_modified(rho: np.ndarray, h0: float, G: float = 1.0, *, restrict: bool = True,
+                   method: str = "fft") -> np.ndarray:
+    """The modified convolution method that keeps the dipole moments across
+    every pair of neighbouring grids (Sect. 7, Appendix B, Eqs. B.1-B.2):
+    Phi(Omega^n) = Phi^n_hole + ~Phi^{n+1}_dbl + (hole potentials of the
+    coarser grids carried down, as in Eq. 14) for every level but the
+    finest, which is Phi^L + the carried hole potentials.  The coarse grid
+    thus sees the finer level's masses at the finer resolution instead of
+    their restriction, so opposite charges inside one coarse cell no longer
+    cancel (Sect. 7, Fig. 15)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    L, N = rho.shape[0], rho.shape[1]
+    if N % 4:
+        raise ValueError("N must be a multiple of 4")
+    conv = _single_grid(method)
+    rr = restrict_cascade(rho) if restrict else rho.copy()
+    phi = np.empty((L, N, N, N), dtype=np.float64)
+    S = None
+    for n in range(L):
+        h = level_spacing(h0, n)
+        M = rr[n] * h ** 3
+        A = prolong(S) if n > 0 else 0.0
+        if n < L - 1:
+            hole_n = conv(hole(M), h, G)
+            hf = level_spacing(h0, n + 1)
+            phi[n] = hole_n + doubled_potential(rr[n + 1] * hf ** 3, hf, G, method) + A
+            S = A + hole_n
+        else:
+            phi[n] = conv(M, h, G) + A
     return phi
 
 

@@ -383,3 +383,71 @@ def test_acceleration_of_point_mass_is_newtonian():
         assert interior.sum() > 0
         assert np.all(err[interior] < 1.2 * (h / (r[interior] - h)) ** 2 + 2e-3), l
         assert err[r > 6 * h].max() < 0.12, (l, err[r > 6 * h].max())
+
+
+# --- modified (dipole-preserving) method, Sect. 7 and Appendix B -------------
+
+@pytest.mark.parametrize("N,L", [(4, 2), (8, 2), (4, 3), (8, 3)])
+def test_modified_method_fft_equals_direct(N, L):
+    """The doubled grids are zero-padded convolutions too: the modified
+    solve by FFTs equals the same solve by brute-force sums (Eq. 10)."""
+    rho = np.random.default_rng(40 + N + L).random((L, N, N, N))
+    a = oracle.solve_modified(rho, 1.0 / N, G=1.1)
+    b = oracle.solve_modified(rho, 1.0 / N, G=1.1, method="direct")
+    assert np.max(np.abs(a - b) / np.abs(b)) < 1e-12
+
+
+def test_modified_method_single_level_is_the_original():
+    rho = np.random.default_rng(3).random((1, 8, 8, 8))
+    assert np.array_equal(oracle.solve_modified(rho, 0.1), oracle.solve(rho, 0.1))
+
+
+def test_doubled_potential_is_fine_resolution_sum_averaged():
+    """At a coarse cell outside the child region, the reduced doubled-grid
+    potential is the mean, over the 2^3 finer cells the coarse cell covers,
+    of the finer masses' potential summed directly at those cell centres
+    (physical positions, no self term since the masses are elsewhere)."""
+    N = 8
+    hf = 1.0 / 16
+    mass = np.random.default_rng(9).random((N, N, N))
+    red = oracle.doubled_potential(mass, hf, G=1.3)
+    xs = oracle.cell_centres(N, hf)                     # fine level, centred
+    xc = oracle.cell_centres(N, 2 * hf)                 # coarse level, centred
+    src = np.stack(np.meshgrid(xs, xs, xs, indexing="ij"), -1).reshape(-1, 3)
+    m = mass.reshape(-1)
+    for c in [(0, 0, 0), (7, 3, 1), (1, 6, 7), (2, 7, 4)]:
+        centre = np.array([xc[c[0]], xc[c[1]], xc[c[2]]])
+        vals = []
+        for dz in (-0.25, 0.25):
+            for dy in (-0.25, 0.25):
+                for dx in (-0.25, 0.25):
+                    p = centre + 2 * hf * np.array([dz, dy, dx])
+                    vals.append(-1.3 * np.sum(m * hf ** 0 / np.linalg.norm(src - p, axis=1)) / hf * hf)
+        assert abs(red[c] - np.mean(vals)) < 1e-12 * abs(np.mean(vals))
+
+
+def test_modified_method_keeps_the_dipole():
+    """Sect. 7, Figs. 15-17: opposite masses in two neighbouring cells of
+    the finest level fall into one coarse cell and cancel in the original
+    method's coarse potential; the modified method's coarse potential is the
+    pair's dipole field (direct sum of the two point masses) far from it."""
+    N, L = 16, 2
+    h0 = 1.0 / N
+    hf = h0 / 2
+    rho = np.zeros((L, N, N, N))
+    c = N // 2
+    rho[1, c, c, c - 2] = 1.0 / hf ** 3   # fine cells c-2, c-1 share coarse cell N/4 + c/2 - 1
+    rho[1, c, c, c - 1] = -1.0 / hf ** 3
+    orig = oracle.solve(rho, h0)
+    mod = oracle.solve_modified(rho, h0)
+    assert np.max(np.abs(orig[0])) < 1e-12
+    xf = oracle.cell_centres(N, hf)
+    xc = oracle.cell_centres(N, h0)
+    Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")
+    def pot(px):  # unit mass at fine cell (c, c, px)
+        return -1.0 / np.sqrt((X - xf[px]) ** 2 + (Y - xf[c]) ** 2 + (Z - xf[c]) ** 2)
+    exact = pot(c - 2) - pot(c - 1)
+    r = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    far = r > 4 * h0
+    scale = np.abs(exact[far]).max()
+    assert np.max(np.abs(mod[0] - exact)[far]) < 0.05 * scale
