@@ -78,8 +78,17 @@ enum {
    * apply (P <= 64, hole-grid formulation; default there: one XY and one
    * I2+I1 launch per kind of grid, each z plane kept in LDS).  For
    * ablation.  In a batch, ONE_STREAM and NO_FUSED_PLANES are taken from the
-   * first request of each group of equal N and precision. */
-  NMC_NO_FUSED_PLANES = 1u << 5
+   * first request of each group of equal N, precision and NMC_MODIFIED. */
+  NMC_NO_FUSED_PLANES = 1u << 5,
+  /* The modified convolution method of Sect. 7 and Appendix B (Eqs. B.1,
+   * B.2), which keeps the dipole moments between neighbouring levels: for
+   * every level l < L-1, phi[l] = Phi^l_hole + the potential of level l+1's
+   * masses convolved on the doubled grid (2N cells of level l+1's spacing
+   * spanning level l, period 2P) and averaged over the 2^3 doubled cells of
+   * each level-l cell + the coarser hole potentials carried down as in
+   * Eq. 14; the finest level is unchanged.  Needs 2P <= 512 (N <= 128) and
+   * a larger workspace (nmc_footprint_bytes_flags). */
+  NMC_MODIFIED = 1u << 6
 };
 
 /* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
@@ -101,6 +110,11 @@ const char* nmc_last_error(const nmc_ctx* ctx);
  * host arithmetic.  Errors: NMC_EINVAL, NMC_EUNSUPPORTED. */
 int nmc_footprint_bytes(int N, int L, nmc_precision p, size_t* bytes);
 
+/* The same for a solve with these flags (NMC_MODIFIED adds the doubled
+ * grids' FFT buffers).  Errors: NMC_EINVAL, NMC_EUNSUPPORTED (also for
+ * NMC_MODIFIED with N above 128). */
+int nmc_footprint_bytes_flags(int N, int L, nmc_precision p, unsigned flags, size_t* bytes);
+
 /* Solve one nested mesh (Sect. 4, Eq. 14).
  *   rho   device, [L][N][N][N] densities (read only, never written)
  *   phi   device, [L][N][N][N] output; phi[l] = Phi(Omega^(l+1)) on all N^3
@@ -112,7 +126,8 @@ int nmc_footprint_bytes(int N, int L, nmc_precision p, size_t* bytes);
  *   refine  refinement factor between levels; must be 2
  *   G     gravitational constant (finite)
  *   p     element type of rho and phi and arithmetic of the FFT path
- *   flags NMC_NO_RESTRICT, NMC_F32_UNCOMPENSATED, NMC_NO_GRAPH
+ *   flags NMC_NO_RESTRICT, NMC_F32_UNCOMPENSATED, NMC_NO_GRAPH, NMC_ONE_STREAM,
+ *         NMC_NO_FUSED_PLANES, NMC_MODIFIED
  *   hip_stream  hipStream_t to enqueue on.  The hole grids and the carry
  *         cascade run on a second, library-owned stream that is forked from
  *         and joined back into hip_stream, so completion is ordered on
@@ -135,9 +150,9 @@ typedef struct {
 } nmc_request;
 
 /* Solve `count` independent nested meshes (Sect. 4: the grids of a solve are
- * independent, and so are solves).  Requests of equal N and precision share
- * every FFT pass launch.  Each result is bitwise identical to the same
- * request solved alone.  All requests are validated before any work. */
+ * independent, and so are solves).  Requests of equal N, precision and
+ * NMC_MODIFIED bit share every FFT pass launch.  Each result is bitwise
+ * identical to the same request solved alone.  All requests are validated before any work. */
 int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_stream);
 
 /* ---- Serving: continuous batching over library-owned streams ----------
@@ -239,7 +254,8 @@ enum {
   /* fused plane passes (P <= 64, used in place of X+Y and I2+I1): */
   NMC_PASS_XY = 8, NMC_PASS_IYX_SECOND = 9, NMC_PASS_IYX_FULL = 10,
   NMC_PASS_ACCEL = 11,    /* nmc_acceleration */
-  NMC_NUM_PASSES = 12
+  NMC_PASS_IX_DOUBLED = 12, /* NMC_MODIFIED: last pass of the doubled grids (2^3 mean, sums) */
+  NMC_NUM_PASSES = 13
 };
 
 typedef struct {

@@ -130,6 +130,10 @@ template <class R> hipError_t launch_z(const FieldTable&, PassGeom, Tables<R>, h
 // Inverse passes (output-pruned).
 template <class R> hipError_t launch_inv_y(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 template <class R> hipError_t launch_inv_x(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
+// Last pass of the doubled grids (kind 3, modified method): the 2^3 mean of
+// the doubled potential added to the hole potential in out and the carry.
+// g.N is the level's N, g.P the doubled grid's period (>= 4N).
+template <class R> hipError_t launch_inv_x_dbl(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 
 // Fused plane passes for P <= 64 when a plane fits the LDS
 // (plane_passes_fit): X+Y in one launch, I2+I1 in one launch; the A

@@ -131,22 +131,28 @@ __device__ __forceinline__ R restricted_at(const FieldDesc& F, int N, int cz, in
   return s;
 }
 
-// Input extent nin and output rows [olo, olo + nout) of a grid (FieldDesc).
+// Input extent nin (input rows [ilo, ilo + nin) of the frame) and output
+// rows [olo, olo + nout) of a grid (FieldDesc).  The forward passes store
+// input rows relative to ilo; the inverse passes store output rows in frame
+// order with the row stride astr().
 struct GridGeo {
-  int nin, olo, nout;
+  int nin, olo, nout, ilo;
+  __device__ int astr() const { return nin > olo + nout ? nin : olo + nout; }
 };
 __device__ __forceinline__ GridGeo grid_geo(int kind, int N) {
-  if (kind == 0) return GridGeo{N, 0, N};
-  if (kind == 1) return GridGeo{N / 2 + 2, 0, N / 2 + 2};
-  return GridGeo{N, N / 4 - 1, N / 2 + 2};
+  if (kind == 0 || kind == 4) return GridGeo{N, 0, N, 0};
+  if (kind == 1) return GridGeo{N / 2 + 2, 0, N / 2 + 2, 0};
+  if (kind == 3) return GridGeo{N, 0, 2 * N, N / 2};
+  return GridGeo{N, N / 4 - 1, N / 2 + 2, 0};
 }
 
 // ---------------------------------------------------------------------------
 // X pass: R2C along x with zero padding (input index >= nin is zero).
 //
 // Inputs of the x line (z, y) of a grid: thread t's points x = t + TL q,
-// q < E/2 (the upper half is the zero padding).  Kind 0/2: the level's row
-// with the child region restricted (kind 0, rc set) or zeroed (kind 2);
+// q < E/2 (the upper half is the zero padding).  Kinds 0, 3: the level's row
+// with the child region restricted when rc is set (kind 3 places it at
+// x + N/2 of the frame); kinds 2, 4: the row with the child region zeroed;
 // kind 1: row of the child-region box.  An inactive line gives zeros.
 template <class R, int P, bool FULLN, int K>
 __device__ __forceinline__ void x_inputs(const FieldDesc& F, int N, int z, int y, bool active, int t,
@@ -158,23 +164,24 @@ __device__ __forceinline__ void x_inputs(const FieldDesc& F, int N, int z, int y
   const int N2 = N / 2;
   if (F.kind != 1) {
     const int lo = N / 4, hi = 3 * N / 4;
+    const int xo = (!FULLN && F.kind == 3) ? N / 2 : 0;  // frame offset of the row
     const bool yz_in = z >= lo && z < hi && y >= lo && y < hi;
-    const bool use_rc = F.kind == 0 && rc && yz_in;
-    const bool zero_c = F.kind == 2 && yz_in;
+    const bool use_rc = (F.kind == 0 || F.kind == 3) && rc && yz_in;
+    const bool zero_c = (F.kind == 2 || F.kind == 4) && yz_in;
     const size_t row = ((size_t)z * N + y) * N;
     // the level's own values first, all loads at once (a valid cell stands
     // in where the value is dropped), then the restricted child region
     R own[E / 2];
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
-      const int x = t + TL * q;
-      own[q] = rho[row + ((FULLN || x < N) ? x : 0)];
+      const int x = t + TL * q - xo;
+      own[q] = rho[row + ((FULLN || (unsigned)x < (unsigned)N) ? x : 0)];
     }
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
-      const int x = t + TL * q;
+      const int x = t + TL * q - xo;
       const bool cen = x >= lo && x < hi;
-      R val = (active && (FULLN || x < N) && !(zero_c && cen)) ? own[q] : (R)0;
+      R val = (active && (FULLN || (unsigned)x < (unsigned)N) && !(zero_c && cen)) ? own[q] : (R)0;
       if (active && use_rc && cen) val = restricted_at<R>(F, N, z - lo, y - lo, x - lo);
       v[q] = T{val, 0};
     }
@@ -300,7 +307,8 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   const TwStage<R, P, C::WS * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const bool full = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks
-  const int n = grid_geo(F.kind, FULLN ? P / 2 : g.N).nin;
+  const GridGeo gg = grid_geo(F.kind, FULLN ? P / 2 : g.N);
+  const int n = gg.nin;
   const int tile = blockIdx.x % NT, z = blockIdx.x / NT;
   if (z >= n) return;  // uniform: a smaller grid of a mixed launch
   const int w = threadIdx.x % W, t = threadIdx.x / W;
@@ -310,8 +318,8 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   T v[E];
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
-    const int yy = t + TL * q;
-    const bool in = full || yy < n;
+    const int yy = t + TL * q - (FULLN ? 0 : gg.ilo);
+    const bool in = full || (unsigned)yy < (unsigned)n;
     const T a = A[(size_t)(in ? yy : 0) * (P / 2)];  // branch-free: a valid row, value dropped
     v[q] = in ? a : T{0, 0};
   }
@@ -360,7 +368,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   z_unit(blockIdx.x, NT * (P / 2), g.nf, TP, unit, f);
   const FieldDesc& F = ft.f[f];
   const bool full_in = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks on loads
-  const bool full = FULLN && F.kind == 0;     // nout = N = P/2 as well
+  const bool full = FULLN && (F.kind == 0 || F.kind == 4);  // nout = N = P/2 as well
   const GridGeo gg = grid_geo(F.kind, FULLN ? P / 2 : g.N);
   const int n = gg.nin;
   const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
@@ -378,8 +386,8 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   } else {
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
-      const int zz = t + TL * q;
-      v[q] = zz < n ? B[(size_t)zz * ZS] : T{0, 0};
+      const int zz = t + TL * q - gg.ilo;
+      v[q] = (unsigned)zz < (unsigned)n ? B[(size_t)zz * ZS] : T{0, 0};
     }
   }
   // spectrum values of this thread's points (the spectrum is even in kz:
@@ -463,7 +471,7 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ cplx<R> stw[P];
   const TwStage<R, P, C::WS * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
-  const bool full = FULLN && F.kind == 0;  // nout = N = P/2: no bound checks
+  const bool full = FULLN && (F.kind == 0 || F.kind == 4);  // nout = N = P/2: no bound checks
   const GridGeo gg = grid_geo(F.kind, FULLN ? P / 2 : g.N);
   const int r = blockIdx.x / NT;
   if (r >= gg.nout) return;  // uniform: a smaller grid of a mixed launch
@@ -471,7 +479,7 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int kx = (blockIdx.x % NT) * W + w;
   const T* B = static_cast<const T*>(F.B) + (size_t)z * P * (P / 2) + kx;
-  T* A = static_cast<T*>(F.A) + (size_t)z * gg.nin * (P / 2) + kx;
+  T* A = static_cast<T*>(F.A) + (size_t)z * gg.astr() * (P / 2) + kx;
   T v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = B[(size_t)(t + TL * q) * (P / 2)];
@@ -520,17 +528,42 @@ __device__ __forceinline__ void hermitian_inputs(Row row, bool active, int t, cp
   }
 }
 
+// Prolong(S_{l-1}) (Eqs. 3-6) at level cell x of the rows srow_i (parent) and
+// srow_j (diagonal neighbour) of the carried box S, as s + l: FP64 and the
+// uncompensated FP32 path give the plain weighted sum and l = 0; the
+// compensated path gives 3/4 a exactly as p1 + e1 (FMA), 1/4 b (exact) added
+// with TwoSum, and the rounding errors plus the carried lo terms in l.
+template <class R>
+__device__ __forceinline__ void carried(const FieldDesc& F, const R* S, const R* Sl, size_t srow_i,
+                                        size_t srow_j, int x, R& s, R& l) {
+  const int ix = x / 2 + 1, jx = ix + ((x & 1) ? 1 : -1);
+  const R a = S[srow_i + ix], b = S[srow_j + jx];
+  if (sizeof(R) == 8 || !F.comp) {
+    s = (R)0.75 * a + (R)0.25 * b;
+    l = 0;
+  } else {
+    const R p1 = (R)0.75 * a;
+    const R e1 = fma((R)0.75, a, -p1);
+    R e2;
+    two_sum(p1, (R)0.25 * b, s, e2);
+    l = e1 + e2;
+    if (Sl) l += (R)0.75 * Sl[srow_i + ix] + (R)0.25 * Sl[srow_j + jx];
+  }
+}
+
 // Outputs of the inverse-transformed x line (z, y) of a grid (zr, yr: its
-// row within the output box).  Kinds 1 and 2 write the box; kind 0 writes
-// Phi(Omega^l) = Phi^l + Prolong(S_{l-1}) and, on the stencil box of a level
-// with a finer one (child-region boxes), S_l = Phi(Omega^l) - C_l.
+// row within the output box).  Kinds 1 and 2 write the box; kinds 0 and 4
+// write Phi(Omega^l) = Phi^l + Prolong(S_{l-1}) (kind 4: the hole potential,
+// no carry) and, on the stencil box of a level with a finer one, S_l =
+// Phi(Omega^l) - C_l (child-region boxes) or the hole potential itself
+// (kind 4, C null).
 template <class R, int P, int K>
 __device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const GridGeo& gg, int z, int y,
                                            int zr, int yr, int t, const cplx<R>* v) {
   constexpr int E = Plan<R, P, K>::E, TL = P / E;
   const int n = gg.nout;
   R* out = static_cast<R*>(F.out);
-  if (F.kind != 0) {  // box output (C or the hole potential)
+  if (F.kind == 1 || F.kind == 2) {  // box output (C or the hole potential)
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int x = t + TL * q;
@@ -557,19 +590,12 @@ __device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const Grid
     const R val = v[q].x;
     R hi = val, lo = 0;  // Phi(Omega^l) as an unevaluated sum hi + lo
     if (S) {
-      const int ix = x / 2 + 1, jx = ix + ((x & 1) ? 1 : -1);
-      const R a = S[srow_i + ix], b = S[srow_j + jx];
+      R s1, l;
+      carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
       if (sizeof(R) == 8 || !F.comp) {
-        hi = val + ((R)0.75 * a + (R)0.25 * b);
+        hi = val + s1;
       } else {
-        // 3/4 a exactly as p1 + e1 (FMA), 1/4 b is exact; add the carried lo
-        // terms and val with TwoSum
-        const R p1 = (R)0.75 * a;
-        const R e1 = fma((R)0.75, a, -p1);
-        R s1, e2, s2, e3;
-        two_sum(p1, (R)0.25 * b, s1, e2);
-        R l = e1 + e2;
-        if (Sl) l += (R)0.75 * Sl[srow_i + ix] + (R)0.25 * Sl[srow_j + jx];
+        R s2, e3;
         two_sum(val, s1, s2, e3);
         hi = s2;
         lo = e3 + l;
@@ -578,12 +604,13 @@ __device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const Grid
     out[((size_t)z * N + y) * N + x] = hi + lo;
     if (yz_box && x >= blo && x < blo + NS) {
       const size_t bi = brow + x;
+      const R cb = Cb ? Cb[bi] : (R)0;
       if (sizeof(R) == 8 || !F.comp) {
-        So[bi] = hi - Cb[bi];
+        So[bi] = hi - cb;
         if (Slo) Slo[bi] = 0;
       } else {
         R d, e;
-        two_sum(hi, -Cb[bi], d, e);
+        two_sum(hi, -cb, d, e);
         e += lo;
         const R dh = d + e;
         So[bi] = dh;
@@ -619,7 +646,7 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int line = active ? LPW * unit : 0;
   const int zr = line / n, yr = line % n;  // within the output box
   const int z = gg.olo + zr, y = gg.olo + yr;
-  const T* ra = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
+  const T* ra = static_cast<const T*>(F.A) + ((size_t)z * gg.astr() + y) * (P / 2);
   const T* rb = ra + P / 2;
   // packed half spectra: k = 0 holds the real DC (.x) and Nyquist (.y) values;
   // every load is issued without a branch (inactive units read row 0 and drop it)
@@ -655,6 +682,118 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) vb[q] = T{v[q].y, 0};
     ix_outputs<R, P, kPassIX>(F, N, gg, z, y + 1, zr, yr + 1, t, vb);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// I1 pass of the doubled grids (kind 3) of the modified method (Sect. 7,
+// Appendix B).  The doubled grid of the pair (l, l+1) has 2N cells per axis
+// of level l+1's spacing and spans level l: level cell (z, y, x) covers the
+// doubled cells 2 (z, y, x) + {0, 1}^3, whose mean brings the finer masses'
+// potential to level l.  A line slot owns level row (z, y): it transforms
+// the doubled rows (2z + s, 2y) and (2z + s, 2y + 1), s = 0, 1, two real
+// lines per complex transform, sums the four values of each doubled x, then
+// the two x neighbours across lanes (doubled x = t + TL q: the neighbour of
+// an even thread is the next lane), and writes
+//   Phi(Omega^l) = Phi^l_hole (left in out by the hole grid) + the mean of
+//                  the eight doubled values + Prolong(S_{l-1}),
+// summed with TwoSum on the compensated FP32 path.
+template <class R, int P>
+__global__ void __launch_bounds__((Cfg<R, P, kPassIX>::WC * Cfg<R, P, kPassIX>::TL))
+k_inv_x_dbl(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using C = Cfg<R, P, kPassIX>;
+  using T = cplx<R>;
+  constexpr int E = C::E, TL = C::TL, W = C::WC;
+  static_assert(64 % TL == 0 && TL % 2 == 0, "x neighbours must share a wavefront");
+  __shared__ R sre[W * P], sim[W * P];
+  __shared__ cplx<R> stw[P];
+  const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = g.N, ND = 2 * N;  // level cells, doubled cells per axis
+  const int nunits = N * N;
+  if ((int)blockIdx.x * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
+  const int t = threadIdx.x % TL, w = threadIdx.x / TL;
+  const int unit = blockIdx.x * W + w;
+  const bool active = unit < nunits;
+  const int u = active ? unit : 0;
+  const int z = u / N, y = u % N;
+  LdsView<R> lds{sre, sim, 1, P, w};
+  tws.put(stw);
+  R acc[E / 2];
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) acc[q] = 0;
+  for (int sz = 0; sz < 2; ++sz) {
+    const T* ra = static_cast<const T*>(F.A) + ((size_t)(2 * z + sz) * ND + 2 * y) * (P / 2);
+    const T* rb = ra + P / 2;
+    T v[E];
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) {
+      const int k = t + TL * q;
+      T a = ra[k], b = rb[k];
+      if (k == 0) {
+        a.y = 0;
+        b.y = 0;
+      }
+      v[q] = active ? T{a.x - b.y, a.y + b.x} : T{0, 0};
+    }
+#pragma unroll
+    for (int q = E / 2; q < E; ++q) {
+      const int kk = P - (t + TL * q);  // in (0, P/2]
+      const int idx = kk == P / 2 ? 0 : kk;
+      T a = ra[idx], b = rb[idx];
+      if (kk == P / 2) {
+        a = T{a.y, 0};
+        b = T{b.y, 0};
+      }
+      v[q] = active ? T{a.x + b.y, b.x - a.y} : T{0, 0};  // conj(A) + i conj(B)
+    }
+    // the second transform's first LDS writes follow a barrier inside
+    // fft_line, after every thread's last reads of the first
+    fft_line<R, P, +1, false, true, kPassIX>(v, t, lds, stw);
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) acc[q] += v[q].x + v[q].y;
+  }
+  const int lane = threadIdx.x & 63;
+  R tot[E / 2];
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) tot[q] = acc[q] + lane_read(acc[q], lane ^ 1);
+  if (!active || (t & 1)) return;
+  const int NS = N / 2 + 2;
+  R* out = static_cast<R*>(F.out);
+  const R* S = static_cast<const R*>(F.S);
+  const R* Sl = static_cast<const R*>(F.Slo);
+  const int iz = z / 2 + 1, iy = y / 2 + 1;
+  const int jz = iz + ((z & 1) ? 1 : -1), jy = iy + ((y & 1) ? 1 : -1);
+  const size_t srow_i = ((size_t)iz * NS + iy) * NS, srow_j = ((size_t)jz * NS + jy) * NS;
+  R* orow = out + ((size_t)z * N + y) * N;
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int xd = t + TL * q;  // even doubled x
+    if (xd >= ND) continue;
+    const int x = xd / 2;
+    const R m = (R)0.125 * tot[q];
+    const R hole = orow[x];
+    R hi, lo = 0;
+    if (sizeof(R) == 8 || !F.comp) {
+      hi = hole + m;
+      if (S) {
+        R s1, l;
+        carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
+        hi += s1;
+      }
+    } else {
+      R e0;
+      two_sum(hole, m, hi, e0);
+      lo = e0;
+      if (S) {
+        R s1, l, s2, e3;
+        carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
+        two_sum(hi, s1, s2, e3);
+        hi = s2;
+        lo += e3 + l;
+      }
+    }
+    orow[x] = hi + lo;
   }
 }
 
@@ -1287,7 +1426,7 @@ hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
   bool pairs = g.N >= 256;
   if (!pairs && x_pairs<R>(g.N)) {
     pairs = true;
-    for (int k = 0; k < g.nf; ++k) pairs = pairs && ft.f[k].kind != 0;
+    for (int k = 0; k < g.nf; ++k) pairs = pairs && ft.f[k].kind != 0 && ft.f[k].kind != 4;
   }
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
@@ -1298,6 +1437,21 @@ hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
       launch(k_inv_x<R, PP, true>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
     else
       launch(k_inv_x<R, PP, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+  });
+}
+
+template <class R>
+hipError_t launch_inv_x_dbl(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  // doubled grids: a period of at least 2 (2N) cells, and at least 16 so
+  // that x neighbours sit in lane pairs
+  if (g.P < 4 * g.N || g.P < 16) return hipErrorInvalidValue;
+  return dispatch_p(g.P, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    if constexpr (PP >= 16) {
+      using C = Cfg<R, PP, kPassIX>;
+      dim3 grid((g.N * g.N + C::WC - 1) / C::WC, g.nf);
+      launch(k_inv_x_dbl<R, PP>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+    }
   });
 }
 
@@ -1441,6 +1595,7 @@ hipError_t launch_fft_lines(const void* in, void* out, int P, int nlines, int di
   template hipError_t launch_z<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);           \
   template hipError_t launch_inv_y<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
   template hipError_t launch_inv_x<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
+  template hipError_t launch_inv_x_dbl<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);   \
   template hipError_t launch_fwd_xy<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);      \
   template hipError_t launch_inv_yx<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);      \
   template bool plane_passes_fit<R>(int);                                                         \

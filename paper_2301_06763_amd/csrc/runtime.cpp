@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -50,15 +51,21 @@ size_t real_size(nmc_precision p) { return p == NMC_F64 ? 8 : 4; }
 //    from N = 128 up (measured).
 bool use_boxes(int N) { return N >= 128; }
 
+// The modified method (Sect. 7, Appendix B) convolves a doubled grid per
+// level pair on twice the period; it uses the hole-grid formulation.
+bool is_modified(unsigned flags) { return (flags & NMC_MODIFIED) != 0; }
+
 // Workspace layout of one request (offsets from its base): per level l the
-// full grid's A and B; per level l < L-1 the second grid (hole grid or
-// child-region box), the restriction data Rc (the block-mean pyramid of level
-// l+1, or the cascaded restriction in its first (N/2)^3 values), the box
-// potential (hole potential or C) and the carried potential S (hi, and lo for
-// the FP32 path).
+// full grid's A and B; per level l < L-1 the second grid (hole grid,
+// child-region box, or with the modified method the doubled grid), the
+// restriction data Rc (the block-mean pyramid of level l+1, or the cascaded
+// restriction in its first (N/2)^3 values), the box potential (hole
+// potential or C) and the carried potential S (hi, and lo for the FP32
+// path).  With the modified method the "full" grids of levels l < L-1 are
+// the hole grids with full output.
 struct Layout {
   int N, L, P, NC;
-  bool boxes;
+  bool boxes, mod;
   size_t r, c;
   size_t a_full, b_full, a_sec, b_sec, rc_bytes, box_bytes;
   size_t total;
@@ -74,20 +81,28 @@ struct Layout {
   size_t Slo(int l) const { return Shi(l) + box_bytes; }
 };
 
-Layout make_layout(int N, int L, nmc_precision p) {
+Layout make_layout(int N, int L, nmc_precision p, unsigned flags) {
   Layout lo{};
   lo.N = N;
   lo.L = L;
   lo.P = period_of(N);
   lo.NC = N / 2 + 2;
-  lo.boxes = use_boxes(N);
+  lo.mod = is_modified(flags);
+  lo.boxes = use_boxes(N) && !lo.mod;
   lo.r = real_size(p);
   lo.c = 2 * lo.r;
   const size_t P = lo.P, NC = lo.NC, ns = lo.boxes ? NC : (size_t)N;
   lo.a_full = align_up((size_t)N * N * (P / 2) * lo.c);
   lo.b_full = align_up((size_t)N * P * (P / 2) * lo.c);
-  lo.a_sec = align_up(ns * ns * (P / 2) * lo.c);
-  lo.b_sec = align_up(ns * P * (P / 2) * lo.c);
+  if (lo.mod) {
+    // doubled grid: inputs N rows, outputs 2N rows per axis, period 2P
+    const size_t PD = 2 * P, ND = 2 * (size_t)N;
+    lo.a_sec = align_up(ND * ND * (PD / 2) * lo.c);
+    lo.b_sec = align_up(ND * PD * (PD / 2) * lo.c);
+  } else {
+    lo.a_sec = align_up(ns * ns * (P / 2) * lo.c);
+    lo.b_sec = align_up(ns * P * (P / 2) * lo.c);
+  }
   lo.rc_bytes = align_up((size_t)nmc::pyramid_slab(N, L) * lo.r);
   lo.box_bytes = align_up(NC * NC * NC * lo.r);
   lo.total = lo.Shi(0) + (size_t)(L - 1) * 2 * lo.box_bytes;
@@ -358,6 +373,8 @@ int validate(nmc_ctx* ctx, const Req& r, int refine) {
   if (!r.rho || !r.phi) return fail(ctx, NMC_EINVAL, "rho and phi must be non-null device pointers");
   if (r.N < kMinN || r.N % 4 != 0) return fail(ctx, NMC_EINVAL, "N must be a multiple of 4, >= 4");
   if (!period_of(r.N)) return fail(ctx, NMC_EUNSUPPORTED, "N above 256 (padded period above 512)");
+  if (is_modified(r.flags) && 2 * period_of(r.N) > kMaxP)
+    return fail(ctx, NMC_EUNSUPPORTED, "NMC_MODIFIED: N above 128 (doubled-grid period above 512)");
   if (r.L < 1 || r.L > kMaxL) return fail(ctx, NMC_EINVAL, "L must be in [1, 16]");
   if (!(r.h0 > 0) || !std::isfinite(r.h0)) return fail(ctx, NMC_EINVAL, "h0 must be positive and finite");
   if (!std::isfinite(r.G)) return fail(ctx, NMC_EINVAL, "G must be finite");
@@ -409,7 +426,8 @@ struct PassBytes {
   int kind;
   PassBytes(int N_, int P_, size_t rsz, int kind_)
       : r((double)rsz), c(2.0 * rsz), N(N_), nin(kind_ == 1 ? N_ / 2 + 2 : N_),
-        nout(kind_ == 0 ? N_ : N_ / 2 + 2), P(P_), H(P_ / 2 + 1), NS(N_ / 2 + 2), kind(kind_) {}
+        nout(kind_ == 0 || kind_ == 4 ? N_ : kind_ == 3 ? 2 * N_ : N_ / 2 + 2), P(P_), H(P_ / 2 + 1),
+        NS(N_ / 2 + 2), kind(kind_) {}
   double half() const { return P / 2; }
   double x() const {
     const double in = kind == 1 ? std::pow(N / 2, 3) : N * N * N;
@@ -426,8 +444,14 @@ struct PassBytes {
   double iyx(bool carry, bool next) const { return nout * P * half() * c + ix(carry, next) - nout * nout * half() * c; }
   double ix(bool carry, bool next) const {
     // the carried box S is read once per level; C is read and S_l written
+    // (kind 4: the hole potential's box written)
     return nout * nout * half() * c + nout * nout * nout * r + (carry ? NS * NS * NS * r : 0.0) +
-           (next ? 2 * NS * NS * NS * r : 0.0);
+           (next ? (kind == 4 ? 1 : 2) * NS * NS * NS * r : 0.0);
+  }
+  // doubled grid's last pass: its (2N)^2 half spectra read, the hole
+  // potential read and Phi(Omega^l) written on N^3 cells, the carry read
+  double ix_doubled(bool carry) const {
+    return nout * nout * half() * c + 2 * N * N * N * r + (carry ? NS * NS * NS * r : 0.0);
   }
 };
 
@@ -438,18 +462,25 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   const int N = reqs[0].N;
   const int P = period_of(N);
   const int NC = N / 2 + 2;
-  const bool boxes = use_boxes(N);
-  PerP& pp = ctx->perp[P];
-  nmc::Tables<R> tb;
-  if constexpr (sizeof(R) == 8) {
-    tb.tw = (const double2*)pp.tw64;
-    tb.gz = pp.gz64;
-    tb.gn = pp.gn64;
-  } else {
-    tb.tw = (const float2*)pp.tw32;
-    tb.gz = pp.gz32;
-    tb.gn = pp.gn32;
-  }
+  const bool mod = is_modified(reqs[0].flags);
+  const bool boxes = use_boxes(N) && !mod;
+  const int PD = 2 * P;  // period of the doubled grids (modified method)
+  auto tables = [&](int Pc) {
+    PerP& pp = ctx->perp[Pc];
+    nmc::Tables<R> t;
+    if constexpr (sizeof(R) == 8) {
+      t.tw = (const double2*)pp.tw64;
+      t.gz = pp.gz64;
+      t.gn = pp.gn64;
+    } else {
+      t.tw = (const float2*)pp.tw32;
+      t.gz = pp.gz32;
+      t.gn = pp.gn32;
+    }
+    return t;
+  };
+  const nmc::Tables<R> tb = tables(P);
+  const nmc::Tables<R> tbd = mod ? tables(PD) : tb;
   const size_t lvl = (size_t)N * N * N;
   std::vector<FieldDesc> fulls, secs;  // full grids; hole grids or child-region boxes
   std::vector<int> full_level;
@@ -467,7 +498,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   size_t off = 0;
   for (int i = 0; i < count; ++i) {
     const Req& q = reqs[i];
-    const Layout lo = make_layout(N, q.L, q.p);
+    const Layout lo = make_layout(N, q.L, q.p, q.flags);
     char* base = ws + off;
     off += lo.total;
     maxL = std::max(maxL, q.L);
@@ -496,30 +527,57 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     for (int l = 0; l < q.L; ++l) {
       const double h = std::ldexp(q.h0, -l);
       const bool finer = l < q.L - 1;  // a finer level exists
+      const bool hole_full = mod && finer;  // modified method: hole grid with full output
       FieldDesc f{};
       f.rho = rho + (size_t)l * lvl;
-      f.rc = (restrict_on && finer) ? (const void*)(base + lo.Rc(l)) : nullptr;
+      f.rc = (restrict_on && finer && !mod) ? (const void*)(base + lo.Rc(l)) : nullptr;
       f.rslab = rslab;
       f.rdepth = pyramid ? q.L - 1 - l : 1;
       f.A = base + lo.A(l);
       f.B = base + lo.B(l);
       f.out = phi + (size_t)l * lvl;
+      const void* carry_in = nullptr;  // S_{l-1}
+      const void* carry_lo = nullptr;
       if (l >= 1) {
         // hole grids: S_0 is the hole potential itself; boxes: S_0 lives in Shi(0)
-        f.S = (!boxes && l == 1) ? base + lo.Box(0) : base + lo.Shi(l - 1);
-        f.Slo = (comp && (boxes || l >= 2)) ? (const void*)(base + lo.Slo(l - 1)) : nullptr;
+        carry_in = (!boxes && l == 1) ? base + lo.Box(0) : base + lo.Shi(l - 1);
+        carry_lo = (comp && (boxes || l >= 2)) ? (const void*)(base + lo.Slo(l - 1)) : nullptr;
+      }
+      if (!hole_full) {  // the modified method adds the carry in the doubled grid's last pass
+        f.S = carry_in;
+        f.Slo = carry_lo;
       }
       if (boxes && finer) {
         f.Sout = base + lo.Shi(l);
         f.Slo_out = comp ? (void*)(base + lo.Slo(l)) : nullptr;
         f.C = base + lo.Box(l);
       }
+      if (hole_full) f.Sout = base + lo.Box(l);  // the hole potential's box, for the carry
       f.scale = -q.G * h * h / P3;
-      f.kind = 0;
+      f.kind = hole_full ? 4 : 0;
       f.comp = comp ? 1 : 0;
       fulls.push_back(f);
       full_level.push_back(l);
-      if (finer) {
+      if (finer && mod) {
+        // doubled grid of the pair (l, l+1): level l+1's density (its own
+        // child region restricted) on the grid of level l+1's spacing
+        const double hf = std::ldexp(q.h0, -(l + 1));
+        const double PD3 = (double)PD * PD * PD;
+        FieldDesc c{};
+        c.rho = rho + (size_t)(l + 1) * lvl;
+        c.rc = (restrict_on && l + 1 < q.L - 1) ? (const void*)(base + lo.Rc(l + 1)) : nullptr;
+        c.rslab = rslab;
+        c.rdepth = pyramid ? q.L - 2 - l : 1;
+        c.A = base + lo.As(l);
+        c.B = base + lo.Bs(l);
+        c.out = phi + (size_t)l * lvl;
+        c.S = carry_in;
+        c.Slo = carry_lo;
+        c.scale = -q.G * hf * hf / PD3;
+        c.kind = 3;
+        c.comp = f.comp;
+        secs.push_back(c);
+      } else if (finer) {
         FieldDesc c{};
         c.rho = f.rho;
         c.rc = boxes ? f.rc : nullptr;
@@ -535,15 +593,15 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
       }
     }
   }
-  auto for_chunks = [&](const std::vector<FieldDesc>& fs, int n, auto launch, int pass,
-                        hipStream_t st) -> hipError_t {
+  auto for_chunks_p = [&](const std::vector<FieldDesc>& fs, int n, auto launch, int pass, hipStream_t st,
+                          int Pc, const nmc::Tables<R>& tbc) -> hipError_t {
     for (size_t a = 0; a < fs.size(); a += nmc::kMaxFieldsPerLaunch) {
       FieldTable ft{};
       const int cnt = (int)std::min<size_t>(nmc::kMaxFieldsPerLaunch, fs.size() - a);
       double bytes = 0;
       for (int k = 0; k < cnt; ++k) {
         ft.f[k] = fs[a + k];
-        const PassBytes pb(N, P, sizeof(R), ft.f[k].kind);
+        const PassBytes pb(N, Pc, sizeof(R), ft.f[k].kind);
         switch (pass) {
           case NMC_PASS_X: bytes += pb.x(); break;
           case NMC_PASS_Y: bytes += pb.y(); break;
@@ -552,16 +610,19 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
           case NMC_PASS_XY: bytes += pb.xy(); break;
           case NMC_PASS_IYX_SECOND:
           case NMC_PASS_IYX_FULL: bytes += pb.iyx(ft.f[k].S != nullptr, ft.f[k].Sout != nullptr); break;
+          case NMC_PASS_IX_DOUBLED: bytes += pb.ix_doubled(ft.f[k].S != nullptr); break;
           default: bytes += pb.ix(ft.f[k].S != nullptr, ft.f[k].Sout != nullptr); break;
         }
       }
-      PassGeom g{N, P, n, cnt};
+      PassGeom g{N, Pc, n, cnt};
       ProfScope ps(ctx, st, pass, bytes);
-      hipError_t e = launch(ft, g, tb, st);
+      hipError_t e = launch(ft, g, tbc, st);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   };
+  auto for_chunks = [&](const std::vector<FieldDesc>& fs, int n, auto launch, int pass,
+                        hipStream_t st) -> hipError_t { return for_chunks_p(fs, n, launch, pass, st, P, tb); };
   auto restrict_cascade = [&](hipStream_t st) -> int {
     const double nn = (double)N * N * N;
     for (size_t a = 0; a < pyramids.size(); a += nmc::kMaxPyramidsPerLaunch) {
@@ -613,21 +674,63 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     }
     return NMC_OK;
   };
-  auto forward_to_iy = [&](const std::vector<FieldDesc>& fs, int nin, int nout, hipStream_t st) -> int {
+  auto forward_to_iy_p = [&](const std::vector<FieldDesc>& fs, int nin, int nout, hipStream_t st, int Pc,
+                             const nmc::Tables<R>& tbc) -> int {
     if (fs.empty()) return NMC_OK;
-    NMC_HIP(ctx, for_chunks(fs, nin, nmc::launch_fwd_x<R>, NMC_PASS_X, st));
-    NMC_HIP(ctx, for_chunks(fs, nin, nmc::launch_fwd_y<R>, NMC_PASS_Y, st));
-    NMC_HIP(ctx, for_chunks(fs, nin, nmc::launch_z<R>, NMC_PASS_Z, st));
-    NMC_HIP(ctx, for_chunks(fs, nout, nmc::launch_inv_y<R>, NMC_PASS_IY, st));
+    NMC_HIP(ctx, for_chunks_p(fs, nin, nmc::launch_fwd_x<R>, NMC_PASS_X, st, Pc, tbc));
+    NMC_HIP(ctx, for_chunks_p(fs, nin, nmc::launch_fwd_y<R>, NMC_PASS_Y, st, Pc, tbc));
+    NMC_HIP(ctx, for_chunks_p(fs, nin, nmc::launch_z<R>, NMC_PASS_Z, st, Pc, tbc));
+    NMC_HIP(ctx, for_chunks_p(fs, nout, nmc::launch_inv_y<R>, NMC_PASS_IY, st, Pc, tbc));
     return NMC_OK;
   };
+  auto forward_to_iy = [&](const std::vector<FieldDesc>& fs, int nin, int nout, hipStream_t st) -> int {
+    return forward_to_iy_p(fs, nin, nout, st, P, tb);
+  };
   int rc;
+  const bool one_stream = (reqs[0].flags & NMC_ONE_STREAM) != 0;
+  const bool fused = nmc::plane_passes_fit<R>(P) && !(reqs[0].flags & NMC_NO_FUSED_PLANES);
+  if (mod) {
+    // Modified method: hole grids with full output (kind 4) and the finest
+    // full grid on period P, as in the hole pipeline; the doubled grids
+    // (kind 3) on period 2P, independent of them until their last pass,
+    // which adds the 2^3 mean to the hole potential in phi and the carry.
+    if ((rc = restrict_cascade(s))) return rc;
+    std::vector<FieldDesc> holes, finest;
+    for (const auto& f : fulls) (f.kind == 4 ? holes : finest).push_back(f);
+    const bool fork = aux && aux != s && !secs.empty() && !ctx->profiling && !one_stream;
+    if (fork) {
+      NMC_HIP(ctx, hipEventRecord(ctx->ev_fork, s));
+      NMC_HIP(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0));
+      if ((rc = forward_to_iy_p(secs, N, 2 * N, aux, PD, tbd))) return rc;
+      NMC_HIP(ctx, hipEventRecord(ctx->ev_join, aux));
+    }
+    if (fused) {
+      NMC_HIP(ctx, for_chunks(fulls, N, nmc::launch_fwd_xy<R>, NMC_PASS_XY, s));
+      NMC_HIP(ctx, for_chunks(fulls, N, nmc::launch_z<R>, NMC_PASS_Z, s));
+      if (!holes.empty()) NMC_HIP(ctx, for_chunks(holes, N, nmc::launch_inv_yx<R>, NMC_PASS_IYX_SECOND, s));
+      if ((rc = carry_cascade(s))) return rc;
+      NMC_HIP(ctx, for_chunks(finest, N, nmc::launch_inv_yx<R>, NMC_PASS_IYX_FULL, s));
+    } else {
+      if ((rc = forward_to_iy(fulls, N, N, s))) return rc;
+      if (!holes.empty()) NMC_HIP(ctx, for_chunks(holes, N, nmc::launch_inv_x<R>, NMC_PASS_IX_SECOND, s));
+      if ((rc = carry_cascade(s))) return rc;
+      NMC_HIP(ctx, for_chunks(finest, N, nmc::launch_inv_x<R>, NMC_PASS_IX_FULL, s));
+    }
+    if (fork) {
+      NMC_HIP(ctx, hipStreamWaitEvent(s, ctx->ev_join, 0));
+    } else if ((rc = forward_to_iy_p(secs, N, 2 * N, s, PD, tbd))) {
+      return rc;
+    }
+    if (!secs.empty())
+      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_inv_x_dbl<R>, NMC_PASS_IX_DOUBLED, s, PD, tbd));
+    return NMC_OK;
+  }
   if (!boxes) {
     // hole grids: one stream, full and hole grids share every launch
     if ((rc = restrict_cascade(s))) return rc;
     std::vector<FieldDesc> all(fulls);
     all.insert(all.end(), secs.begin(), secs.end());
-    if (nmc::plane_passes_fit<R>(P) && !(reqs[0].flags & NMC_NO_FUSED_PLANES)) {
+    if (fused) {
       NMC_HIP(ctx, for_chunks(all, N, nmc::launch_fwd_xy<R>, NMC_PASS_XY, s));
       NMC_HIP(ctx, for_chunks(all, N, nmc::launch_z<R>, NMC_PASS_Z, s));
       if (!secs.empty()) NMC_HIP(ctx, for_chunks(secs, NC, nmc::launch_inv_yx<R>, NMC_PASS_IYX_SECOND, s));
@@ -644,7 +747,6 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   // child-region boxes: they need the restriction, then the boxes and the
   // full grids are independent until the last pass and may use two streams
   if ((rc = restrict_cascade(s))) return rc;
-  const bool one_stream = (reqs[0].flags & NMC_ONE_STREAM) != 0;
   if (aux && aux != s && !secs.empty() && !ctx->profiling && !one_stream) {
     NMC_HIP(ctx, hipEventRecord(ctx->ev_fork, s));
     NMC_HIP(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0));
@@ -670,16 +772,18 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   return NMC_OK;
 }
 
-int prepare(nmc_ctx* ctx, int N, hipStream_t s) {
+int prepare(nmc_ctx* ctx, int N, unsigned flags, hipStream_t s) {
   const int P = period_of(N);
-  return ensure_green(ctx, P, s);
+  int rc = ensure_green(ctx, P, s);
+  if (rc == NMC_OK && is_modified(flags)) rc = ensure_green(ctx, 2 * P, s);
+  return rc;
 }
 
 // Launch requests that share N and precision, on one workspace block.
 int launch_group(nmc_ctx* ctx, const Req* reqs, int count, hipStream_t s, Lease* lease, hipStream_t aux) {
   size_t total = 0;
-  for (int i = 0; i < count; ++i) total += make_layout(reqs[i].N, reqs[i].L, reqs[i].p).total;
-  int rc = prepare(ctx, reqs[0].N, s);
+  for (int i = 0; i < count; ++i) total += make_layout(reqs[i].N, reqs[i].L, reqs[i].p, reqs[i].flags).total;
+  int rc = prepare(ctx, reqs[0].N, reqs[0].flags, s);
   if (rc) return rc;
   Block b{};
   rc = pool_alloc(ctx, total, &b);
@@ -690,9 +794,10 @@ int launch_group(nmc_ctx* ctx, const Req* reqs, int count, hipStream_t s, Lease*
 }
 
 int solve_many(nmc_ctx* ctx, const Req* reqs, int count, hipStream_t s, Lease* lease) {
-  // group by (N, precision), preserving order inside a group
-  std::map<std::pair<int, int>, std::vector<Req>> groups;
-  for (int i = 0; i < count; ++i) groups[{reqs[i].N, (int)reqs[i].p}].push_back(reqs[i]);
+  // group by (N, precision, method), preserving order inside a group
+  std::map<std::tuple<int, int, bool>, std::vector<Req>> groups;
+  for (int i = 0; i < count; ++i)
+    groups[std::make_tuple(reqs[i].N, (int)reqs[i].p, is_modified(reqs[i].flags))].push_back(reqs[i]);
   for (auto& kv : groups) {
     auto& v = kv.second;
     for (size_t a = 0; a < v.size(); a += kMaxBatchRequests) {
@@ -718,7 +823,7 @@ void drop_graph(nmc_ctx* ctx, std::map<GraphKey, GraphEntry>::iterator it) {
 }
 
 int build_graph(nmc_ctx* ctx, const Req& r, const GraphKey& key, hipStream_t s) {
-  int rc = prepare(ctx, r.N, s);
+  int rc = prepare(ctx, r.N, r.flags, s);
   if (rc) return rc;
   if (!ctx->cap_stream) NMC_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   while (ctx->graphs.size() >= kMaxGraphs) {
@@ -728,7 +833,7 @@ int build_graph(nmc_ctx* ctx, const Req& r, const GraphKey& key, hipStream_t s) 
     drop_graph(ctx, lru);
   }
   GraphEntry e;
-  rc = pool_alloc(ctx, make_layout(r.N, r.L, r.p).total, &e.ws);
+  rc = pool_alloc(ctx, make_layout(r.N, r.L, r.p, r.flags).total, &e.ws);
   if (rc) return rc;
   NMC_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
   rc = r.p == NMC_F64 ? run_group<double>(ctx, &r, 1, (char*)e.ws.ptr, ctx->cap_stream, ctx->aux_stream)
@@ -799,12 +904,15 @@ int serve_tick(nmc_ctx* ctx, int* launched) {
     admitted.push_back(t);
     ctx->queue.pop_front();
   }
-  // 3. batches per (N, precision) group, each on the next serving stream.  A
+  // 3. batches per (N, precision, method) group, each on the next serving stream.  A
   // batch holds at most a quarter of the budget so that several batches are
   // in flight and overlap on the device.
   const size_t max_batch_bytes = ctx->budget ? std::max<size_t>(ctx->budget / 4, 1) : SIZE_MAX;
-  std::map<std::pair<int, int>, std::vector<uint64_t>> groups;
-  for (uint64_t t : admitted) groups[{ctx->items[t].r.N, (int)ctx->items[t].r.p}].push_back(t);
+  std::map<std::tuple<int, int, bool>, std::vector<uint64_t>> groups;
+  for (uint64_t t : admitted) {
+    const Req& r = ctx->items[t].r;
+    groups[std::make_tuple(r.N, (int)r.p, is_modified(r.flags))].push_back(t);
+  }
   std::vector<std::vector<uint64_t>> batches;
   for (auto& kv : groups) {
     std::vector<uint64_t> cur;
@@ -875,12 +983,17 @@ extern "C" {
 
 int nmc_period(int N) { return period_of(N); }
 
-int nmc_footprint_bytes(int N, int L, nmc_precision p, size_t* bytes) {
+int nmc_footprint_bytes_flags(int N, int L, nmc_precision p, unsigned flags, size_t* bytes) {
   if (!bytes || N < kMinN || N % 4 != 0 || L < 1 || L > kMaxL || (p != NMC_F64 && p != NMC_F32))
     return NMC_EINVAL;
   if (!period_of(N)) return NMC_EUNSUPPORTED;
-  *bytes = make_layout(N, L, p).total;
+  if (is_modified(flags) && 2 * period_of(N) > kMaxP) return NMC_EUNSUPPORTED;
+  *bytes = make_layout(N, L, p, flags).total;
   return NMC_OK;
+}
+
+int nmc_footprint_bytes(int N, int L, nmc_precision p, size_t* bytes) {
+  return nmc_footprint_bytes_flags(N, L, p, 0u, bytes);
 }
 
 int nmc_create(nmc_ctx** out, int hip_device, size_t hbm_budget_bytes) {
@@ -1037,7 +1150,7 @@ int nmc_serve_submit(nmc_ctx* ctx, const nmc_request* req, uint64_t* ticket) {
   Req r{req->rho, req->phi, req->N, req->L, req->h0, req->G, req->p, req->flags};
   int rc = validate(ctx, r, 2);
   if (rc) return rc;
-  const size_t bytes = align_up(make_layout(r.N, r.L, r.p).total, 2u << 20);
+  const size_t bytes = align_up(make_layout(r.N, r.L, r.p, r.flags).total, 2u << 20);
   if (ctx->budget && bytes > ctx->budget)
     return fail(ctx, NMC_ENOMEM, "request footprint " + std::to_string(bytes) + " exceeds the budget");
   const uint64_t t = ctx->next_ticket++;
@@ -1172,7 +1285,8 @@ int nmc_profile_read(nmc_ctx* ctx, nmc_pass_stat* out) {
 
 const char* nmc_pass_name(int pass) {
   static const char* names[NMC_NUM_PASSES] = {"restrict", "x",     "y",  "z", "inv_y", "inv_x_second", "carry",
-                                              "inv_x_full", "xy", "inv_yx_second", "inv_yx_full", "acceleration"};
+                                              "inv_x_full", "xy", "inv_yx_second", "inv_yx_full", "acceleration",
+                                              "inv_x_doubled"};
   return (pass >= 0 && pass < NMC_NUM_PASSES) ? names[pass] : "?";
 }
 

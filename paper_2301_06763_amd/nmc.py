@@ -23,6 +23,7 @@ NMC_F32_UNCOMPENSATED = 1 << 2
 NMC_NO_GRAPH = 1 << 3
 NMC_ONE_STREAM = 1 << 4
 NMC_NO_FUSED_PLANES = 1 << 5
+NMC_MODIFIED = 1 << 6  # the dipole-preserving method of Sect. 7 / Appendix B
 
 _CODES = {NMC_EINVAL: "EINVAL", NMC_ENOMEM: "ENOMEM", NMC_EDEVICE: "EDEVICE",
           NMC_EUNSUPPORTED: "EUNSUPPORTED", NMC_EAGAIN: "EAGAIN"}
@@ -44,7 +45,7 @@ class PassStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-NUM_PASSES = 12
+NUM_PASSES = 13
 
 
 class ServeStats(ctypes.Structure):
@@ -72,6 +73,7 @@ def lib() -> ctypes.CDLL:
         "nmc_destroy": (None, [vp]),
         "nmc_last_error": (ctypes.c_char_p, [vp]),
         "nmc_footprint_bytes": (i, [i, i, i, ctypes.POINTER(sz)]),
+        "nmc_footprint_bytes_flags": (i, [i, i, i, ctypes.c_uint, ctypes.POINTER(sz)]),
         "nmc_solve": (i, [vp, vp, vp, i, i, d, i, d, i, u, vp]),
         "nmc_solve_batch": (i, [vp, ctypes.POINTER(Request), i, vp]),
         "nmc_serve_submit": (i, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -108,11 +110,11 @@ def precision_of(dtype: torch.dtype) -> int:
     raise TypeError(f"unsupported dtype {dtype} (float64 or float32)")
 
 
-def footprint_bytes(N: int, L: int, dtype=torch.float64) -> int:
+def footprint_bytes(N: int, L: int, dtype=torch.float64, flags: int = 0) -> int:
     out = ctypes.c_size_t()
-    rc = lib().nmc_footprint_bytes(N, L, precision_of(dtype), ctypes.byref(out))
+    rc = lib().nmc_footprint_bytes_flags(N, L, precision_of(dtype), flags, ctypes.byref(out))
     if rc:
-        raise NmcError(rc, f"footprint of N={N} L={L}")
+        raise NmcError(rc, f"footprint of N={N} L={L} flags={flags}")
     return out.value
 
 

@@ -72,6 +72,25 @@ def test_footprint(lib):
     assert lib.nmc_footprint_bytes(8, 2, 0, None) == nmc.NMC_EINVAL
 
 
+def test_footprint_of_the_modified_method(lib):
+    from paper_2301_06763_amd import nmc
+    import torch
+    # L full-size grids (L-1 hole grids and the finest level) plus L-1 doubled
+    # grids of period 2P: A = (2N)^2 (P) and B = 2N (2P) P complex values each
+    N, L, P = 32, 4, 64
+    grid = (N * N * (P // 2) + N * P * (P // 2)) * 16
+    dbl = ((2 * N) ** 2 * P + 2 * N * (2 * P) * P) * 16
+    fp = nmc.footprint_bytes(N, L, torch.float64, nmc.NMC_MODIFIED)
+    assert L * grid + (L - 1) * dbl <= fp < (L * grid + (L - 1) * dbl) * 1.05
+    assert fp > nmc.footprint_bytes(N, L, torch.float64)
+    assert nmc.footprint_bytes(N, L, torch.float64, 0) == nmc.footprint_bytes(N, L, torch.float64)
+    out = ctypes.c_size_t()
+    # the doubled grid's period 2P must stay within 512: N <= 128
+    assert lib.nmc_footprint_bytes_flags(128, 3, 0, nmc.NMC_MODIFIED, ctypes.byref(out)) == nmc.NMC_OK
+    assert lib.nmc_footprint_bytes_flags(132, 3, 0, nmc.NMC_MODIFIED, ctypes.byref(out)) == nmc.NMC_EUNSUPPORTED
+    assert lib.nmc_footprint_bytes_flags(132, 3, 0, 0, ctypes.byref(out)) == nmc.NMC_OK
+
+
 def test_null_context_is_rejected(lib):
     from paper_2301_06763_amd import nmc
     assert lib.nmc_solve(None, None, None, 8, 2, 0.1, 2, 1.0, 0, 0, None) == nmc.NMC_EINVAL
@@ -91,7 +110,7 @@ def test_create_without_gpu_fails_cleanly(lib):
 
 
 def test_pass_names(lib):
-    names = [lib.nmc_pass_name(i).decode() for i in range(12)]
+    names = [lib.nmc_pass_name(i).decode() for i in range(13)]
     assert names == ["restrict", "x", "y", "z", "inv_y", "inv_x_second", "carry", "inv_x_full",
-                     "xy", "inv_yx_second", "inv_yx_full", "acceleration"]
+                     "xy", "inv_yx_second", "inv_yx_full", "acceleration", "inv_x_doubled"]
     assert lib.nmc_pass_name(99) == b"?"
