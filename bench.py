@@ -279,6 +279,8 @@ def main():
     res = {}
     outs = {}
     accel = {}
+    modified, mouts = {}, {}
+    mod_steps = max(10, args.steps // 4)
     for tag, dt in (("f32", torch.float32), ("f64", torch.float64)):
         rho = w.rho.to(dt).contiguous()
         out, el, prof, lat = time_solves(ctx, rho, w.h0, args.steps, args.warmup, torch, args.flags)
@@ -286,6 +288,13 @@ def main():
         outs[tag] = out.double()
         res[tag] = {"solves_per_s": args.steps / el, "ms_per_step": el / args.steps * 1e3,
                     "passes": pass_table(prof), "lat": lat, "prof": prof}
+        if 2 * nmc.period(N) <= 512:  # the modified method's doubled grids fit
+            mo, mel, mprof, mlat = time_solves(ctx, rho, w.h0, mod_steps, args.warmup, torch,
+                                               args.flags | nmc.NMC_MODIFIED)
+            mouts[tag] = mo.double()
+            modified[tag] = {"solves_per_s": round(mod_steps / mel, 3), "ms_per_step": round(mel / mod_steps * 1e3, 4),
+                             "latency_ms": {"p50": round(pct(mlat, 50), 4), "p99": round(pct(mlat, 99), 4)},
+                             "steps": mod_steps, "passes": pass_table(mprof)}
     # FP32 against the FP64 GPU result (the FP64 path is checked against the oracle in tests)
     e = ((outs["f32"] - outs["f64"]).abs() / outs["f64"].abs())
     err32 = {"max": float(e.max()), "rms": float(e.pow(2).mean().sqrt()),
@@ -326,6 +335,15 @@ def main():
                                  "interface rules of Appendix A); a separate call, not in the solve step",
                          "f32": accel["f32"], "f64": accel["f64"]},
     }
+    if modified:
+        em = ((mouts["f32"] - mouts["f64"]).abs() / mouts["f64"].abs())
+        line["modified"] = {
+            "what": "the dipole-preserving method of Sect. 7 / Appendix B (NMC_MODIFIED): per level pair a "
+                    "doubled grid of period 2P (2N cells of the finer spacing) in addition to the hole grids; "
+                    "z and x..inv_y pass rows mix both periods",
+            "doubled_period": 2 * nmc.period(N),
+            "f32": modified["f32"], "f64": modified["f64"],
+            "fp32_vs_fp64": {"max_rel_err": float(em.max()), "rms_rel_err": float(em.pow(2).mean().sqrt())}}
     other = "f64" if args.dtype == "f32" else "f32"
     o = res[other]
     oz = o["prof"]["z"]

@@ -139,10 +139,13 @@ struct GridGeo {
   int nin, olo, nout, ilo;
   __device__ int astr() const { return nin > olo + nout ? nin : olo + nout; }
 };
+// DBL: a launch of doubled grids (kind 3 only); kept out of the other
+// launches' code, where the extra case measurably costs registers.
+template <bool DBL = false>
 __device__ __forceinline__ GridGeo grid_geo(int kind, int N) {
+  if (DBL) return GridGeo{N, 0, 2 * N, N / 2};
   if (kind == 0 || kind == 4) return GridGeo{N, 0, N, 0};
   if (kind == 1) return GridGeo{N / 2 + 2, 0, N / 2 + 2, 0};
-  if (kind == 3) return GridGeo{N, 0, 2 * N, N / 2};
   return GridGeo{N, N / 4 - 1, N / 2 + 2, 0};
 }
 
@@ -154,7 +157,7 @@ __device__ __forceinline__ GridGeo grid_geo(int kind, int N) {
 // with the child region restricted when rc is set (kind 3 places it at
 // x + N/2 of the frame); kinds 2, 4: the row with the child region zeroed;
 // kind 1: row of the child-region box.  An inactive line gives zeros.
-template <class R, int P, bool FULLN, int K>
+template <class R, int P, bool FULLN, int K, bool DBL = false>
 __device__ __forceinline__ void x_inputs(const FieldDesc& F, int N, int z, int y, bool active, int t,
                                          cplx<R>* v) {
   using T = cplx<R>;
@@ -164,9 +167,9 @@ __device__ __forceinline__ void x_inputs(const FieldDesc& F, int N, int z, int y
   const int N2 = N / 2;
   if (F.kind != 1) {
     const int lo = N / 4, hi = 3 * N / 4;
-    const int xo = (!FULLN && F.kind == 3) ? N / 2 : 0;  // frame offset of the row
+    const int xo = DBL ? N / 2 : 0;  // frame offset of the row (doubled grids, kind 3)
     const bool yz_in = z >= lo && z < hi && y >= lo && y < hi;
-    const bool use_rc = (F.kind == 0 || F.kind == 3) && rc && yz_in;
+    const bool use_rc = (DBL || F.kind == 0) && rc && yz_in;
     const bool zero_c = (F.kind == 2 || F.kind == 4) && yz_in;
     const size_t row = ((size_t)z * N + y) * N;
     // the level's own values first, all loads at once (a valid cell stands
@@ -175,13 +178,15 @@ __device__ __forceinline__ void x_inputs(const FieldDesc& F, int N, int z, int y
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int x = t + TL * q - xo;
-      own[q] = rho[row + ((FULLN || (unsigned)x < (unsigned)N) ? x : 0)];
+      const bool xin = DBL ? (unsigned)x < (unsigned)N : x < N;
+      own[q] = rho[row + ((FULLN || xin) ? x : 0)];
     }
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int x = t + TL * q - xo;
+      const bool xin = DBL ? (unsigned)x < (unsigned)N : x < N;
       const bool cen = x >= lo && x < hi;
-      R val = (active && (FULLN || (unsigned)x < (unsigned)N) && !(zero_c && cen)) ? own[q] : (R)0;
+      R val = (active && (FULLN || xin) && !(zero_c && cen)) ? own[q] : (R)0;
       if (active && use_rc && cen) val = restricted_at<R>(F, N, z - lo, y - lo, x - lo);
       v[q] = T{val, 0};
     }
@@ -227,7 +232,7 @@ __device__ __forceinline__ double lane_read(double x, int src) {
 // slot E-1-q (thread 0 holds its own), read across lanes; the TL threads of a
 // line are consecutive lanes of one wavefront.  Otherwise one line per
 // transform (more workgroups; measured faster for FP32 below N = 128).
-template <class R, int P, bool FULLN, bool PAIRS>
+template <class R, int P, bool FULLN, bool PAIRS, bool DBL = false>
 __global__ void __launch_bounds__((Cfg<R, P, kPassX>::WC * Cfg<R, P, kPassX>::TL))
 k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassX>;
@@ -238,7 +243,7 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ cplx<R> stw[P];
   const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
-  const int N = FULLN ? P / 2 : g.N, n = grid_geo(F.kind, N).nin;
+  const int N = FULLN ? P / 2 : g.N, n = grid_geo<DBL>(F.kind, N).nin;
   const int nunits = n * n / LPW;  // n is even: the two lines of a pair share z
   if ((int)blockIdx.x * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
@@ -247,10 +252,10 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int line = active ? LPW * unit : 0;
   const int z = line / n, y = line % n;
   T va[E], v[E];
-  x_inputs<R, P, FULLN, kPassX>(F, N, z, y, active, t, va);
+  x_inputs<R, P, FULLN, kPassX, DBL>(F, N, z, y, active, t, va);
   if constexpr (PAIRS) {
     T vb[E];
-    x_inputs<R, P, FULLN, kPassX>(F, N, z, y + 1, active, t, vb);
+    x_inputs<R, P, FULLN, kPassX, DBL>(F, N, z, y + 1, active, t, vb);
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) v[q] = T{va[q].x, vb[q].x};
   } else {
@@ -295,8 +300,9 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
 }
 
 // ---------------------------------------------------------------------------
-// Y pass: C2C along y, inputs y >= n zero, all P outputs kept.
-template <class R, int P, bool FULLN>
+// Y pass: C2C along y, inputs y >= n zero, all P outputs kept.  DBL: a
+// launch of doubled grids (kind 3), whose input rows start at ilo.
+template <class R, int P, bool FULLN, bool DBL = false>
 __global__ void __launch_bounds__((Cfg<R, P, kPassY>::WS * Cfg<R, P, kPassY>::TL), (Cfg<R, P, kPassY>::MINW))
 k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassY>;
@@ -307,7 +313,7 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   const TwStage<R, P, C::WS * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const bool full = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks
-  const GridGeo gg = grid_geo(F.kind, FULLN ? P / 2 : g.N);
+  const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N);
   const int n = gg.nin;
   const int tile = blockIdx.x % NT, z = blockIdx.x / NT;
   if (z >= n) return;  // uniform: a smaller grid of a mixed launch
@@ -318,8 +324,8 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   T v[E];
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
-    const int yy = t + TL * q - (FULLN ? 0 : gg.ilo);
-    const bool in = full || (unsigned)yy < (unsigned)n;
+    const int yy = t + TL * q - (DBL ? gg.ilo : 0);
+    const bool in = full || (DBL ? (unsigned)yy < (unsigned)n : yy < n);
     const T a = A[(size_t)(in ? yy : 0) * (P / 2)];  // branch-free: a valid row, value dropped
     v[q] = in ? a : T{0, 0};
   }
@@ -353,8 +359,9 @@ __device__ __forceinline__ void z_unit(int b, int U, int nf, int TP, int& u, int
 // spectrum times the level scale, inverse along z, keep rows z < n.
 // A workgroup owns the rows ky and -ky (mod P) of W adjacent kx columns: the
 // packed DC/Nyquist column needs the value at (-ky, -kz) to separate the two
-// real planes before they are multiplied by different spectra.
-template <class R, int P, bool FULLN>
+// real planes before they are multiplied by different spectra.  DBL: a
+// launch of doubled grids (kind 3), whose input rows start at ilo.
+template <class R, int P, bool FULLN, bool DBL = false>
 __global__ void __launch_bounds__((2 * Cfg<R, P, kPassZ>::WZ * Cfg<R, P, kPassZ>::TL), (Cfg<R, P, kPassZ>::MINW))
 k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassZ>;
@@ -368,8 +375,8 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   z_unit(blockIdx.x, NT * (P / 2), g.nf, TP, unit, f);
   const FieldDesc& F = ft.f[f];
   const bool full_in = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks on loads
-  const bool full = FULLN && (F.kind == 0 || F.kind == 4);  // nout = N = P/2 as well
-  const GridGeo gg = grid_geo(F.kind, FULLN ? P / 2 : g.N);
+  const bool full = FULLN && F.kind == 0;     // nout = N = P/2 as well
+  const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N);
   const int n = gg.nin;
   const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
   const int tile = unit % NT, p = unit / NT;
@@ -386,8 +393,8 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   } else {
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
-      const int zz = t + TL * q - gg.ilo;
-      v[q] = (unsigned)zz < (unsigned)n ? B[(size_t)zz * ZS] : T{0, 0};
+      const int zz = t + TL * q - (DBL ? gg.ilo : 0);
+      v[q] = (DBL ? (unsigned)zz < (unsigned)n : zz < n) ? B[(size_t)zz * ZS] : T{0, 0};
     }
   }
   // spectrum values of this thread's points (the spectrum is even in kz:
@@ -460,8 +467,9 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
 }
 
 // ---------------------------------------------------------------------------
-// I2 pass: inverse along y over rows z < n; keep rows y < n.
-template <class R, int P, bool FULLN>
+// I2 pass: inverse along y over rows z < n; keep rows y < n.  DBL: a launch
+// of doubled grids (kind 3), whose output rows outnumber the input rows.
+template <class R, int P, bool FULLN, bool DBL = false>
 __global__ void __launch_bounds__((Cfg<R, P, kPassIY>::WS * Cfg<R, P, kPassIY>::TL), (Cfg<R, P, kPassIY>::MINW))
 k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassIY>;
@@ -471,15 +479,15 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ cplx<R> stw[P];
   const TwStage<R, P, C::WS * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
-  const bool full = FULLN && (F.kind == 0 || F.kind == 4);  // nout = N = P/2: no bound checks
-  const GridGeo gg = grid_geo(F.kind, FULLN ? P / 2 : g.N);
+  const bool full = FULLN && F.kind == 0;  // nout = N = P/2: no bound checks
+  const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N);
   const int r = blockIdx.x / NT;
   if (r >= gg.nout) return;  // uniform: a smaller grid of a mixed launch
   const int z = gg.olo + r;
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int kx = (blockIdx.x % NT) * W + w;
   const T* B = static_cast<const T*>(F.B) + (size_t)z * P * (P / 2) + kx;
-  T* A = static_cast<T*>(F.A) + (size_t)z * gg.astr() * (P / 2) + kx;
+  T* A = static_cast<T*>(F.A) + (size_t)z * (DBL ? gg.astr() : gg.nin) * (P / 2) + kx;
   T v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = B[(size_t)(t + TL * q) * (P / 2)];
@@ -646,7 +654,7 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int line = active ? LPW * unit : 0;
   const int zr = line / n, yr = line % n;  // within the output box
   const int z = gg.olo + zr, y = gg.olo + yr;
-  const T* ra = static_cast<const T*>(F.A) + ((size_t)z * gg.astr() + y) * (P / 2);
+  const T* ra = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
   const T* rb = ra + P / 2;
   // packed half spectra: k = 0 holds the real DC (.x) and Nyquist (.y) values;
   // every load is issued without a branch (inactive units read row 0 and drop it)
@@ -1373,6 +1381,13 @@ hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     const int units = pairs ? g.n * g.n / 2 : g.n * g.n;
     dim3 grid((units + C::WC - 1) / C::WC, g.nf), block(C::WC * C::TL);
     const bool full = g.N == PP / 2;
+    if constexpr (PP >= 16) {
+      if (PP >= 4 * g.N) {  // doubled grids
+        if (pairs) launch(k_fwd_x<R, PP, false, true, true>, grid, block, 0, s, ft, g, tb);
+        else launch(k_fwd_x<R, PP, false, false, true>, grid, block, 0, s, ft, g, tb);
+        return;
+      }
+    }
     if (pairs && full) launch(k_fwd_x<R, PP, true, true>, grid, block, 0, s, ft, g, tb);
     else if (pairs) launch(k_fwd_x<R, PP, false, true>, grid, block, 0, s, ft, g, tb);
     else if (full) launch(k_fwd_x<R, PP, true, false>, grid, block, 0, s, ft, g, tb);
@@ -1386,6 +1401,12 @@ hipError_t launch_fwd_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassY>;
     dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
+    if constexpr (PP >= 16) {
+      if (PP >= 4 * g.N) {  // doubled grids
+        launch(k_fwd_y<R, PP, false, true>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+        return;
+      }
+    }
     if (g.N == PP / 2)
       launch(k_fwd_y<R, PP, true>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
     else
@@ -1399,6 +1420,12 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassZ>;
     dim3 grid(((PP / 2) / C::WZ) * (PP / 2) * g.nf);  // one dimension: see z_unit
+    if constexpr (PP >= 16) {
+      if (PP >= 4 * g.N) {  // doubled grids
+        launch(k_z<R, PP, false, true>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
+        return;
+      }
+    }
     if (g.N == PP / 2)
       launch(k_z<R, PP, true>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
     else
@@ -1412,6 +1439,12 @@ hipError_t launch_inv_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassIY>;
     dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
+    if constexpr (PP >= 16) {
+      if (PP >= 4 * g.N) {  // doubled grids
+        launch(k_inv_y<R, PP, false, true>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+        return;
+      }
+    }
     if (g.N == PP / 2)
       launch(k_inv_y<R, PP, true>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
     else
