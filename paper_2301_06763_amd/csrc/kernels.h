@@ -20,12 +20,20 @@ namespace nmc {
 //    hole potential of Sect. 4 by linearity: Phi_hole = Phi - C;
 //  * kind 2, the level with its child region zeroed (Omega^m_hole of Sect. 4,
 //    Fig. 5): nin = N, output only on the stencil box (olo = N/4 - 1,
-//    nout = N/2 + 2).
+//    nout = N/2 + 2);
+//  * kind 3 (modified method, Sect. 7 and Appendix B), the doubled grid of
+//    the pair (l, l+1): level l+1's density (rho, rc) on a grid of 2N cells
+//    of level l+1's spacing spanning level l, period 2P: its N input rows
+//    sit at frame rows [N/2, 3N/2), its output rows are [0, 2N), reduced to
+//    level l's N cells per axis by the inverse passes (out: level l's
+//    potential, to which the reduced values and the carry S are added);
+//  * kind 4 (modified method), kind 2's grid with full output: out gets the
+//    hole potential on all N^3 cells and Sout its stencil box.
 struct FieldDesc {
   const void* rho;   // level density [N][N][N] (x fastest), caller-owned
   const void* rc;    // restriction data of the child region (pyramid slab of level l+1), or null
   void* A;           // workspace [nin][nin][P/2] complex: x-pass output, y-inverse output
-  void* B;           // workspace [nin][P][P/2] complex: y-pass output, z-pass in place
+  void* B;           // workspace [nin][P][P/2] complex ([2N][P][P/2] for kind 3): y-pass output, z-pass in place
   void* out;         // kind 0: potential [N][N][N]; kinds 1, 2: box [(N/2+2)^3]
   const void* S;     // kind 0, level >= 1: carried coarse potential S_{l-1} on the box (hi)
   const void* Slo;   // its compensation term (FP32 path) or null
@@ -35,7 +43,8 @@ struct FieldDesc {
   double scale;      // -G h^2 / P^3 (mass = rho h^3, kernel 1/(h |d|), 1/P^3 of the inverse)
   long long rslab;   // elements between the restriction slabs of consecutive levels
   int rdepth;        // terms of the restricted value (1: rc holds the finished restriction)
-  int kind;          // 0 full level, 1 child-region box, 2 level with its child region zeroed
+  int kind;          // 0 full level, 1 child-region box, 2 level with its child region zeroed,
+                     // 3 doubled grid, 4 hole grid with full output
   int comp;          // FP32: compensated (two-term) carry
 };
 
@@ -130,10 +139,13 @@ template <class R> hipError_t launch_z(const FieldTable&, PassGeom, Tables<R>, h
 // Inverse passes (output-pruned).
 template <class R> hipError_t launch_inv_y(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 template <class R> hipError_t launch_inv_x(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
-// Last pass of the doubled grids (kind 3, modified method): the 2^3 mean of
-// the doubled potential added to the hole potential in out and the carry.
-// g.N is the level's N, g.P the doubled grid's period (>= 4N).
-template <class R> hipError_t launch_inv_x_dbl(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
+// Inverse passes of the doubled grids (kind 3, modified method) after their
+// z pass, with the 2^3 mean taken in the spectrum (each transform at half
+// the period): I2 (sum of z rows 2j, 2j+1, y fold, rows y < N kept) and I1
+// (x fold, C2R, the mean added to the hole potential in out and the carry).
+// g.N is the level's N, g.P the doubled grids' period (>= 4N); tb its tables.
+template <class R> hipError_t launch_inv_y_fold(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
+template <class R> hipError_t launch_inv_x_fold(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 
 // Fused plane passes for P <= 64 when a plane fits the LDS
 // (plane_passes_fit): X+Y in one launch, I2+I1 in one launch; the A

@@ -75,8 +75,9 @@ __device__ __forceinline__ void stage_twiddles(cplx<R>* stw, const cplx<R>* __re
 
 // The same for a workgroup of NTH threads, split in two: the loads are
 // issued first (constructor) and the LDS writes (put) come after the
-// kernel's own data loads, so that no load waits for another.
-template <class R, int P, int NTH>
+// kernel's own data loads, so that no load waits for another.  STRIDE 2
+// takes the P twiddles from the table of period 2P (every second entry).
+template <class R, int P, int NTH, int STRIDE = 1>
 struct TwStage {
   static constexpr int K = (P + NTH - 1) / NTH;
   cplx<R> r[K];
@@ -84,7 +85,7 @@ struct TwStage {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int j = threadIdx.x + k * NTH;
-      if (j < P) r[k] = tw[j];
+      if (j < P) r[k] = tw[STRIDE * j];
     }
   }
   __device__ __forceinline__ void put(cplx<R>* stw) const {
@@ -131,13 +132,11 @@ __device__ __forceinline__ R restricted_at(const FieldDesc& F, int N, int cz, in
   return s;
 }
 
-// Input extent nin (input rows [ilo, ilo + nin) of the frame) and output
-// rows [olo, olo + nout) of a grid (FieldDesc).  The forward passes store
-// input rows relative to ilo; the inverse passes store output rows in frame
-// order with the row stride astr().
+// Input extent nin (input rows [ilo, ilo + nin) of the frame, stored
+// relative to ilo by the forward passes) and output rows [olo, olo + nout)
+// of a grid (FieldDesc).
 struct GridGeo {
   int nin, olo, nout, ilo;
-  __device__ int astr() const { return nin > olo + nout ? nin : olo + nout; }
 };
 // DBL: a launch of doubled grids (kind 3 only); kept out of the other
 // launches' code, where the extra case measurably costs registers.
@@ -467,9 +466,8 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
 }
 
 // ---------------------------------------------------------------------------
-// I2 pass: inverse along y over rows z < n; keep rows y < n.  DBL: a launch
-// of doubled grids (kind 3), whose output rows outnumber the input rows.
-template <class R, int P, bool FULLN, bool DBL = false>
+// I2 pass: inverse along y over rows z < n; keep rows y < n.
+template <class R, int P, bool FULLN>
 __global__ void __launch_bounds__((Cfg<R, P, kPassIY>::WS * Cfg<R, P, kPassIY>::TL), (Cfg<R, P, kPassIY>::MINW))
 k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassIY>;
@@ -480,14 +478,14 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   const TwStage<R, P, C::WS * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const bool full = FULLN && F.kind == 0;  // nout = N = P/2: no bound checks
-  const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N);
+  const GridGeo gg = grid_geo(F.kind, FULLN ? P / 2 : g.N);
   const int r = blockIdx.x / NT;
   if (r >= gg.nout) return;  // uniform: a smaller grid of a mixed launch
   const int z = gg.olo + r;
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int kx = (blockIdx.x % NT) * W + w;
   const T* B = static_cast<const T*>(F.B) + (size_t)z * P * (P / 2) + kx;
-  T* A = static_cast<T*>(F.A) + (size_t)z * (DBL ? gg.astr() : gg.nin) * (P / 2) + kx;
+  T* A = static_cast<T*>(F.A) + (size_t)z * gg.nin * (P / 2) + kx;
   T v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = B[(size_t)(t + TL * q) * (P / 2)];
@@ -694,114 +692,161 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
 }
 
 // ---------------------------------------------------------------------------
-// I1 pass of the doubled grids (kind 3) of the modified method (Sect. 7,
-// Appendix B).  The doubled grid of the pair (l, l+1) has 2N cells per axis
-// of level l+1's spacing and spans level l: level cell (z, y, x) covers the
-// doubled cells 2 (z, y, x) + {0, 1}^3, whose mean brings the finer masses'
-// potential to level l.  A line slot owns level row (z, y): it transforms
-// the doubled rows (2z + s, 2y) and (2z + s, 2y + 1), s = 0, 1, two real
-// lines per complex transform, sums the four values of each doubled x, then
-// the two x neighbours across lanes (doubled x = t + TL q: the neighbour of
-// an even thread is the next lane), and writes
-//   Phi(Omega^l) = Phi^l_hole (left in out by the hole grid) + the mean of
-//                  the eight doubled values + Prolong(S_{l-1}),
-// summed with TwoSum on the compensated FP32 path.
+// Inverse passes of the doubled grids (kind 3) of the modified method
+// (Sect. 7, Appendix B), with the reduction to level l taken in the
+// spectrum.  The doubled grid of the pair (l, l+1) has 2N cells per axis of
+// level l+1's spacing and spans level l: level cell j covers the doubled
+// cells 2j and 2j + 1 per axis, and its value is the mean of the 2^3.  For a
+// line of doubled values x_n of period 2P with spectrum X (x_n = sum_K X[K]
+// exp(2 pi i K n / 2P)), the pair means y_j = (x_2j + x_2j+1) / 2 have the
+// period-P spectrum
+//   Y[k] = ((X[k] + X[k+P]) + w^k (X[k] - X[k+P])) / 2,  w = exp(2 pi i / 2P),
+// so each inverse transform runs at length P on the folded spectrum and
+// yields level l's cells directly.  The z pairs are averaged by adding the
+// z pass's rows 2j and 2j + 1 (the y and x transforms are linear).
+// fold_pair: Y[k] from X[k] = a, X[k+P] = b and wc = exp(-2 pi i k / 2P)
+// (the table entry; w^k is its conjugate), times the extra factor s.
+template <class R>
+__device__ __forceinline__ cplx<R> fold_pair(cplx<R> a, cplx<R> b, cplx<R> wc, R s) {
+  const cplx<R> d{a.x - b.x, a.y - b.y};
+  const cplx<R> wd{wc.x * d.x + wc.y * d.y, wc.x * d.y - wc.y * d.x};  // conj(wc) d
+  return cplx<R>{s * (a.x + b.x + wd.x), s * (a.y + b.y + wd.y)};
+}
+
+// I2 of the doubled grids: the y columns (level row z, kx) of the sum of
+// the z pass's rows 2z and 2z + 1, folded to length P and inverted, rows
+// y < N kept: A[z][y][kx] (kx < P, the x half spectrum of period 2P).
+template <class R, int P>
+__global__ void __launch_bounds__((Cfg<R, P, kPassIY>::WS * Cfg<R, P, kPassIY>::TL), (Cfg<R, P, kPassIY>::MINW))
+k_inv_y_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using C = Cfg<R, P, kPassIY>;
+  using T = cplx<R>;
+  constexpr int E = C::E, TL = C::TL, W = C::WS, NT = P / W, PD = 2 * P;
+  __shared__ R sre[W * P], sim[W * P];
+  __shared__ cplx<R> stw[P];
+  const TwStage<R, P, C::WS * C::TL, 2> tws(tb.tw);  // tb: the period-2P tables
+  const FieldDesc& F = ft.f[blockIdx.y];
+  const int N = g.N;
+  const int z = blockIdx.x / NT;
+  if (z >= N) return;  // uniform: a smaller grid of a mixed launch
+  const int w = threadIdx.x % W, t = threadIdx.x / W;
+  const int kx = (blockIdx.x % NT) * W + w;
+  const T* B0 = static_cast<const T*>(F.B) + (size_t)(2 * z) * PD * P + kx;  // ky at + ky * P
+  const T* B1 = B0 + (size_t)PD * P;
+  T v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int k = t + TL * q;
+    const T a0 = B0[(size_t)k * P], a1 = B1[(size_t)k * P];
+    const T b0 = B0[(size_t)(k + P) * P], b1 = B1[(size_t)(k + P) * P];
+    v[q] = fold_pair<R>(T{a0.x + a1.x, a0.y + a1.y}, T{b0.x + b1.x, b0.y + b1.y}, tb.tw[k], (R)0.25);
+  }
+  LdsView<R> lds{sre, sim, W, 1, w};
+  tws.put(stw);
+  fft_line<R, P, +1, false, true, kPassIY>(v, t, lds, stw);
+  T* A = static_cast<T*>(F.A) + (size_t)z * N * P + kx;
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int y = t + TL * q;
+    if (y < N) A[(size_t)y * P] = v[q];
+  }
+}
+
+// Phi(Omega^l) at level cell x of the row `orow` (holding the hole
+// potential): the hole potential + the reduced doubled-grid value m +
+// Prolong(S_{l-1}), summed with TwoSum on the compensated FP32 path.
+template <class R>
+__device__ __forceinline__ void doubled_out(const FieldDesc& F, R* orow, const R* S, const R* Sl, size_t srow_i,
+                                            size_t srow_j, int x, R m) {
+  const R hole = orow[x];
+  R hi, lo = 0;
+  if (sizeof(R) == 8 || !F.comp) {
+    hi = hole + m;
+    if (S) {
+      R s1, l;
+      carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
+      hi += s1;
+    }
+  } else {
+    two_sum(hole, m, hi, lo);
+    if (S) {
+      R s1, l, s2, e3;
+      carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
+      two_sum(hi, s1, s2, e3);
+      hi = s2;
+      lo += e3 + l;
+    }
+  }
+  orow[x] = hi + lo;
+}
+
+// I1 of the doubled grids: the x half spectra (period 2P) of level rows
+// (z, y) and (z, y + 1), folded to the packed half spectra of length P and
+// inverted as one complex transform (row y in the real part, y + 1 in the
+// imaginary part); then Phi(Omega^l) = Phi^l_hole (left in out by the hole
+// grid) + the doubled-grid mean + Prolong(S_{l-1}).
 template <class R, int P>
 __global__ void __launch_bounds__((Cfg<R, P, kPassIX>::WC * Cfg<R, P, kPassIX>::TL))
-k_inv_x_dbl(FieldTable ft, PassGeom g, Tables<R> tb) {
+k_inv_x_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassIX>;
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WC;
-  static_assert(64 % TL == 0 && TL % 2 == 0, "x neighbours must share a wavefront");
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
-  const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
+  const TwStage<R, P, C::WC * C::TL, 2> tws(tb.tw);  // tb: the period-2P tables
   const FieldDesc& F = ft.f[blockIdx.y];
-  const int N = g.N, ND = 2 * N;  // level cells, doubled cells per axis
-  const int nunits = N * N;
+  const int N = g.N;
+  const int nunits = N * N / 2;
   if ((int)blockIdx.x * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
   const int unit = blockIdx.x * W + w;
   const bool active = unit < nunits;
-  const int u = active ? unit : 0;
-  const int z = u / N, y = u % N;
+  const int line = active ? 2 * unit : 0;
+  const int z = line / N, y = line % N;
+  const T* ra = static_cast<const T*>(F.A) + ((size_t)z * N + y) * P;
+  const T* rb = ra + P;
+  // Y[k], 0 <= k <= P/2, of a row: X[k+P] = conj(X[P-k]) (real input);
+  // k = 0 gives the DC value X[0], k = P/2 the real Re X[P/2] - Im X[P/2];
+  // every load is issued without a branch
+  auto folded = [&](const T* r, int k) -> T {
+    const T a = r[k], c = r[k == 0 ? 0 : P - k];
+    if (k == 0) return T{a.x, 0};
+    if (k == P / 2) return T{a.x - a.y, 0};
+    return fold_pair<R>(a, T{c.x, -c.y}, tb.tw[k], (R)0.5);
+  };
+  T v[E];
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int k = t + TL * q;  // < P/2
+    const T a = folded(ra, k), b = folded(rb, k);
+    v[q] = active ? T{a.x - b.y, a.y + b.x} : T{0, 0};
+  }
+#pragma unroll
+  for (int q = E / 2; q < E; ++q) {
+    const int kk = P - (t + TL * q);  // in (0, P/2]
+    const T a = folded(ra, kk), b = folded(rb, kk);
+    v[q] = active ? T{a.x + b.y, b.x - a.y} : T{0, 0};  // conj(Y_a) + i conj(Y_b)
+  }
   LdsView<R> lds{sre, sim, 1, P, w};
   tws.put(stw);
-  R acc[E / 2];
-#pragma unroll
-  for (int q = 0; q < E / 2; ++q) acc[q] = 0;
-  for (int sz = 0; sz < 2; ++sz) {
-    const T* ra = static_cast<const T*>(F.A) + ((size_t)(2 * z + sz) * ND + 2 * y) * (P / 2);
-    const T* rb = ra + P / 2;
-    T v[E];
-#pragma unroll
-    for (int q = 0; q < E / 2; ++q) {
-      const int k = t + TL * q;
-      T a = ra[k], b = rb[k];
-      if (k == 0) {
-        a.y = 0;
-        b.y = 0;
-      }
-      v[q] = active ? T{a.x - b.y, a.y + b.x} : T{0, 0};
-    }
-#pragma unroll
-    for (int q = E / 2; q < E; ++q) {
-      const int kk = P - (t + TL * q);  // in (0, P/2]
-      const int idx = kk == P / 2 ? 0 : kk;
-      T a = ra[idx], b = rb[idx];
-      if (kk == P / 2) {
-        a = T{a.y, 0};
-        b = T{b.y, 0};
-      }
-      v[q] = active ? T{a.x + b.y, b.x - a.y} : T{0, 0};  // conj(A) + i conj(B)
-    }
-    // the second transform's first LDS writes follow a barrier inside
-    // fft_line, after every thread's last reads of the first
-    fft_line<R, P, +1, false, true, kPassIX>(v, t, lds, stw);
-#pragma unroll
-    for (int q = 0; q < E / 2; ++q) acc[q] += v[q].x + v[q].y;
-  }
-  const int lane = threadIdx.x & 63;
-  R tot[E / 2];
-#pragma unroll
-  for (int q = 0; q < E / 2; ++q) tot[q] = acc[q] + lane_read(acc[q], lane ^ 1);
-  if (!active || (t & 1)) return;
+  fft_line<R, P, +1, false, true, kPassIX>(v, t, lds, stw);
+  if (!active) return;
   const int NS = N / 2 + 2;
   R* out = static_cast<R*>(F.out);
   const R* S = static_cast<const R*>(F.S);
   const R* Sl = static_cast<const R*>(F.Slo);
-  const int iz = z / 2 + 1, iy = y / 2 + 1;
-  const int jz = iz + ((z & 1) ? 1 : -1), jy = iy + ((y & 1) ? 1 : -1);
-  const size_t srow_i = ((size_t)iz * NS + iy) * NS, srow_j = ((size_t)jz * NS + jy) * NS;
-  R* orow = out + ((size_t)z * N + y) * N;
+  const int iz = z / 2 + 1, jz = iz + ((z & 1) ? 1 : -1);
 #pragma unroll
-  for (int q = 0; q < E / 2; ++q) {
-    const int xd = t + TL * q;  // even doubled x
-    if (xd >= ND) continue;
-    const int x = xd / 2;
-    const R m = (R)0.125 * tot[q];
-    const R hole = orow[x];
-    R hi, lo = 0;
-    if (sizeof(R) == 8 || !F.comp) {
-      hi = hole + m;
-      if (S) {
-        R s1, l;
-        carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
-        hi += s1;
-      }
-    } else {
-      R e0;
-      two_sum(hole, m, hi, e0);
-      lo = e0;
-      if (S) {
-        R s1, l, s2, e3;
-        carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
-        two_sum(hi, s1, s2, e3);
-        hi = s2;
-        lo += e3 + l;
-      }
+  for (int h = 0; h < 2; ++h) {
+    const int yy = y + h;
+    const int iy = yy / 2 + 1, jy = iy + ((yy & 1) ? 1 : -1);
+    const size_t srow_i = ((size_t)iz * NS + iy) * NS, srow_j = ((size_t)jz * NS + jy) * NS;
+    R* orow = out + ((size_t)z * N + yy) * N;
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) {
+      const int x = t + TL * q;
+      if (x < N) doubled_out<R>(F, orow, S, Sl, srow_i, srow_j, x, h == 0 ? v[q].x : v[q].y);
     }
-    orow[x] = hi + lo;
   }
 }
 
@@ -1439,12 +1484,6 @@ hipError_t launch_inv_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassIY>;
     dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
-    if constexpr (PP >= 16) {
-      if (PP >= 4 * g.N) {  // doubled grids
-        launch(k_inv_y<R, PP, false, true>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
-        return;
-      }
-    }
     if (g.N == PP / 2)
       launch(k_inv_y<R, PP, true>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
     else
@@ -1474,16 +1513,28 @@ hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
 }
 
 template <class R>
-hipError_t launch_inv_x_dbl(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
-  // doubled grids: a period of at least 2 (2N) cells, and at least 16 so
-  // that x neighbours sit in lane pairs
+hipError_t launch_inv_y_fold(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  // g.P is the doubled grids' period 2P (>= 4N); the transforms run at P
   if (g.P < 4 * g.N || g.P < 16) return hipErrorInvalidValue;
-  return dispatch_p(g.P, [&](auto pc) {
+  return dispatch_p(g.P / 2, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
-    if constexpr (PP >= 16) {
+    if constexpr (PP <= 256) {
+      using C = Cfg<R, PP, kPassIY>;
+      dim3 grid((PP / C::WS) * g.N, g.nf);
+      launch(k_inv_y_fold<R, PP>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+    }
+  });
+}
+
+template <class R>
+hipError_t launch_inv_x_fold(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
+  if (g.P < 4 * g.N || g.P < 16) return hipErrorInvalidValue;
+  return dispatch_p(g.P / 2, [&](auto pc) {
+    constexpr int PP = decltype(pc)::value;
+    if constexpr (PP <= 256) {
       using C = Cfg<R, PP, kPassIX>;
-      dim3 grid((g.N * g.N + C::WC - 1) / C::WC, g.nf);
-      launch(k_inv_x_dbl<R, PP>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+      dim3 grid((g.N * g.N / 2 + C::WC - 1) / C::WC, g.nf);
+      launch(k_inv_x_fold<R, PP>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
     }
   });
 }
@@ -1628,7 +1679,8 @@ hipError_t launch_fft_lines(const void* in, void* out, int P, int nlines, int di
   template hipError_t launch_z<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);           \
   template hipError_t launch_inv_y<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
   template hipError_t launch_inv_x<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);       \
-  template hipError_t launch_inv_x_dbl<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);   \
+  template hipError_t launch_inv_y_fold<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);  \
+  template hipError_t launch_inv_x_fold<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);  \
   template hipError_t launch_fwd_xy<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);      \
   template hipError_t launch_inv_yx<R>(const FieldTable&, PassGeom, Tables<R>, hipStream_t);      \
   template bool plane_passes_fit<R>(int);                                                         \

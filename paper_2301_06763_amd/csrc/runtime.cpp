@@ -95,9 +95,10 @@ Layout make_layout(int N, int L, nmc_precision p, unsigned flags) {
   lo.a_full = align_up((size_t)N * N * (P / 2) * lo.c);
   lo.b_full = align_up((size_t)N * P * (P / 2) * lo.c);
   if (lo.mod) {
-    // doubled grid: inputs N rows, outputs 2N rows per axis, period 2P
+    // doubled grid, period 2P: N x N rows of the x half spectrum (P values;
+    // x-pass output and folded y-inverse output), 2N z rows after the z pass
     const size_t PD = 2 * P, ND = 2 * (size_t)N;
-    lo.a_sec = align_up(ND * ND * (PD / 2) * lo.c);
+    lo.a_sec = align_up((size_t)N * N * (PD / 2) * lo.c);
     lo.b_sec = align_up(ND * PD * (PD / 2) * lo.c);
   } else {
     lo.a_sec = align_up(ns * ns * (P / 2) * lo.c);
@@ -435,7 +436,11 @@ struct PassBytes {
   }
   double y() const { return nin * nin * half() * c + nin * P * half() * c; }
   double z() const { return (nin + nout) * P * half() * c + H * H * H * r; }
-  double iy() const { return nout * P * half() * c + nout * nout * half() * c; }
+  double iy() const {
+    if (kind == 3)  // folded: all 2N z rows read, N x N rows written
+      return nout * P * half() * c + N * N * half() * c;
+    return nout * P * half() * c + nout * nout * half() * c;
+  }
   // fused plane passes: the x-transformed plane stays on chip
   double xy() const {
     const double in = kind == 1 ? std::pow(N / 2, 3) : N * N * N;
@@ -448,10 +453,10 @@ struct PassBytes {
     return nout * nout * half() * c + nout * nout * nout * r + (carry ? NS * NS * NS * r : 0.0) +
            (next ? (kind == 4 ? 1 : 2) * NS * NS * NS * r : 0.0);
   }
-  // doubled grid's last pass: its (2N)^2 half spectra read, the hole
+  // doubled grid's folded last pass: N^2 half spectra read, the hole
   // potential read and Phi(Omega^l) written on N^3 cells, the carry read
   double ix_doubled(bool carry) const {
-    return nout * nout * half() * c + 2 * N * N * N * r + (carry ? NS * NS * NS * r : 0.0);
+    return N * N * half() * c + 2 * N * N * N * r + (carry ? NS * NS * NS * r : 0.0);
   }
 };
 
@@ -674,17 +679,13 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     }
     return NMC_OK;
   };
-  auto forward_to_iy_p = [&](const std::vector<FieldDesc>& fs, int nin, int nout, hipStream_t st, int Pc,
-                             const nmc::Tables<R>& tbc) -> int {
-    if (fs.empty()) return NMC_OK;
-    NMC_HIP(ctx, for_chunks_p(fs, nin, nmc::launch_fwd_x<R>, NMC_PASS_X, st, Pc, tbc));
-    NMC_HIP(ctx, for_chunks_p(fs, nin, nmc::launch_fwd_y<R>, NMC_PASS_Y, st, Pc, tbc));
-    NMC_HIP(ctx, for_chunks_p(fs, nin, nmc::launch_z<R>, NMC_PASS_Z, st, Pc, tbc));
-    NMC_HIP(ctx, for_chunks_p(fs, nout, nmc::launch_inv_y<R>, NMC_PASS_IY, st, Pc, tbc));
-    return NMC_OK;
-  };
   auto forward_to_iy = [&](const std::vector<FieldDesc>& fs, int nin, int nout, hipStream_t st) -> int {
-    return forward_to_iy_p(fs, nin, nout, st, P, tb);
+    if (fs.empty()) return NMC_OK;
+    NMC_HIP(ctx, for_chunks(fs, nin, nmc::launch_fwd_x<R>, NMC_PASS_X, st));
+    NMC_HIP(ctx, for_chunks(fs, nin, nmc::launch_fwd_y<R>, NMC_PASS_Y, st));
+    NMC_HIP(ctx, for_chunks(fs, nin, nmc::launch_z<R>, NMC_PASS_Z, st));
+    NMC_HIP(ctx, for_chunks(fs, nout, nmc::launch_inv_y<R>, NMC_PASS_IY, st));
+    return NMC_OK;
   };
   int rc;
   const bool one_stream = (reqs[0].flags & NMC_ONE_STREAM) != 0;
@@ -697,11 +698,19 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     if ((rc = restrict_cascade(s))) return rc;
     std::vector<FieldDesc> holes, finest;
     for (const auto& f : fulls) (f.kind == 4 ? holes : finest).push_back(f);
+    auto doubled_to_iy = [&](hipStream_t st) -> int {
+      if (secs.empty()) return NMC_OK;
+      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_fwd_x<R>, NMC_PASS_X, st, PD, tbd));
+      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_fwd_y<R>, NMC_PASS_Y, st, PD, tbd));
+      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_z<R>, NMC_PASS_Z, st, PD, tbd));
+      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_inv_y_fold<R>, NMC_PASS_IY, st, PD, tbd));
+      return NMC_OK;
+    };
     const bool fork = aux && aux != s && !secs.empty() && !ctx->profiling && !one_stream;
     if (fork) {
       NMC_HIP(ctx, hipEventRecord(ctx->ev_fork, s));
       NMC_HIP(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0));
-      if ((rc = forward_to_iy_p(secs, N, 2 * N, aux, PD, tbd))) return rc;
+      if ((rc = doubled_to_iy(aux))) return rc;
       NMC_HIP(ctx, hipEventRecord(ctx->ev_join, aux));
     }
     if (fused) {
@@ -718,11 +727,11 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     }
     if (fork) {
       NMC_HIP(ctx, hipStreamWaitEvent(s, ctx->ev_join, 0));
-    } else if ((rc = forward_to_iy_p(secs, N, 2 * N, s, PD, tbd))) {
+    } else if ((rc = doubled_to_iy(s))) {
       return rc;
     }
     if (!secs.empty())
-      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_inv_x_dbl<R>, NMC_PASS_IX_DOUBLED, s, PD, tbd));
+      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_inv_x_fold<R>, NMC_PASS_IX_DOUBLED, s, PD, tbd));
     return NMC_OK;
   }
   if (!boxes) {

@@ -76,10 +76,11 @@ def test_footprint_of_the_modified_method(lib):
     from paper_2301_06763_amd import nmc
     import torch
     # L full-size grids (L-1 hole grids and the finest level) plus L-1 doubled
-    # grids of period 2P: A = (2N)^2 (P) and B = 2N (2P) P complex values each
+    # grids of period 2P: A = N^2 P (x half spectra) and B = 2N (2P) P
+    # (2N z rows after the z pass) complex values each
     N, L, P = 32, 4, 64
     grid = (N * N * (P // 2) + N * P * (P // 2)) * 16
-    dbl = ((2 * N) ** 2 * P + 2 * N * (2 * P) * P) * 16
+    dbl = (N * N * P + 2 * N * (2 * P) * P) * 16
     fp = nmc.footprint_bytes(N, L, torch.float64, nmc.NMC_MODIFIED)
     assert L * grid + (L - 1) * dbl <= fp < (L * grid + (L - 1) * dbl) * 1.05
     assert fp > nmc.footprint_bytes(N, L, torch.float64)
