@@ -51,6 +51,14 @@ Readings where the paper is silent or ambiguous:
   spans level n; its potential is brought to level n's cells ("tilde",
   fine to coarse) as the mean over the 2^3 fine cells each coarse cell
   covers, the same averaging as the acceleration's method B.
+* R20 three-level dipole scheme, Appendix B (the equations for dipoles
+  across three neighbouring grids): for a level n with two finer levels,
+  the doubled grid holds level n+1's density with its own child region
+  zeroed (the "dbl,hole" grid, so that level n+2's mass is not counted
+  twice), and the quadrupled grid holds level n+2's (restricted) density
+  centred in 4N cells of level n+2's spacing spanning level n, reduced by
+  the mean over the 4^3 cells each level-n cell covers.  The second finest
+  level keeps the pairwise doubled grid, the finest its own full grid.
 * R17 acceleration at covered cells (inside the child region) uses the
   level's own potential; method B applies to coarse cells outside the child
   region whose stencil neighbour lies inside it.
@@ -300,8 +308,22 @@ def doubled_potential(mass_fine: np.ndarray, h_fine: float, G: float = 1.0, meth
     return Pd.reshape(N, 2, N, 2, N, 2).mean(axis=(1, 3, 5))
 
 
+def quadrupled_potential(mass_fine: np.ndarray, h_fine: float, G: float = 1.0, method: str = "fft") -> np.ndarray:
+    """Reduced potential of the quadrupled grid of Appendix B (three-level
+    scheme): the masses of level n+2 (N^3 cells of spacing h_fine) placed at
+    cells [3N/2, 5N/2) per axis of a grid of 4N cells of that spacing, which
+    spans level n, zeros around; reduced to level n's N^3 cells by the mean
+    over the 4^3 fine cells each covers (reading R20)."""
+    N = mass_fine.shape[0]
+    Mq = np.zeros((4 * N, 4 * N, 4 * N), dtype=np.float64)
+    a, b = 3 * N // 2, 5 * N // 2
+    Mq[a:b, a:b, a:b] = mass_fine
+    Pq = _single_grid(method)(Mq, h_fine, G)
+    return Pq.reshape(N, 4, N, 4, N, 4).mean(axis=(1, 3, 5))
+
+
 def solve_modified(rho: np.ndarray, h0: float, G: float = 1.0, *, restrict: bool = True,
-                   method: str = "fft") -> np.ndarray:
+                   method: str = "fft", scheme: str = "pairs") -> np.ndarray:
     """The modified convolution method that keeps the dipole moments across
     every pair of neighbouring grids (Sect. 7, Appendix B, Eqs. B.1-B.2):
     Phi(Omega^n) = Phi^n_hole + ~Phi^{n+1}_dbl + (hole potentials of the
@@ -309,7 +331,14 @@ def solve_modified(rho: np.ndarray, h0: float, G: float = 1.0, *, restrict: bool
     finest, which is Phi^L + the carried hole potentials.  The coarse grid
     thus sees the finer level's masses at the finer resolution instead of
     their restriction, so opposite charges inside one coarse cell no longer
-    cancel (Sect. 7, Fig. 15)."""
+    cancel (Sect. 7, Fig. 15).
+
+    scheme="triples" is Appendix B's scheme for dipoles across three
+    neighbouring grids: a level n with two finer levels takes
+    Phi^n_hole + ~Phi^{n+1}_{dbl,hole} + ~Phi^{n+2}_{qdp} + the carry
+    (reading R20); the other levels are as in "pairs"."""
+    if scheme not in ("pairs", "triples"):
+        raise ValueError("scheme must be 'pairs' or 'triples'")
     rho = np.asarray(rho, dtype=np.float64)
     L, N = rho.shape[0], rho.shape[1]
     if N % 4:
@@ -325,7 +354,12 @@ def solve_modified(rho: np.ndarray, h0: float, G: float = 1.0, *, restrict: bool
         if n < L - 1:
             hole_n = conv(hole(M), h, G)
             hf = level_spacing(h0, n + 1)
-            phi[n] = hole_n + doubled_potential(rr[n + 1] * hf ** 3, hf, G, method) + A
+            if scheme == "triples" and n < L - 2:
+                hq = level_spacing(h0, n + 2)
+                phi[n] = (hole_n + doubled_potential(hole(rr[n + 1] * hf ** 3), hf, G, method)
+                          + quadrupled_potential(rr[n + 2] * hq ** 3, hq, G, method) + A)
+            else:
+                phi[n] = hole_n + doubled_potential(rr[n + 1] * hf ** 3, hf, G, method) + A
             S = A + hole_n
         else:
             phi[n] = conv(M, h, G) + A

@@ -98,3 +98,29 @@ def test_smooth_densities_four_levels(case, fn, slack):
     assert d[-1] < 1e-13  # the finest level is the same in both methods
     assert worst < slack * bound, (case, [100 * v for v in d])
     assert worst > 0.3 * bound  # the pin is not vacuous: the methods do differ
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_close_binary_three_levels(n):
+    """Fig. 18, right column: three nested grids, the close binary on the
+    finest; the pairwise scheme and the three-level scheme agree on the two
+    finer grids and differ on the coarsest by at most 1.5 % (N = 32) and
+    0.7 % (N = 64) on the plane through the binary, halving with N (the
+    paper's 0.35 % at N = 128 needs a 1024^3 transform, not pinned).  The
+    oracle gives 1.58 % and 0.80 % (up to 15 % slack for the unstated
+    placement)."""
+    g = golden()["close_binary_3_levels"]
+    h0 = BOX / n
+    c = slice(n // 4, 3 * n // 4)
+    m = np.ones((n, n, n), bool)
+    m[c, c, c] = False
+    rho = np.zeros((3, n, n, n))
+    rho[2, n // 2, n // 2, n // 2 - 1] = 1.0
+    rho[2, n // 2, n // 2, n // 2] = 2.0
+    p2 = oracle.solve_modified(rho, h0)
+    p3 = oracle.solve_modified(rho, h0, scheme="triples")
+    assert np.array_equal(p2[1:], p3[1:])
+    e = np.where(m, np.abs(p2[0] - p3[0]) / np.abs(p3[0]), 0.0)
+    plane = 100 * e[:, n // 2, :].max()
+    bound = g[f"N{n}_max_percent_below"]
+    assert 0.6 * bound < plane < 1.15 * bound, plane

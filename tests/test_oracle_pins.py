@@ -451,3 +451,70 @@ def test_modified_method_keeps_the_dipole():
     far = r > 4 * h0
     scale = np.abs(exact[far]).max()
     assert np.max(np.abs(mod[0] - exact)[far]) < 0.05 * scale
+
+
+# --- three-level dipole scheme, Appendix B ----------------------------------
+
+@pytest.mark.parametrize("N,L", [(4, 3), (4, 4)])
+def test_triples_fft_equals_direct(N, L):
+    """The quadrupled and doubled-hole grids are zero-padded convolutions:
+    the three-level scheme by FFTs equals the same by brute-force sums."""
+    rho = np.random.default_rng(60 + N + L).random((L, N, N, N))
+    a = oracle.solve_modified(rho, 1.0 / N, G=0.9, scheme="triples")
+    b = oracle.solve_modified(rho, 1.0 / N, G=0.9, scheme="triples", method="direct")
+    assert np.max(np.abs(a - b) / np.abs(b)) < 1e-12
+
+
+def test_triples_differ_from_pairs_only_where_two_finer_levels_exist():
+    rho = np.random.default_rng(5).random((4, 8, 8, 8))
+    p2 = oracle.solve_modified(rho, 0.1)
+    p3 = oracle.solve_modified(rho, 0.1, scheme="triples")
+    assert np.array_equal(p2[2:], p3[2:])          # levels L-2 and L-1 as in the pairwise scheme
+    assert np.max(np.abs(p2[:2] - p3[:2])) > 0       # the two coarsest see level n+2 at its own resolution
+    two = rho[:2]
+    assert np.array_equal(oracle.solve_modified(two, 0.1), oracle.solve_modified(two, 0.1, scheme="triples"))
+
+
+def test_quadrupled_potential_is_fine_resolution_sum_averaged():
+    """The reduced quadrupled potential at a level-n cell is the mean, over
+    the 4^3 level-(n+2) cells it covers, of the level-(n+2) masses' potential
+    summed directly at those cell centres (physical positions)."""
+    N = 8
+    hq = 1.0 / 32
+    mass = np.random.default_rng(11).random((N, N, N))
+    red = oracle.quadrupled_potential(mass, hq, G=0.8)
+    xs = oracle.cell_centres(N, hq)        # level n+2, centred
+    xc = oracle.cell_centres(N, 4 * hq)    # level n, centred
+    src = np.stack(np.meshgrid(xs, xs, xs, indexing="ij"), -1).reshape(-1, 3)
+    m = mass.reshape(-1)
+    offs = (np.arange(4) - 1.5) * hq
+    for c in [(0, 0, 0), (7, 2, 5), (1, 7, 3)]:
+        centre = np.array([xc[c[0]], xc[c[1]], xc[c[2]]])
+        vals = [-0.8 * np.sum(m / np.linalg.norm(src - (centre + np.array([dz, dy, dx])), axis=1))
+                for dz in offs for dy in offs for dx in offs]
+        assert abs(red[c] - np.mean(vals)) < 1e-12 * abs(np.mean(vals))
+
+
+def test_triples_keep_the_dipole_across_two_levels():
+    """Opposite masses in two level-2 cells under one level-1 cell cancel in
+    level 1's restricted density, so the pairwise scheme's coarsest level
+    sees nothing of them; the three-level scheme's coarsest level sees their
+    dipole field (direct sum of the two point masses) away from them."""
+    N, L = 16, 3
+    h0 = 1.0 / N
+    hq = h0 / 4
+    rho = np.zeros((L, N, N, N))
+    c = N // 2
+    rho[2, c, c, c - 2] = 1.0 / hq ** 3
+    rho[2, c, c, c - 1] = -1.0 / hq ** 3
+    pairs = oracle.solve_modified(rho, h0)
+    triples = oracle.solve_modified(rho, h0, scheme="triples")
+    assert np.max(np.abs(pairs[0])) < 1e-12
+    xq = oracle.cell_centres(N, hq)
+    xc = oracle.cell_centres(N, h0)
+    Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")
+    def pot(px):
+        return -1.0 / np.sqrt((X - xq[px]) ** 2 + (Y - xq[c]) ** 2 + (Z - xq[c]) ** 2)
+    exact = pot(c - 2) - pot(c - 1)
+    far = np.sqrt(X ** 2 + Y ** 2 + Z ** 2) > 4 * h0
+    assert np.max(np.abs(triples[0] - exact)[far]) < 0.05 * np.abs(exact[far]).max()
