@@ -78,7 +78,7 @@ enum {
    * apply (P <= 64, hole-grid formulation; default there: one XY and one
    * I2+I1 launch per kind of grid, each z plane kept in LDS).  For
    * ablation.  In a batch, ONE_STREAM and NO_FUSED_PLANES are taken from the
-   * first request of each group of equal N, precision and NMC_MODIFIED. */
+   * first request of each group of equal N, precision and method. */
   NMC_NO_FUSED_PLANES = 1u << 5,
   /* The modified convolution method of Sect. 7 and Appendix B (Eqs. B.1,
    * B.2), which keeps the dipole moments between neighbouring levels: for
@@ -88,7 +88,15 @@ enum {
    * each level-l cell + the coarser hole potentials carried down as in
    * Eq. 14; the finest level is unchanged.  Needs 2P <= 512 (N <= 128) and
    * a larger workspace (nmc_footprint_bytes_flags). */
-  NMC_MODIFIED = 1u << 6
+  NMC_MODIFIED = 1u << 6,
+  /* The modified method with Appendix B's scheme for dipoles across three
+   * neighbouring grids (implies NMC_MODIFIED): every level l with two finer
+   * levels takes Phi^l_hole + level l+1's density with its child region
+   * zeroed on the doubled grid + level l+2's density on a quadrupled grid
+   * (4N cells of level l+2's spacing spanning level l, period 4P, averaged
+   * over the 4^3 cells of each level-l cell) + the carry; the two finest
+   * levels as with NMC_MODIFIED.  Needs 4P <= 512 (N <= 64) when L >= 3. */
+  NMC_MODIFIED3 = 1u << 7
 };
 
 /* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
@@ -111,8 +119,9 @@ const char* nmc_last_error(const nmc_ctx* ctx);
 int nmc_footprint_bytes(int N, int L, nmc_precision p, size_t* bytes);
 
 /* The same for a solve with these flags (NMC_MODIFIED adds the doubled
- * grids' FFT buffers).  Errors: NMC_EINVAL, NMC_EUNSUPPORTED (also for
- * NMC_MODIFIED with N above 128). */
+ * grids' FFT buffers, NMC_MODIFIED3 also the quadrupled grids').  Errors:
+ * NMC_EINVAL, NMC_EUNSUPPORTED (also for NMC_MODIFIED with N above 128 and
+ * NMC_MODIFIED3 with N above 64 and L >= 3). */
 int nmc_footprint_bytes_flags(int N, int L, nmc_precision p, unsigned flags, size_t* bytes);
 
 /* Solve one nested mesh (Sect. 4, Eq. 14).
@@ -127,7 +136,7 @@ int nmc_footprint_bytes_flags(int N, int L, nmc_precision p, unsigned flags, siz
  *   G     gravitational constant (finite)
  *   p     element type of rho and phi and arithmetic of the FFT path
  *   flags NMC_NO_RESTRICT, NMC_F32_UNCOMPENSATED, NMC_NO_GRAPH, NMC_ONE_STREAM,
- *         NMC_NO_FUSED_PLANES, NMC_MODIFIED
+ *         NMC_NO_FUSED_PLANES, NMC_MODIFIED, NMC_MODIFIED3
  *   hip_stream  hipStream_t to enqueue on.  The hole grids and the carry
  *         cascade run on a second, library-owned stream that is forked from
  *         and joined back into hip_stream, so completion is ordered on
@@ -151,8 +160,9 @@ typedef struct {
 
 /* Solve `count` independent nested meshes (Sect. 4: the grids of a solve are
  * independent, and so are solves).  Requests of equal N, precision and
- * NMC_MODIFIED bit share every FFT pass launch.  Each result is bitwise
- * identical to the same request solved alone.  All requests are validated before any work. */
+ * method (original, NMC_MODIFIED, NMC_MODIFIED3) share every FFT pass
+ * launch.  Each result is bitwise identical to the same request solved
+ * alone.  All requests are validated before any work. */
 int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_stream);
 
 /* ---- Serving: continuous batching over library-owned streams ----------

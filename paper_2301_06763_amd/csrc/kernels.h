@@ -28,7 +28,11 @@ namespace nmc {
 //    level l's N cells per axis by the inverse passes (out: level l's
 //    potential, to which the reduced values and the carry S are added);
 //  * kind 4 (modified method), kind 2's grid with full output: out gets the
-//    hole potential on all N^3 cells and Sout its stencil box.
+//    hole potential on all N^3 cells and Sout its stencil box;
+//  * kind 5 (three-level scheme of Appendix B), kind 3 with the input's
+//    child region zeroed (the doubled hole grid).  Kinds 3 and 5 also serve
+//    at scale 4 (quadrupled grid: 4N cells of level l+2's spacing, period
+//    4P, input rows at [3N/2, 5N/2)); PassGeom.S gives the scale.
 struct FieldDesc {
   const void* rho;   // level density [N][N][N] (x fastest), caller-owned
   const void* rc;    // restriction data of the child region (pyramid slab of level l+1), or null
@@ -109,9 +113,10 @@ struct FieldTable {
 
 struct PassGeom {
   int N;     // cells per axis of the level
-  int P;     // padded period (power of two >= 2N)
+  int P;     // padded period (power of two >= 2N; S times the level's for scaled grids)
   int n;     // largest nin (x, y passes) or nout (inverse passes) of the launch's grids
   int nf;    // grids in this launch
+  int S;     // scale factor of the launch's grids: 1, or 2 (doubled) / 4 (quadrupled) for kinds 3, 5
 };
 
 template <class R>
@@ -139,11 +144,12 @@ template <class R> hipError_t launch_z(const FieldTable&, PassGeom, Tables<R>, h
 // Inverse passes (output-pruned).
 template <class R> hipError_t launch_inv_y(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 template <class R> hipError_t launch_inv_x(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
-// Inverse passes of the doubled grids (kind 3, modified method) after their
-// z pass, with the 2^3 mean taken in the spectrum (each transform at half
-// the period): I2 (sum of z rows 2j, 2j+1, y fold, rows y < N kept) and I1
-// (x fold, C2R, the mean added to the hole potential in out and the carry).
-// g.N is the level's N, g.P the doubled grids' period (>= 4N); tb its tables.
+// Inverse passes of the scaled grids (kinds 3, 5: modified method) after
+// their z pass, with the S^3 mean taken in the spectrum (each transform at
+// the level's period g.P / g.S): I2 (sum of z rows S j .. S j + S - 1, y
+// fold, rows y < N kept) and I1 (x fold, C2R, the mean added to out, plus
+// the carry S when set).  g.N is the level's N, g.P the scaled period
+// (>= 4N), g.S = 2 or 4; tb its tables.
 template <class R> hipError_t launch_inv_y_fold(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 template <class R> hipError_t launch_inv_x_fold(const FieldTable&, PassGeom, Tables<R>, hipStream_t);
 

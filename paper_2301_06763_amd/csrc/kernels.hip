@@ -138,11 +138,13 @@ __device__ __forceinline__ R restricted_at(const FieldDesc& F, int N, int cz, in
 struct GridGeo {
   int nin, olo, nout, ilo;
 };
-// DBL: a launch of doubled grids (kind 3 only); kept out of the other
-// launches' code, where the extra case measurably costs registers.
+// DBL: a launch of scaled grids (kinds 3 and 5, scale factor S = 2 or 4:
+// S N cells of the finer level's spacing spanning level l, its N input rows
+// centred at (S-1) N/2, S N output rows); kept out of the other launches'
+// code, where the extra case measurably costs registers.
 template <bool DBL = false>
-__device__ __forceinline__ GridGeo grid_geo(int kind, int N) {
-  if (DBL) return GridGeo{N, 0, 2 * N, N / 2};
+__device__ __forceinline__ GridGeo grid_geo(int kind, int N, int S = 1) {
+  if (DBL) return GridGeo{N, 0, S * N, (S - 1) * N / 2};
   if (kind == 0 || kind == 4) return GridGeo{N, 0, N, 0};
   if (kind == 1) return GridGeo{N / 2 + 2, 0, N / 2 + 2, 0};
   return GridGeo{N, N / 4 - 1, N / 2 + 2, 0};
@@ -153,12 +155,12 @@ __device__ __forceinline__ GridGeo grid_geo(int kind, int N) {
 //
 // Inputs of the x line (z, y) of a grid: thread t's points x = t + TL q,
 // q < E/2 (the upper half is the zero padding).  Kinds 0, 3: the level's row
-// with the child region restricted when rc is set (kind 3 places it at
-// x + N/2 of the frame); kinds 2, 4: the row with the child region zeroed;
+// with the child region restricted when rc is set (kinds 3 and 5 place it at
+// x + xo of the frame); kinds 2, 4, 5: the row with the child region zeroed;
 // kind 1: row of the child-region box.  An inactive line gives zeros.
 template <class R, int P, bool FULLN, int K, bool DBL = false>
 __device__ __forceinline__ void x_inputs(const FieldDesc& F, int N, int z, int y, bool active, int t,
-                                         cplx<R>* v) {
+                                         cplx<R>* v, int xo = 0) {
   using T = cplx<R>;
   constexpr int E = Plan<R, P, K>::E, TL = P / E;
   const R* rho = static_cast<const R*>(F.rho);
@@ -166,10 +168,10 @@ __device__ __forceinline__ void x_inputs(const FieldDesc& F, int N, int z, int y
   const int N2 = N / 2;
   if (F.kind != 1) {
     const int lo = N / 4, hi = 3 * N / 4;
-    const int xo = DBL ? N / 2 : 0;  // frame offset of the row (doubled grids, kind 3)
+    // xo: frame offset of the row (scaled grids); kind 5 zeroes the child region
     const bool yz_in = z >= lo && z < hi && y >= lo && y < hi;
     const bool use_rc = (DBL || F.kind == 0) && rc && yz_in;
-    const bool zero_c = (F.kind == 2 || F.kind == 4) && yz_in;
+    const bool zero_c = (F.kind == 2 || F.kind == 4 || (DBL && F.kind == 5)) && yz_in;
     const size_t row = ((size_t)z * N + y) * N;
     // the level's own values first, all loads at once (a valid cell stands
     // in where the value is dropped), then the restricted child region
@@ -242,7 +244,7 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ cplx<R> stw[P];
   const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
-  const int N = FULLN ? P / 2 : g.N, n = grid_geo<DBL>(F.kind, N).nin;
+  const int N = FULLN ? P / 2 : g.N, n = grid_geo<DBL>(F.kind, N, g.S).nin;
   const int nunits = n * n / LPW;  // n is even: the two lines of a pair share z
   if ((int)blockIdx.x * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
@@ -251,10 +253,11 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int line = active ? LPW * unit : 0;
   const int z = line / n, y = line % n;
   T va[E], v[E];
-  x_inputs<R, P, FULLN, kPassX, DBL>(F, N, z, y, active, t, va);
+  const int xo = DBL ? (g.S - 1) * N / 2 : 0;
+  x_inputs<R, P, FULLN, kPassX, DBL>(F, N, z, y, active, t, va, xo);
   if constexpr (PAIRS) {
     T vb[E];
-    x_inputs<R, P, FULLN, kPassX, DBL>(F, N, z, y + 1, active, t, vb);
+    x_inputs<R, P, FULLN, kPassX, DBL>(F, N, z, y + 1, active, t, vb, xo);
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) v[q] = T{va[q].x, vb[q].x};
   } else {
@@ -312,7 +315,7 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   const TwStage<R, P, C::WS * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const bool full = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks
-  const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N);
+  const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N, g.S);
   const int n = gg.nin;
   const int tile = blockIdx.x % NT, z = blockIdx.x / NT;
   if (z >= n) return;  // uniform: a smaller grid of a mixed launch
@@ -375,7 +378,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   const FieldDesc& F = ft.f[f];
   const bool full_in = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks on loads
   const bool full = FULLN && F.kind == 0;     // nout = N = P/2 as well
-  const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N);
+  const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N, g.S);
   const int n = gg.nin;
   const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
   const int tile = unit % NT, p = unit / NT;
@@ -692,19 +695,21 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
 }
 
 // ---------------------------------------------------------------------------
-// Inverse passes of the doubled grids (kind 3) of the modified method
+// Inverse passes of the scaled grids (kinds 3 and 5) of the modified method
 // (Sect. 7, Appendix B), with the reduction to level l taken in the
-// spectrum.  The doubled grid of the pair (l, l+1) has 2N cells per axis of
-// level l+1's spacing and spans level l: level cell j covers the doubled
-// cells 2j and 2j + 1 per axis, and its value is the mean of the 2^3.  For a
-// line of doubled values x_n of period 2P with spectrum X (x_n = sum_K X[K]
-// exp(2 pi i K n / 2P)), the pair means y_j = (x_2j + x_2j+1) / 2 have the
-// period-P spectrum
-//   Y[k] = ((X[k] + X[k+P]) + w^k (X[k] - X[k+P])) / 2,  w = exp(2 pi i / 2P),
-// so each inverse transform runs at length P on the folded spectrum and
-// yields level l's cells directly.  The z pairs are averaged by adding the
-// z pass's rows 2j and 2j + 1 (the y and x transforms are linear).
-// fold_pair: Y[k] from X[k] = a, X[k+P] = b and wc = exp(-2 pi i k / 2P)
+// spectrum.  A doubled (S = 2) or quadrupled (S = 4) grid has S N cells per
+// axis of the finer level's spacing and spans level l: level cell j covers
+// the scaled cells S j .. S j + S - 1 per axis, and its value is the mean of
+// the S^3.  For a line of values x_n of period 2Q with spectrum X
+// (x_n = sum_K X[K] exp(2 pi i K n / 2Q)), the pair means
+// y_j = (x_2j + x_2j+1) / 2 have the period-Q spectrum
+//   Y[k] = ((X[k] + X[k+Q]) + w^k (X[k] - X[k+Q])) / 2,  w = exp(2 pi i / 2Q),
+// and the means of four are the pair means of the pair means.  So each
+// inverse transform runs at the level's period P on the spectrum folded
+// log2 S times and yields level l's cells directly.  The z means are taken
+// by adding the z pass's rows S j .. S j + S - 1 (the y and x transforms
+// are linear).
+// fold_pair: Y[k] from X[k] = a, X[k+Q] = b and wc = exp(-2 pi i k / 2Q)
 // (the table entry; w^k is its conjugate), times the extra factor s.
 template <class R>
 __device__ __forceinline__ cplx<R> fold_pair(cplx<R> a, cplx<R> b, cplx<R> wc, R s) {
@@ -713,62 +718,81 @@ __device__ __forceinline__ cplx<R> fold_pair(cplx<R> a, cplx<R> b, cplx<R> wc, R
   return cplx<R>{s * (a.x + b.x + wd.x), s * (a.y + b.y + wd.y)};
 }
 
-// I2 of the doubled grids: the y columns (level row z, kx) of the sum of
-// the z pass's rows 2z and 2z + 1, folded to length P and inverted, rows
-// y < N kept: A[z][y][kx] (kx < P, the x half spectrum of period 2P).
-template <class R, int P>
+// The period-P spectrum value Y[k] of the S-means from the period-S P
+// spectrum point values xs(m), m = k + P s (tw: the period-S P table).
+template <class R, int P, int S, class X>
+__device__ __forceinline__ cplx<R> fold_to_p(X xs, int k, const cplx<R>* __restrict__ tw) {
+  if constexpr (S == 2) {
+    return fold_pair<R>(xs(k), xs(k + P), tw[k], (R)0.5);
+  } else {
+    static_assert(S == 4, "scale 2 or 4");
+    const cplx<R> lo = fold_pair<R>(xs(k), xs(k + 2 * P), tw[k], (R)0.5);
+    const cplx<R> hi = fold_pair<R>(xs(k + P), xs(k + 3 * P), tw[k + P], (R)0.5);
+    return fold_pair<R>(lo, hi, tw[2 * k], (R)0.5);
+  }
+}
+
+// I2 of the scaled grids: the y columns (level row z, kx) of the sum of the
+// z pass's rows S z .. S z + S - 1, folded to length P and inverted, rows
+// y < N kept: A[z][y][kx] (kx < S P / 2, the x half spectrum).
+template <class R, int P, int S>
 __global__ void __launch_bounds__((Cfg<R, P, kPassIY>::WS * Cfg<R, P, kPassIY>::TL), (Cfg<R, P, kPassIY>::MINW))
 k_inv_y_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassIY>;
   using T = cplx<R>;
-  constexpr int E = C::E, TL = C::TL, W = C::WS, NT = P / W, PD = 2 * P;
+  constexpr int E = C::E, TL = C::TL, W = C::WS, PS = S * P, HS = PS / 2, NT = HS / W;
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
-  const TwStage<R, P, C::WS * C::TL, 2> tws(tb.tw);  // tb: the period-2P tables
+  const TwStage<R, P, C::WS * C::TL, S> tws(tb.tw);  // tb: the period-S P tables
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = g.N;
   const int z = blockIdx.x / NT;
   if (z >= N) return;  // uniform: a smaller grid of a mixed launch
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int kx = (blockIdx.x % NT) * W + w;
-  const T* B0 = static_cast<const T*>(F.B) + (size_t)(2 * z) * PD * P + kx;  // ky at + ky * P
-  const T* B1 = B0 + (size_t)PD * P;
+  const T* B0 = static_cast<const T*>(F.B) + (size_t)(S * z) * PS * HS + kx;  // row r, ky at + (r PS + ky) HS
+  // the z sum of the S rows at ky (all loads issued before the first fold)
+  auto zsum = [&](int ky) -> T {
+    T a{0, 0};
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      const T b = B0[((size_t)r * PS + ky) * HS];
+      a = T{a.x + b.x, a.y + b.y};
+    }
+    return T{a.x * ((R)1 / S), a.y * ((R)1 / S)};
+  };
   T v[E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) {
-    const int k = t + TL * q;
-    const T a0 = B0[(size_t)k * P], a1 = B1[(size_t)k * P];
-    const T b0 = B0[(size_t)(k + P) * P], b1 = B1[(size_t)(k + P) * P];
-    v[q] = fold_pair<R>(T{a0.x + a1.x, a0.y + a1.y}, T{b0.x + b1.x, b0.y + b1.y}, tb.tw[k], (R)0.25);
-  }
+  for (int q = 0; q < E; ++q) v[q] = fold_to_p<R, P, S>(zsum, t + TL * q, tb.tw);
   LdsView<R> lds{sre, sim, W, 1, w};
   tws.put(stw);
   fft_line<R, P, +1, false, true, kPassIY>(v, t, lds, stw);
-  T* A = static_cast<T*>(F.A) + (size_t)z * N * P + kx;
+  T* A = static_cast<T*>(F.A) + (size_t)z * N * HS + kx;
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
     const int y = t + TL * q;
-    if (y < N) A[(size_t)y * P] = v[q];
+    if (y < N) A[(size_t)y * HS] = v[q];
   }
 }
 
-// Phi(Omega^l) at level cell x of the row `orow` (holding the hole
-// potential): the hole potential + the reduced doubled-grid value m +
-// Prolong(S_{l-1}), summed with TwoSum on the compensated FP32 path.
+// Out(x) of the row `orow` plus the reduced scaled-grid value m and, when
+// S is set, Prolong(S_{l-1}); TwoSum on the compensated FP32 path.  For a
+// doubled grid out holds the hole potential, for a quadrupled grid (run
+// after it) the sum so far.
 template <class R>
-__device__ __forceinline__ void doubled_out(const FieldDesc& F, R* orow, const R* S, const R* Sl, size_t srow_i,
-                                            size_t srow_j, int x, R m) {
-  const R hole = orow[x];
+__device__ __forceinline__ void scaled_out(const FieldDesc& F, R* orow, const R* S, const R* Sl, size_t srow_i,
+                                           size_t srow_j, int x, R m) {
+  const R base = orow[x];
   R hi, lo = 0;
   if (sizeof(R) == 8 || !F.comp) {
-    hi = hole + m;
+    hi = base + m;
     if (S) {
       R s1, l;
       carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
       hi += s1;
     }
   } else {
-    two_sum(hole, m, hi, lo);
+    two_sum(base, m, hi, lo);
     if (S) {
       R s1, l, s2, e3;
       carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
@@ -780,20 +804,19 @@ __device__ __forceinline__ void doubled_out(const FieldDesc& F, R* orow, const R
   orow[x] = hi + lo;
 }
 
-// I1 of the doubled grids: the x half spectra (period 2P) of level rows
+// I1 of the scaled grids: the x half spectra (period S P) of level rows
 // (z, y) and (z, y + 1), folded to the packed half spectra of length P and
 // inverted as one complex transform (row y in the real part, y + 1 in the
-// imaginary part); then Phi(Omega^l) = Phi^l_hole (left in out by the hole
-// grid) + the doubled-grid mean + Prolong(S_{l-1}).
-template <class R, int P>
+// imaginary part); the S^3 means are added to out (scaled_out).
+template <class R, int P, int S>
 __global__ void __launch_bounds__((Cfg<R, P, kPassIX>::WC * Cfg<R, P, kPassIX>::TL))
 k_inv_x_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassIX>;
   using T = cplx<R>;
-  constexpr int E = C::E, TL = C::TL, W = C::WC;
+  constexpr int E = C::E, TL = C::TL, W = C::WC, PS = S * P, HS = PS / 2;
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
-  const TwStage<R, P, C::WC * C::TL, 2> tws(tb.tw);  // tb: the period-2P tables
+  const TwStage<R, P, C::WC * C::TL, S> tws(tb.tw);  // tb: the period-S P tables
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = g.N;
   const int nunits = N * N / 2;
@@ -803,16 +826,20 @@ k_inv_x_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
   const bool active = unit < nunits;
   const int line = active ? 2 * unit : 0;
   const int z = line / N, y = line % N;
-  const T* ra = static_cast<const T*>(F.A) + ((size_t)z * N + y) * P;
-  const T* rb = ra + P;
-  // Y[k], 0 <= k <= P/2, of a row: X[k+P] = conj(X[P-k]) (real input);
-  // k = 0 gives the DC value X[0], k = P/2 the real Re X[P/2] - Im X[P/2];
-  // every load is issued without a branch
+  const T* ra = static_cast<const T*>(F.A) + ((size_t)z * N + y) * HS;
+  const T* rb = ra + HS;
+  // X[m], 0 <= m < S P, of a real line from its packed half spectrum
+  // (slot 0: the real DC and Nyquist values; X[S P - m] = conj X[m])
+  auto spec = [](const T* r, int m) -> T {
+    const int i = m <= HS ? m : PS - m;
+    const T a = r[i == HS ? 0 : i];
+    const T u = i == 0 ? T{a.x, 0} : i == HS ? T{a.y, 0} : a;
+    return m <= HS ? u : T{u.x, -u.y};
+  };
+  // Y[k], 0 <= k <= P/2; Y[0] and Y[P/2] are real
   auto folded = [&](const T* r, int k) -> T {
-    const T a = r[k], c = r[k == 0 ? 0 : P - k];
-    if (k == 0) return T{a.x, 0};
-    if (k == P / 2) return T{a.x - a.y, 0};
-    return fold_pair<R>(a, T{c.x, -c.y}, tb.tw[k], (R)0.5);
+    const T u = fold_to_p<R, P, S>([&](int m) { return spec(r, m); }, k, tb.tw);
+    return (k == 0 || k == P / 2) ? T{u.x, 0} : u;
   };
   T v[E];
 #pragma unroll
@@ -833,7 +860,7 @@ k_inv_x_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
   if (!active) return;
   const int NS = N / 2 + 2;
   R* out = static_cast<R*>(F.out);
-  const R* S = static_cast<const R*>(F.S);
+  const R* Sc = static_cast<const R*>(F.S);
   const R* Sl = static_cast<const R*>(F.Slo);
   const int iz = z / 2 + 1, jz = iz + ((z & 1) ? 1 : -1);
 #pragma unroll
@@ -845,7 +872,7 @@ k_inv_x_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int x = t + TL * q;
-      if (x < N) doubled_out<R>(F, orow, S, Sl, srow_i, srow_j, x, h == 0 ? v[q].x : v[q].y);
+      if (x < N) scaled_out<R>(F, orow, Sc, Sl, srow_i, srow_j, x, h == 0 ? v[q].x : v[q].y);
     }
   }
 }
@@ -1514,27 +1541,36 @@ hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
 
 template <class R>
 hipError_t launch_inv_y_fold(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
-  // g.P is the doubled grids' period 2P (>= 4N); the transforms run at P
-  if (g.P < 4 * g.N || g.P < 16) return hipErrorInvalidValue;
-  return dispatch_p(g.P / 2, [&](auto pc) {
+  // g.P is the scaled period S P (>= 4N); the transforms run at P
+  if ((g.S != 2 && g.S != 4) || g.P < 4 * g.N || g.P / g.S < 8) return hipErrorInvalidValue;
+  return dispatch_p(g.P / g.S, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     if constexpr (PP <= 256) {
       using C = Cfg<R, PP, kPassIY>;
-      dim3 grid((PP / C::WS) * g.N, g.nf);
-      launch(k_inv_y_fold<R, PP>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+      if (g.S == 2) {
+        dim3 grid((PP / C::WS) * g.N, g.nf);
+        launch(k_inv_y_fold<R, PP, 2>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+      } else if constexpr (PP <= 128) {
+        dim3 grid((2 * PP / C::WS) * g.N, g.nf);
+        launch(k_inv_y_fold<R, PP, 4>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+      }
     }
   });
 }
 
 template <class R>
 hipError_t launch_inv_x_fold(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
-  if (g.P < 4 * g.N || g.P < 16) return hipErrorInvalidValue;
-  return dispatch_p(g.P / 2, [&](auto pc) {
+  if ((g.S != 2 && g.S != 4) || g.P < 4 * g.N || g.P / g.S < 8) return hipErrorInvalidValue;
+  return dispatch_p(g.P / g.S, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     if constexpr (PP <= 256) {
       using C = Cfg<R, PP, kPassIX>;
       dim3 grid((g.N * g.N / 2 + C::WC - 1) / C::WC, g.nf);
-      launch(k_inv_x_fold<R, PP>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+      if (g.S == 2) {
+        launch(k_inv_x_fold<R, PP, 2>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+      } else if constexpr (PP <= 128) {
+        launch(k_inv_x_fold<R, PP, 4>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+      }
     }
   });
 }

@@ -53,7 +53,17 @@ bool use_boxes(int N) { return N >= 128; }
 
 // The modified method (Sect. 7, Appendix B) convolves a doubled grid per
 // level pair on twice the period; it uses the hole-grid formulation.
-bool is_modified(unsigned flags) { return (flags & NMC_MODIFIED) != 0; }
+bool is_modified(unsigned flags) { return (flags & (NMC_MODIFIED | NMC_MODIFIED3)) != 0; }
+// The three-level scheme of Appendix B adds a quadrupled grid (period 4P)
+// per level with two finer levels.
+bool is_modified3(unsigned flags, int L) { return (flags & NMC_MODIFIED3) != 0 && L >= 3; }
+// Which method a request uses (requests of one group share every launch).
+int method_of(unsigned flags) { return (flags & NMC_MODIFIED3) ? 2 : (flags & NMC_MODIFIED) ? 1 : 0; }
+// Largest period a solve with these flags needs.
+int max_period(int N, int L, unsigned flags) {
+  const int P = period_of(N);
+  return is_modified3(flags, L) ? 4 * P : is_modified(flags) ? 2 * P : P;
+}
 
 // Workspace layout of one request (offsets from its base): per level l the
 // full grid's A and B; per level l < L-1 the second grid (hole grid,
@@ -65,9 +75,9 @@ bool is_modified(unsigned flags) { return (flags & NMC_MODIFIED) != 0; }
 // the hole grids with full output.
 struct Layout {
   int N, L, P, NC;
-  bool boxes, mod;
+  bool boxes, mod, mod3;
   size_t r, c;
-  size_t a_full, b_full, a_sec, b_sec, rc_bytes, box_bytes;
+  size_t a_full, b_full, a_sec, b_sec, rc_bytes, box_bytes, a_q, b_q;
   size_t total;
   size_t A(int l) const { return (size_t)l * (a_full + b_full); }
   size_t B(int l) const { return A(l) + a_full; }
@@ -79,6 +89,9 @@ struct Layout {
   size_t Box(int l) const { return Rc(0) + (size_t)(L - 1) * rc_bytes + (size_t)l * box_bytes; }
   size_t Shi(int l) const { return Box(0) + (size_t)(L - 1) * box_bytes + (size_t)l * 2 * box_bytes; }
   size_t Slo(int l) const { return Shi(l) + box_bytes; }
+  // quadrupled grids of the three-level scheme, levels l < L-2
+  size_t Aq(int l) const { return Shi(0) + (size_t)(L - 1) * 2 * box_bytes + (size_t)l * (a_q + b_q); }
+  size_t Bq(int l) const { return Aq(l) + a_q; }
 };
 
 Layout make_layout(int N, int L, nmc_precision p, unsigned flags) {
@@ -88,6 +101,7 @@ Layout make_layout(int N, int L, nmc_precision p, unsigned flags) {
   lo.P = period_of(N);
   lo.NC = N / 2 + 2;
   lo.mod = is_modified(flags);
+  lo.mod3 = is_modified3(flags, L);
   lo.boxes = use_boxes(N) && !lo.mod;
   lo.r = real_size(p);
   lo.c = 2 * lo.r;
@@ -106,7 +120,14 @@ Layout make_layout(int N, int L, nmc_precision p, unsigned flags) {
   }
   lo.rc_bytes = align_up((size_t)nmc::pyramid_slab(N, L) * lo.r);
   lo.box_bytes = align_up(NC * NC * NC * lo.r);
-  lo.total = lo.Shi(0) + (size_t)(L - 1) * 2 * lo.box_bytes;
+  if (lo.mod3) {
+    // quadrupled grid, period 4P: N x N rows of the x half spectrum (2P
+    // values), 4N z rows after the z pass
+    const size_t PQ = 4 * P;
+    lo.a_q = align_up((size_t)N * N * (PQ / 2) * lo.c);
+    lo.b_q = align_up(4 * (size_t)N * PQ * (PQ / 2) * lo.c);
+  }
+  lo.total = lo.Aq(0) + (lo.mod3 ? (size_t)(L - 2) * (lo.a_q + lo.b_q) : 0);
   lo.total = std::max(lo.total, kAlign);
   return lo;
 }
@@ -374,8 +395,10 @@ int validate(nmc_ctx* ctx, const Req& r, int refine) {
   if (!r.rho || !r.phi) return fail(ctx, NMC_EINVAL, "rho and phi must be non-null device pointers");
   if (r.N < kMinN || r.N % 4 != 0) return fail(ctx, NMC_EINVAL, "N must be a multiple of 4, >= 4");
   if (!period_of(r.N)) return fail(ctx, NMC_EUNSUPPORTED, "N above 256 (padded period above 512)");
-  if (is_modified(r.flags) && 2 * period_of(r.N) > kMaxP)
-    return fail(ctx, NMC_EUNSUPPORTED, "NMC_MODIFIED: N above 128 (doubled-grid period above 512)");
+  if (max_period(r.N, r.L, r.flags) > kMaxP)
+    return fail(ctx, NMC_EUNSUPPORTED, is_modified3(r.flags, r.L)
+                                           ? "NMC_MODIFIED3: N above 64 (quadrupled-grid period above 512)"
+                                           : "NMC_MODIFIED: N above 128 (doubled-grid period above 512)");
   if (r.L < 1 || r.L > kMaxL) return fail(ctx, NMC_EINVAL, "L must be in [1, 16]");
   if (!(r.h0 > 0) || !std::isfinite(r.h0)) return fail(ctx, NMC_EINVAL, "h0 must be positive and finite");
   if (!std::isfinite(r.G)) return fail(ctx, NMC_EINVAL, "G must be finite");
@@ -425,10 +448,11 @@ struct ProfScope {
 struct PassBytes {
   double r, c, N, nin, nout, P, H, NS;
   int kind;
-  PassBytes(int N_, int P_, size_t rsz, int kind_)
+  // S: scale of the launch (kinds 3, 5: S N output rows at period P = S times the level's)
+  PassBytes(int N_, int P_, size_t rsz, int kind_, int S = 1)
       : r((double)rsz), c(2.0 * rsz), N(N_), nin(kind_ == 1 ? N_ / 2 + 2 : N_),
-        nout(kind_ == 0 || kind_ == 4 ? N_ : kind_ == 3 ? 2 * N_ : N_ / 2 + 2), P(P_), H(P_ / 2 + 1),
-        NS(N_ / 2 + 2), kind(kind_) {}
+        nout(kind_ == 0 || kind_ == 4 ? N_ : (kind_ == 3 || kind_ == 5) ? S * N_ : N_ / 2 + 2), P(P_),
+        H(P_ / 2 + 1), NS(N_ / 2 + 2), kind(kind_) {}
   double half() const { return P / 2; }
   double x() const {
     const double in = kind == 1 ? std::pow(N / 2, 3) : N * N * N;
@@ -437,7 +461,7 @@ struct PassBytes {
   double y() const { return nin * nin * half() * c + nin * P * half() * c; }
   double z() const { return (nin + nout) * P * half() * c + H * H * H * r; }
   double iy() const {
-    if (kind == 3)  // folded: all 2N z rows read, N x N rows written
+    if (kind == 3 || kind == 5)  // folded: all S N z rows read, N x N rows written
       return nout * P * half() * c + N * N * half() * c;
     return nout * P * half() * c + nout * nout * half() * c;
   }
@@ -486,6 +510,10 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   };
   const nmc::Tables<R> tb = tables(P);
   const nmc::Tables<R> tbd = mod ? tables(PD) : tb;
+  const int PQ = 4 * P;  // period of the quadrupled grids (three-level scheme)
+  const bool any_mod3 = mod && (reqs[0].flags & NMC_MODIFIED3) && PQ <= kMaxP;
+  const nmc::Tables<R> tbq = any_mod3 ? tables(PQ) : tb;
+  std::vector<FieldDesc> quads;  // quadrupled grids
   const size_t lvl = (size_t)N * N * N;
   std::vector<FieldDesc> fulls, secs;  // full grids; hole grids or child-region boxes
   std::vector<int> full_level;
@@ -563,14 +591,35 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
       f.comp = comp ? 1 : 0;
       fulls.push_back(f);
       full_level.push_back(l);
+      // three-level scheme (Appendix B): a level with two finer levels takes
+      // level l+1's hole density on the doubled grid and level l+2's density
+      // on a quadrupled grid
+      const bool triple = lo.mod3 && l < q.L - 2;
+      if (triple) {
+        const double hq = std::ldexp(q.h0, -(l + 2));
+        const double PQ3 = (double)PQ * PQ * PQ;
+        FieldDesc c{};
+        c.rho = rho + (size_t)(l + 2) * lvl;
+        c.rc = (restrict_on && l + 2 < q.L - 1) ? (const void*)(base + lo.Rc(l + 2)) : nullptr;
+        c.rslab = rslab;
+        c.rdepth = pyramid ? q.L - 3 - l : 1;
+        c.A = base + lo.Aq(l);
+        c.B = base + lo.Bq(l);
+        c.out = phi + (size_t)l * lvl;  // added after the doubled grid's pass
+        c.scale = -q.G * hq * hq / PQ3;
+        c.kind = 3;
+        c.comp = f.comp;
+        quads.push_back(c);
+      }
       if (finer && mod) {
         // doubled grid of the pair (l, l+1): level l+1's density (its own
-        // child region restricted) on the grid of level l+1's spacing
+        // child region restricted, or zeroed in the three-level scheme) on
+        // the grid of level l+1's spacing
         const double hf = std::ldexp(q.h0, -(l + 1));
         const double PD3 = (double)PD * PD * PD;
         FieldDesc c{};
         c.rho = rho + (size_t)(l + 1) * lvl;
-        c.rc = (restrict_on && l + 1 < q.L - 1) ? (const void*)(base + lo.Rc(l + 1)) : nullptr;
+        c.rc = (restrict_on && l + 1 < q.L - 1 && !triple) ? (const void*)(base + lo.Rc(l + 1)) : nullptr;
         c.rslab = rslab;
         c.rdepth = pyramid ? q.L - 2 - l : 1;
         c.A = base + lo.As(l);
@@ -579,7 +628,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
         c.S = carry_in;
         c.Slo = carry_lo;
         c.scale = -q.G * hf * hf / PD3;
-        c.kind = 3;
+        c.kind = triple ? 5 : 3;
         c.comp = f.comp;
         secs.push_back(c);
       } else if (finer) {
@@ -606,7 +655,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
       double bytes = 0;
       for (int k = 0; k < cnt; ++k) {
         ft.f[k] = fs[a + k];
-        const PassBytes pb(N, Pc, sizeof(R), ft.f[k].kind);
+        const PassBytes pb(N, Pc, sizeof(R), ft.f[k].kind, Pc / P);
         switch (pass) {
           case NMC_PASS_X: bytes += pb.x(); break;
           case NMC_PASS_Y: bytes += pb.y(); break;
@@ -619,7 +668,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
           default: bytes += pb.ix(ft.f[k].S != nullptr, ft.f[k].Sout != nullptr); break;
         }
       }
-      PassGeom g{N, Pc, n, cnt};
+      PassGeom g{N, Pc, n, cnt, Pc / P};
       ProfScope ps(ctx, st, pass, bytes);
       hipError_t e = launch(ft, g, tbc, st);
       if (e != hipSuccess) return e;
@@ -698,13 +747,18 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     if ((rc = restrict_cascade(s))) return rc;
     std::vector<FieldDesc> holes, finest;
     for (const auto& f : fulls) (f.kind == 4 ? holes : finest).push_back(f);
-    auto doubled_to_iy = [&](hipStream_t st) -> int {
-      if (secs.empty()) return NMC_OK;
-      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_fwd_x<R>, NMC_PASS_X, st, PD, tbd));
-      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_fwd_y<R>, NMC_PASS_Y, st, PD, tbd));
-      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_z<R>, NMC_PASS_Z, st, PD, tbd));
-      NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_inv_y_fold<R>, NMC_PASS_IY, st, PD, tbd));
+    auto scaled_to_iy = [&](const std::vector<FieldDesc>& fs, int Pc, const nmc::Tables<R>& tbc,
+                            hipStream_t st) -> int {
+      if (fs.empty()) return NMC_OK;
+      NMC_HIP(ctx, for_chunks_p(fs, N, nmc::launch_fwd_x<R>, NMC_PASS_X, st, Pc, tbc));
+      NMC_HIP(ctx, for_chunks_p(fs, N, nmc::launch_fwd_y<R>, NMC_PASS_Y, st, Pc, tbc));
+      NMC_HIP(ctx, for_chunks_p(fs, N, nmc::launch_z<R>, NMC_PASS_Z, st, Pc, tbc));
+      NMC_HIP(ctx, for_chunks_p(fs, N, nmc::launch_inv_y_fold<R>, NMC_PASS_IY, st, Pc, tbc));
       return NMC_OK;
+    };
+    auto doubled_to_iy = [&](hipStream_t st) -> int {
+      int r = scaled_to_iy(secs, PD, tbd, st);
+      return r ? r : scaled_to_iy(quads, PQ, tbq, st);
     };
     const bool fork = aux && aux != s && !secs.empty() && !ctx->profiling && !one_stream;
     if (fork) {
@@ -732,6 +786,8 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     }
     if (!secs.empty())
       NMC_HIP(ctx, for_chunks_p(secs, N, nmc::launch_inv_x_fold<R>, NMC_PASS_IX_DOUBLED, s, PD, tbd));
+    if (!quads.empty())
+      NMC_HIP(ctx, for_chunks_p(quads, N, nmc::launch_inv_x_fold<R>, NMC_PASS_IX_DOUBLED, s, PQ, tbq));
     return NMC_OK;
   }
   if (!boxes) {
@@ -785,6 +841,7 @@ int prepare(nmc_ctx* ctx, int N, unsigned flags, hipStream_t s) {
   const int P = period_of(N);
   int rc = ensure_green(ctx, P, s);
   if (rc == NMC_OK && is_modified(flags)) rc = ensure_green(ctx, 2 * P, s);
+  if (rc == NMC_OK && (flags & NMC_MODIFIED3) && 4 * P <= kMaxP) rc = ensure_green(ctx, 4 * P, s);
   return rc;
 }
 
@@ -804,9 +861,9 @@ int launch_group(nmc_ctx* ctx, const Req* reqs, int count, hipStream_t s, Lease*
 
 int solve_many(nmc_ctx* ctx, const Req* reqs, int count, hipStream_t s, Lease* lease) {
   // group by (N, precision, method), preserving order inside a group
-  std::map<std::tuple<int, int, bool>, std::vector<Req>> groups;
+  std::map<std::tuple<int, int, int>, std::vector<Req>> groups;
   for (int i = 0; i < count; ++i)
-    groups[std::make_tuple(reqs[i].N, (int)reqs[i].p, is_modified(reqs[i].flags))].push_back(reqs[i]);
+    groups[std::make_tuple(reqs[i].N, (int)reqs[i].p, method_of(reqs[i].flags))].push_back(reqs[i]);
   for (auto& kv : groups) {
     auto& v = kv.second;
     for (size_t a = 0; a < v.size(); a += kMaxBatchRequests) {
@@ -917,10 +974,10 @@ int serve_tick(nmc_ctx* ctx, int* launched) {
   // batch holds at most a quarter of the budget so that several batches are
   // in flight and overlap on the device.
   const size_t max_batch_bytes = ctx->budget ? std::max<size_t>(ctx->budget / 4, 1) : SIZE_MAX;
-  std::map<std::tuple<int, int, bool>, std::vector<uint64_t>> groups;
+  std::map<std::tuple<int, int, int>, std::vector<uint64_t>> groups;
   for (uint64_t t : admitted) {
     const Req& r = ctx->items[t].r;
-    groups[std::make_tuple(r.N, (int)r.p, is_modified(r.flags))].push_back(t);
+    groups[std::make_tuple(r.N, (int)r.p, method_of(r.flags))].push_back(t);
   }
   std::vector<std::vector<uint64_t>> batches;
   for (auto& kv : groups) {
@@ -996,7 +1053,7 @@ int nmc_footprint_bytes_flags(int N, int L, nmc_precision p, unsigned flags, siz
   if (!bytes || N < kMinN || N % 4 != 0 || L < 1 || L > kMaxL || (p != NMC_F64 && p != NMC_F32))
     return NMC_EINVAL;
   if (!period_of(N)) return NMC_EUNSUPPORTED;
-  if (is_modified(flags) && 2 * period_of(N) > kMaxP) return NMC_EUNSUPPORTED;
+  if (max_period(N, L, flags) > kMaxP) return NMC_EUNSUPPORTED;
   *bytes = make_layout(N, L, p, flags).total;
   return NMC_OK;
 }

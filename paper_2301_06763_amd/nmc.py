@@ -24,6 +24,7 @@ NMC_NO_GRAPH = 1 << 3
 NMC_ONE_STREAM = 1 << 4
 NMC_NO_FUSED_PLANES = 1 << 5
 NMC_MODIFIED = 1 << 6  # the dipole-preserving method of Sect. 7 / Appendix B
+NMC_MODIFIED3 = 1 << 7  # ... with Appendix B's three-level scheme
 
 _CODES = {NMC_EINVAL: "EINVAL", NMC_ENOMEM: "ENOMEM", NMC_EDEVICE: "EDEVICE",
           NMC_EUNSUPPORTED: "EUNSUPPORTED", NMC_EAGAIN: "EAGAIN"}

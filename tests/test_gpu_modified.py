@@ -188,3 +188,114 @@ def test_modified_batch_and_graph_equal_alone(ctx, MOD, dtype):
         ctx.solve(r, h, G, f, out=out)
         torch.cuda.synchronize()
         assert torch.equal(out, alone[0])
+
+
+# --- three-level dipole scheme (Appendix B), NMC_MODIFIED3 --------------------
+
+@pytest.fixture(scope="module")
+def MOD3():
+    from paper_2301_06763_amd import nmc
+    return nmc.NMC_MODIFIED3
+
+
+# N = 12, 20: periods above 2N (quadrupled period 4P above 8N); L - 2
+# quadrupled grids per request; pyramid or cascaded restriction as for the
+# pairwise tests; L = 6 at N = 16 takes two carry launches.
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("N,L", [(4, 3), (8, 3), (8, 4), (12, 3), (16, 4), (16, 6), (20, 3), (32, 4)])
+def test_modified3_random_levels(ctx, MOD3, dtype, N, L):
+    w = inputs.random_levels(N, L, seed=800 + N + L)
+    rho = w.rho.numpy()
+    ref = oracle.solve_modified(rho, w.h0, G=0.8, scheme="triples")
+    got = run(ctx, rho, w.h0, MOD3, dtype=dtype, G=0.8)
+    assert np.max(rel_err(got, ref)) < tol_of(dtype), (N, L)
+
+
+def test_modified3_two_levels_is_the_pairwise_scheme(ctx, MOD, MOD3):
+    w = inputs.random_levels(16, 2, seed=13)
+    rho = w.rho.numpy()
+    assert np.array_equal(run(ctx, rho, w.h0, MOD3), run(ctx, rho, w.h0, MOD))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_modified3_no_restrict_and_fused_planes(ctx, MOD3, dtype):
+    from paper_2301_06763_amd import nmc
+    w = inputs.random_levels(16, 4, seed=14)
+    rho = w.rho.numpy()
+    ref = oracle.solve_modified(rho, w.h0, restrict=False, scheme="triples")
+    for extra in (nmc.NMC_NO_RESTRICT, nmc.NMC_NO_RESTRICT | nmc.NMC_NO_FUSED_PLANES):
+        got = run(ctx, rho, w.h0, MOD3 | extra, dtype=dtype)
+        assert np.max(rel_err(got, ref)) < tol_of(dtype)
+
+
+@pytest.fixture(scope="module")
+def ellipsoid64_mod3():
+    w = inputs.ellipsoid64()
+    rho = w.rho.numpy()
+    return w, rho, oracle.solve_modified(rho, w.h0, scheme="triples")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_modified3_ellipsoid64_largest_n(ctx, MOD3, ellipsoid64_mod3, dtype):
+    """N = 64, the largest N of the three-level scheme (quadrupled period 512)."""
+    w, rho, ref = ellipsoid64_mod3
+    got = run(ctx, rho, w.h0, MOD3, dtype=dtype)
+    assert np.max(rel_err(got, ref)) < tol_of(dtype)
+
+
+def test_modified3_rejects_n_above_64(ctx, MOD3):
+    from paper_2301_06763_amd import nmc
+    rho = torch.zeros(3, 68, 68, 68, device="cuda", dtype=torch.float32)
+    with pytest.raises(nmc.NmcError) as e:
+        ctx.solve(rho, 1.0, 1.0, MOD3)
+    assert e.value.code == nmc.NMC_EUNSUPPORTED
+    ok = torch.zeros(2, 128, 128, 128, device="cuda", dtype=torch.float32)  # two levels: no quadrupled grid
+    ctx.solve(ok, 1.0, 1.0, MOD3)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_modified3_close_binary_fig18(ctx, MOD, MOD3, n):
+    """Fig. 18, right column, on the GPU path: the pairwise and three-level
+    schemes agree on the two finer grids and differ on the coarsest by at
+    most 1.5 % (N = 32) / 0.7 % (N = 64) on the plane through the binary
+    (up to 15 % slack for the unstated placement)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "modified_vs_original.json")) as fh:
+        bound = json.load(fh)["close_binary_3_levels"][f"N{n}_max_percent_below"]
+    rho = np.zeros((3, n, n, n))
+    rho[2, n // 2, n // 2, n // 2 - 1] = 1.0
+    rho[2, n // 2, n // 2, n // 2] = 2.0
+    h0 = 4.5 / n
+    p2 = run(ctx, rho, h0, MOD)
+    p3 = run(ctx, rho, h0, MOD3)
+    assert np.max(np.abs(p2[1:] - p3[1:]) / np.abs(p3[1:])) < 1e-12
+    c = slice(n // 4, 3 * n // 4)
+    m = np.ones((n, n, n), bool)
+    m[c, c, c] = False
+    e = np.where(m, np.abs(p2[0] - p3[0]) / np.abs(p3[0]), 0.0)
+    plane = 100 * e[:, n // 2, :].max()
+    assert 0.6 * bound < plane < 1.15 * bound, plane
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_modified3_batch_and_graph_equal_alone(ctx, MOD, MOD3, dtype):
+    """Requests of the three methods in one batch (three groups), and a
+    captured-graph replay of a three-level solve, equal their direct solves."""
+    from paper_2301_06763_amd import nmc
+    items = []
+    for i, (N, L, f) in enumerate(((16, 4, MOD3), (16, 4, 0), (16, 3, MOD), (32, 3, MOD3), (16, 5, MOD3))):
+        w = inputs.random_levels(N, L, seed=900 + i)
+        items.append((w.rho.to("cuda", dtype), w.h0, 1.0, f))
+    alone = [ctx.solve(r, h, G, f | nmc.NMC_NO_GRAPH).clone() for r, h, G, f in items]
+    batch = ctx.solve_batch(items)
+    torch.cuda.synchronize()
+    for a, b in zip(alone, batch):
+        assert torch.equal(a, b)
+    r, h, G, f = items[0]
+    out = torch.empty_like(r)
+    for _ in range(3):
+        ctx.solve(r, h, G, f, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, alone[0])
