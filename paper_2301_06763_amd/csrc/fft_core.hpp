@@ -204,7 +204,12 @@ __device__ __forceinline__ void fft_stages(cplx<R>* v, int t, const LdsView<R>& 
 // one LDS exchange fewer and fewer twiddle products per point, for more
 // registers per thread.  Which passes take the wide plan was measured pass
 // by pass (kernels.hip); NMC_WIDE_PASSES is a bit mask over PassKind.
-enum PassKind { kPassX = 0, kPassY = 1, kPassZ = 2, kPassIY = 3, kPassIX = 4, kPassOther = 5 };
+enum PassKind {
+  kPassX = 0, kPassY = 1, kPassZ = 2, kPassIY = 3, kPassIX = 4, kPassOther = 5,
+  // z pass of the scaled grids (modified method), and its inverse transform
+  // after the spectrum is folded by 2 or 4 (E / 2 or E / 4 points per thread)
+  kPassZScaled = 6, kPassZFold2 = 7, kPassZFold4 = 8
+};
 #ifndef NMC_WIDE_PASSES
 #define NMC_WIDE_PASSES ((1 << kPassY) | (1 << kPassZ))
 #endif
@@ -218,6 +223,18 @@ template <> struct NarrowPlan<128> { static constexpr int E = 8; template <class
 template <> struct NarrowPlan<256> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 4>(); } };
 template <> struct NarrowPlan<512> { static constexpr int E = 8; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
 
+// Plans with 4 and 2 points per thread (the inverse after a fold).
+template <int P> struct Plan4;
+template <> struct Plan4<8> { static constexpr int E = 4; template <class F> __device__ static void run(F f) { f.template go<4, 2>(); } };
+template <> struct Plan4<16> { static constexpr int E = 4; template <class F> __device__ static void run(F f) { f.template go<4, 4>(); } };
+template <> struct Plan4<32> { static constexpr int E = 4; template <class F> __device__ static void run(F f) { f.template go<4, 4, 2>(); } };
+template <> struct Plan4<64> { static constexpr int E = 4; template <class F> __device__ static void run(F f) { f.template go<4, 4, 4>(); } };
+template <> struct Plan4<128> { static constexpr int E = 4; template <class F> __device__ static void run(F f) { f.template go<4, 4, 4, 2>(); } };
+template <> struct Plan4<256> { static constexpr int E = 4; template <class F> __device__ static void run(F f) { f.template go<4, 4, 4, 4>(); } };
+template <int P> struct Plan2;
+template <> struct Plan2<8> { static constexpr int E = 2; template <class F> __device__ static void run(F f) { f.template go<2, 2, 2>(); } };
+template <> struct Plan2<16> { static constexpr int E = 2; template <class F> __device__ static void run(F f) { f.template go<2, 2, 2, 2>(); } };
+
 template <int P> struct WidePlan;
 template <> struct WidePlan<128> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8>(); } };
 template <> struct WidePlan<256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
@@ -228,13 +245,34 @@ template <> struct WidePlan<512> { static constexpr int E = 16; template <class 
 #endif
 // FP64 wide plans only up to P = 256: they need ~200 VGPRs (two waves per
 // SIMD), which the larger P = 512 tiles measured slower with.
+// The scaled grids' z pass takes the wide plans from P = 128 in both
+// precisions, so that the fold leaves at least 4 points per thread there.
 template <class R, int P, int K>
 constexpr bool wide_plan() {
-  if constexpr (sizeof(R) == 4) return P >= 128 && ((NMC_WIDE_PASSES >> K) & 1) != 0;
+  if constexpr (K == kPassZScaled) return P >= 128;
+  else if constexpr (sizeof(R) == 4) return P >= 128 && ((NMC_WIDE_PASSES >> K) & 1) != 0;
   else return P >= 128 && P <= 256 && ((NMC_WIDE_PASSES_F64 >> K) & 1) != 0;
 }
+template <int P, int E> struct PlanE;
+template <int P> struct PlanE<P, 16> : WidePlan<P> {};
+template <int P> struct PlanE<P, 8> : NarrowPlan<P> {};
+template <int P> struct PlanE<P, 4> : Plan4<P> {};
+template <int P> struct PlanE<P, 2> : Plan2<P> {};
+template <class R, int P, int K>
+struct PlanSel {
+  using type = std::conditional_t<wide_plan<R, P, K>(), WidePlan<P>, NarrowPlan<P>>;
+};
+// after a fold by S the same threads hold E / S points of a line of P = P' / S
+template <class R, int P>
+struct PlanSel<R, P, kPassZFold2> {
+  using type = PlanE<P, PlanSel<R, 2 * P, kPassZScaled>::type::E / 2>;
+};
+template <class R, int P>
+struct PlanSel<R, P, kPassZFold4> {
+  using type = PlanE<P, PlanSel<R, 4 * P, kPassZScaled>::type::E / 4>;
+};
 template <class R, int P, int K = kPassOther>
-struct Plan : std::conditional_t<wide_plan<R, P, K>(), WidePlan<P>, NarrowPlan<P>> {};
+struct Plan : PlanSel<R, P, K>::type {};
 
 template <class R, int P, int DIR, bool PIN, bool POUT, int K>
 struct FftRun {

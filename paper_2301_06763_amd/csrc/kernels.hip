@@ -140,11 +140,12 @@ struct GridGeo {
 };
 // DBL: a launch of scaled grids (kinds 3 and 5, scale factor S = 2 or 4:
 // S N cells of the finer level's spacing spanning level l, its N input rows
-// centred at (S-1) N/2, S N output rows); kept out of the other launches'
-// code, where the extra case measurably costs registers.
+// centred at (S-1) N/2, the N rows of level l left by the z pass's fold);
+// kept out of the other launches' code, where the extra case measurably
+// costs registers.
 template <bool DBL = false>
 __device__ __forceinline__ GridGeo grid_geo(int kind, int N, int S = 1) {
-  if (DBL) return GridGeo{N, 0, S * N, (S - 1) * N / 2};
+  if (DBL) return GridGeo{N, 0, N, (S - 1) * N / 2};
   if (kind == 0 || kind == 4) return GridGeo{N, 0, N, 0};
   if (kind == 1) return GridGeo{N / 2 + 2, 0, N / 2 + 2, 0};
   return GridGeo{N, N / 4 - 1, N / 2 + 2, 0};
@@ -338,6 +339,41 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   for (int q = 0; q < E; ++q) B[(size_t)(t + TL * q) * (P / 2)] = v[q];
 }
 
+// ---------------------------------------------------------------------------
+// Reduction of the scaled grids (kinds 3 and 5) of the modified method
+// (Sect. 7, Appendix B) to level l, taken in the spectrum.  A doubled (S = 2) or quadrupled (S = 4) grid has S N cells per
+// axis of the finer level's spacing and spans level l: level cell j covers
+// the scaled cells S j .. S j + S - 1 per axis, and its value is the mean of
+// the S^3.  For a line of values x_n of period 2Q with spectrum X
+// (x_n = sum_K X[K] exp(2 pi i K n / 2Q)), the pair means
+// y_j = (x_2j + x_2j+1) / 2 have the period-Q spectrum
+//   Y[k] = ((X[k] + X[k+Q]) + w^k (X[k] - X[k+Q])) / 2,  w = exp(2 pi i / 2Q),
+// and the means of four are the pair means of the pair means.  So each
+// inverse transform (z, y, x) runs at the level's period P on the spectrum
+// folded log2 S times and yields level l's cells directly.
+// fold_pair: Y[k] from X[k] = a, X[k+Q] = b and wc = exp(-2 pi i k / 2Q)
+// (the table entry; w^k is its conjugate), times the extra factor s.
+template <class R>
+__device__ __forceinline__ cplx<R> fold_pair(cplx<R> a, cplx<R> b, cplx<R> wc, R s) {
+  const cplx<R> d{a.x - b.x, a.y - b.y};
+  const cplx<R> wd{wc.x * d.x + wc.y * d.y, wc.x * d.y - wc.y * d.x};  // conj(wc) d
+  return cplx<R>{s * (a.x + b.x + wd.x), s * (a.y + b.y + wd.y)};
+}
+
+// The period-P spectrum value Y[k] of the S-means from the period-S P
+// spectrum point values xs(m), m = k + P s (tw: the period-S P table).
+template <class R, int P, int S, class X>
+__device__ __forceinline__ cplx<R> fold_to_p(X xs, int k, const cplx<R>* __restrict__ tw) {
+  if constexpr (S == 2) {
+    return fold_pair<R>(xs(k), xs(k + P), tw[k], (R)0.5);
+  } else {
+    static_assert(S == 4, "scale 2 or 4");
+    const cplx<R> lo = fold_pair<R>(xs(k), xs(k + 2 * P), tw[k], (R)0.5);
+    const cplx<R> hi = fold_pair<R>(xs(k + P), xs(k + 3 * P), tw[k + P], (R)0.5);
+    return fold_pair<R>(lo, hi, tw[2 * k], (R)0.5);
+  }
+}
+
 // Work unit (row pair p, tile) and grid f of z-pass block b.  Consecutive
 // blocks are dispatched to the 8 XCDs in turn, each with its own L2; the
 // remap gives every XCD all grids of a unit back to back (the unit's spectrum
@@ -361,12 +397,19 @@ __device__ __forceinline__ void z_unit(int b, int U, int nf, int TP, int& u, int
 // spectrum times the level scale, inverse along z, keep rows z < n.
 // A workgroup owns the rows ky and -ky (mod P) of W adjacent kx columns: the
 // packed DC/Nyquist column needs the value at (-ky, -kz) to separate the two
-// real planes before they are multiplied by different spectra.  DBL: a
-// launch of doubled grids (kind 3), whose input rows start at ilo.
-template <class R, int P, bool FULLN, bool DBL = false>
-__global__ void __launch_bounds__((2 * Cfg<R, P, kPassZ>::WZ * Cfg<R, P, kPassZ>::TL), (Cfg<R, P, kPassZ>::MINW))
+// real planes before they are multiplied by different spectra.  SC > 1: a
+// launch of scaled grids (kinds 3 and 5) of scale SC, whose input rows start
+// at ilo; after the multiply their spectrum is folded SC times shorter and
+// inverted at P / SC, which leaves the N rows of level l (the z means).
+template <class R, int P, bool FULLN, int SC = 1>
+__global__ void __launch_bounds__((2 * Cfg<R, P, SC == 1 ? kPassZ : kPassZScaled>::WZ *
+                                   Cfg<R, P, SC == 1 ? kPassZ : kPassZScaled>::TL),
+                                  (Cfg<R, P, SC == 1 ? kPassZ : kPassZScaled>::MINW))
 k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
-  using C = Cfg<R, P, kPassZ>;
+  constexpr bool DBL = SC > 1;
+  constexpr int KZ = DBL ? kPassZScaled : kPassZ;
+  using C = Cfg<R, P, KZ>;
+  static_assert(C::WZ == Cfg<R, P, kPassZ>::WZ, "the spectrum layout assumes the z pass's tile width");
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WZ, NT = (P / 2) / W, H = P / 2 + 1;
   __shared__ R sre[2 * W * P], sim[2 * W * P];
@@ -420,7 +463,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   if constexpr (!late) fetch_spectrum();
   LdsView<R> lds{sre, sim, 2 * W, 1, w + W * side};
   tws.put(stw);
-  fft_line<R, P, -1, true, false, kPassZ>(v, t, lds, stw);
+  fft_line<R, P, -1, true, false, KZ>(v, t, lds, stw);
   if constexpr (late) fetch_spectrum();
 
   const R sc = (R)F.scale;
@@ -460,11 +503,39 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
       v[q] = T{a * v[q].x + b * cm.x, a * v[q].y + b * cm.y};
     }
   }
-  fft_line<R, P, +1, false, true, kPassZ>(v, t, lds, stw);
+  if constexpr (!DBL) {
+    fft_line<R, P, +1, false, true, kPassZ>(v, t, lds, stw);
 #pragma unroll
-  for (int q = 0; q < E / 2; ++q) {
-    const int zz = t + TL * q;
-    if (full || (zz >= gg.olo && zz < gg.olo + gg.nout)) B[zz * ZS] = v[q];
+    for (int q = 0; q < E / 2; ++q) {
+      const int zz = t + TL * q;
+      if (full || (zz >= gg.olo && zz < gg.olo + gg.nout)) B[zz * ZS] = v[q];
+    }
+  } else {
+    // fold: point kz + (P/SC) s of this thread is its slot q + s E/SC
+    constexpr int EF = E / SC, PF = P / SC, KF = SC == 2 ? kPassZFold2 : kPassZFold4;
+    static_assert(Plan<R, PF, KF>::E == EF, "fold plan");
+    __shared__ cplx<R> stw2[PF];  // exp(-2 pi i j / PF): every SC-th twiddle
+    for (int j = threadIdx.x; j < PF; j += blockDim.x) stw2[j] = stw[SC * j];
+    T u[EF];
+#pragma unroll
+    for (int q = 0; q < EF; ++q) {  // fold_to_p with the points in registers
+      const int kz = t + TL * q;
+      if constexpr (SC == 2) {
+        u[q] = fold_pair<R>(v[q], v[q + EF], stw[kz], (R)0.5);
+      } else {
+        const T lo = fold_pair<R>(v[q], v[q + 2 * EF], stw[kz], (R)0.5);
+        const T hi = fold_pair<R>(v[q + EF], v[q + 3 * EF], stw[kz + PF], (R)0.5);
+        u[q] = fold_pair<R>(lo, hi, stw[2 * kz], (R)0.5);
+      }
+    }
+    // the first stage's LDS writes follow a barrier, after the stw2 writes
+    fft_line<R, PF, +1, false, true, KF>(u, t, lds, stw2);
+    const int Nl = g.N;
+#pragma unroll
+    for (int q = 0; q < EF / 2; ++q) {
+      const int zz = t + TL * q;
+      if (zz < Nl) B[(size_t)zz * ZS] = u[q];
+    }
   }
 }
 
@@ -694,47 +765,9 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Inverse passes of the scaled grids (kinds 3 and 5) of the modified method
-// (Sect. 7, Appendix B), with the reduction to level l taken in the
-// spectrum.  A doubled (S = 2) or quadrupled (S = 4) grid has S N cells per
-// axis of the finer level's spacing and spans level l: level cell j covers
-// the scaled cells S j .. S j + S - 1 per axis, and its value is the mean of
-// the S^3.  For a line of values x_n of period 2Q with spectrum X
-// (x_n = sum_K X[K] exp(2 pi i K n / 2Q)), the pair means
-// y_j = (x_2j + x_2j+1) / 2 have the period-Q spectrum
-//   Y[k] = ((X[k] + X[k+Q]) + w^k (X[k] - X[k+Q])) / 2,  w = exp(2 pi i / 2Q),
-// and the means of four are the pair means of the pair means.  So each
-// inverse transform runs at the level's period P on the spectrum folded
-// log2 S times and yields level l's cells directly.  The z means are taken
-// by adding the z pass's rows S j .. S j + S - 1 (the y and x transforms
-// are linear).
-// fold_pair: Y[k] from X[k] = a, X[k+Q] = b and wc = exp(-2 pi i k / 2Q)
-// (the table entry; w^k is its conjugate), times the extra factor s.
-template <class R>
-__device__ __forceinline__ cplx<R> fold_pair(cplx<R> a, cplx<R> b, cplx<R> wc, R s) {
-  const cplx<R> d{a.x - b.x, a.y - b.y};
-  const cplx<R> wd{wc.x * d.x + wc.y * d.y, wc.x * d.y - wc.y * d.x};  // conj(wc) d
-  return cplx<R>{s * (a.x + b.x + wd.x), s * (a.y + b.y + wd.y)};
-}
-
-// The period-P spectrum value Y[k] of the S-means from the period-S P
-// spectrum point values xs(m), m = k + P s (tw: the period-S P table).
-template <class R, int P, int S, class X>
-__device__ __forceinline__ cplx<R> fold_to_p(X xs, int k, const cplx<R>* __restrict__ tw) {
-  if constexpr (S == 2) {
-    return fold_pair<R>(xs(k), xs(k + P), tw[k], (R)0.5);
-  } else {
-    static_assert(S == 4, "scale 2 or 4");
-    const cplx<R> lo = fold_pair<R>(xs(k), xs(k + 2 * P), tw[k], (R)0.5);
-    const cplx<R> hi = fold_pair<R>(xs(k + P), xs(k + 3 * P), tw[k + P], (R)0.5);
-    return fold_pair<R>(lo, hi, tw[2 * k], (R)0.5);
-  }
-}
-
-// I2 of the scaled grids: the y columns (level row z, kx) of the sum of the
-// z pass's rows S z .. S z + S - 1, folded to length P and inverted, rows
-// y < N kept: A[z][y][kx] (kx < S P / 2, the x half spectrum).
+// I2 of the scaled grids: the y columns (level row z, kx) of the z pass's
+// folded output, folded along y to length P and inverted, rows y < N kept:
+// A[z][y][kx] (kx < S P / 2, the x half spectrum).
 template <class R, int P, int S>
 __global__ void __launch_bounds__((Cfg<R, P, kPassIY>::WS * Cfg<R, P, kPassIY>::TL), (Cfg<R, P, kPassIY>::MINW))
 k_inv_y_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
@@ -750,20 +783,11 @@ k_inv_y_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
   if (z >= N) return;  // uniform: a smaller grid of a mixed launch
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int kx = (blockIdx.x % NT) * W + w;
-  const T* B0 = static_cast<const T*>(F.B) + (size_t)(S * z) * PS * HS + kx;  // row r, ky at + (r PS + ky) HS
-  // the z sum of the S rows at ky (all loads issued before the first fold)
-  auto zsum = [&](int ky) -> T {
-    T a{0, 0};
-#pragma unroll
-    for (int r = 0; r < S; ++r) {
-      const T b = B0[((size_t)r * PS + ky) * HS];
-      a = T{a.x + b.x, a.y + b.y};
-    }
-    return T{a.x * ((R)1 / S), a.y * ((R)1 / S)};
-  };
+  const T* B0 = static_cast<const T*>(F.B) + (size_t)z * PS * HS + kx;  // ky at + ky HS
   T v[E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) v[q] = fold_to_p<R, P, S>(zsum, t + TL * q, tb.tw);
+  for (int q = 0; q < E; ++q)
+    v[q] = fold_to_p<R, P, S>([&](int ky) { return B0[(size_t)ky * HS]; }, t + TL * q, tb.tw);
   LdsView<R> lds{sre, sim, W, 1, w};
   tws.put(stw);
   fft_line<R, P, +1, false, true, kPassIY>(v, t, lds, stw);
@@ -1492,11 +1516,16 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassZ>;
     dim3 grid(((PP / 2) / C::WZ) * (PP / 2) * g.nf);  // one dimension: see z_unit
-    if constexpr (PP >= 16) {
-      if (PP >= 4 * g.N) {  // doubled grids
-        launch(k_z<R, PP, false, true>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
-        return;
+    if (PP >= 4 * g.N) {  // scaled grids
+      using CS = Cfg<R, PP, kPassZScaled>;
+      const dim3 block(2 * CS::WZ * CS::TL);
+      if constexpr (PP >= 16) {
+        if (g.S == 2) launch(k_z<R, PP, false, 2>, grid, block, 0, s, ft, g, tb);
       }
+      if constexpr (PP >= 32) {
+        if (g.S == 4) launch(k_z<R, PP, false, 4>, grid, block, 0, s, ft, g, tb);
+      }
+      return;
     }
     if (g.N == PP / 2)
       launch(k_z<R, PP, true>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);

@@ -110,10 +110,11 @@ Layout make_layout(int N, int L, nmc_precision p, unsigned flags) {
   lo.b_full = align_up((size_t)N * P * (P / 2) * lo.c);
   if (lo.mod) {
     // doubled grid, period 2P: N x N rows of the x half spectrum (P values;
-    // x-pass output and folded y-inverse output), 2N z rows after the z pass
-    const size_t PD = 2 * P, ND = 2 * (size_t)N;
+    // x-pass output and folded y-inverse output), N z rows (y-pass output,
+    // folded z-pass output in place)
+    const size_t PD = 2 * P;
     lo.a_sec = align_up((size_t)N * N * (PD / 2) * lo.c);
-    lo.b_sec = align_up(ND * PD * (PD / 2) * lo.c);
+    lo.b_sec = align_up((size_t)N * PD * (PD / 2) * lo.c);
   } else {
     lo.a_sec = align_up(ns * ns * (P / 2) * lo.c);
     lo.b_sec = align_up(ns * P * (P / 2) * lo.c);
@@ -122,10 +123,10 @@ Layout make_layout(int N, int L, nmc_precision p, unsigned flags) {
   lo.box_bytes = align_up(NC * NC * NC * lo.r);
   if (lo.mod3) {
     // quadrupled grid, period 4P: N x N rows of the x half spectrum (2P
-    // values), 4N z rows after the z pass
+    // values), N z rows
     const size_t PQ = 4 * P;
     lo.a_q = align_up((size_t)N * N * (PQ / 2) * lo.c);
-    lo.b_q = align_up(4 * (size_t)N * PQ * (PQ / 2) * lo.c);
+    lo.b_q = align_up((size_t)N * PQ * (PQ / 2) * lo.c);
   }
   lo.total = lo.Aq(0) + (lo.mod3 ? (size_t)(L - 2) * (lo.a_q + lo.b_q) : 0);
   lo.total = std::max(lo.total, kAlign);
@@ -448,10 +449,10 @@ struct ProfScope {
 struct PassBytes {
   double r, c, N, nin, nout, P, H, NS;
   int kind;
-  // S: scale of the launch (kinds 3, 5: S N output rows at period P = S times the level's)
-  PassBytes(int N_, int P_, size_t rsz, int kind_, int S = 1)
+  // kinds 3, 5 (scaled grids, P the scaled period): N output rows after the fold
+  PassBytes(int N_, int P_, size_t rsz, int kind_)
       : r((double)rsz), c(2.0 * rsz), N(N_), nin(kind_ == 1 ? N_ / 2 + 2 : N_),
-        nout(kind_ == 0 || kind_ == 4 ? N_ : (kind_ == 3 || kind_ == 5) ? S * N_ : N_ / 2 + 2), P(P_),
+        nout(kind_ == 0 || kind_ == 4 || kind_ == 3 || kind_ == 5 ? N_ : N_ / 2 + 2), P(P_),
         H(P_ / 2 + 1), NS(N_ / 2 + 2), kind(kind_) {}
   double half() const { return P / 2; }
   double x() const {
@@ -461,8 +462,6 @@ struct PassBytes {
   double y() const { return nin * nin * half() * c + nin * P * half() * c; }
   double z() const { return (nin + nout) * P * half() * c + H * H * H * r; }
   double iy() const {
-    if (kind == 3 || kind == 5)  // folded: all S N z rows read, N x N rows written
-      return nout * P * half() * c + N * N * half() * c;
     return nout * P * half() * c + nout * nout * half() * c;
   }
   // fused plane passes: the x-transformed plane stays on chip
@@ -655,7 +654,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
       double bytes = 0;
       for (int k = 0; k < cnt; ++k) {
         ft.f[k] = fs[a + k];
-        const PassBytes pb(N, Pc, sizeof(R), ft.f[k].kind, Pc / P);
+        const PassBytes pb(N, Pc, sizeof(R), ft.f[k].kind);
         switch (pass) {
           case NMC_PASS_X: bytes += pb.x(); break;
           case NMC_PASS_Y: bytes += pb.y(); break;

@@ -76,11 +76,11 @@ def test_footprint_of_the_modified_method(lib):
     from paper_2301_06763_amd import nmc
     import torch
     # L full-size grids (L-1 hole grids and the finest level) plus L-1 doubled
-    # grids of period 2P: A = N^2 P (x half spectra) and B = 2N (2P) P
-    # (2N z rows after the z pass) complex values each
+    # grids of period 2P: A = N^2 P (x half spectra) and B = N (2P) P
+    # (N z rows) complex values each
     N, L, P = 32, 4, 64
     grid = (N * N * (P // 2) + N * P * (P // 2)) * 16
-    dbl = (N * N * P + 2 * N * (2 * P) * P) * 16
+    dbl = (N * N * P + N * (2 * P) * P) * 16
     fp = nmc.footprint_bytes(N, L, torch.float64, nmc.NMC_MODIFIED)
     assert L * grid + (L - 1) * dbl <= fp < (L * grid + (L - 1) * dbl) * 1.05
     assert fp > nmc.footprint_bytes(N, L, torch.float64)
@@ -90,6 +90,14 @@ def test_footprint_of_the_modified_method(lib):
     assert lib.nmc_footprint_bytes_flags(128, 3, 0, nmc.NMC_MODIFIED, ctypes.byref(out)) == nmc.NMC_OK
     assert lib.nmc_footprint_bytes_flags(132, 3, 0, nmc.NMC_MODIFIED, ctypes.byref(out)) == nmc.NMC_EUNSUPPORTED
     assert lib.nmc_footprint_bytes_flags(132, 3, 0, 0, ctypes.byref(out)) == nmc.NMC_OK
+    # the three-level scheme adds L-2 quadrupled grids of period 4P: A = N^2 (2P)
+    # and B = N (4P) (2P) complex values; 4P <= 512 needs N <= 64 from L = 3
+    qdp = (N * N * 2 * P + N * 4 * P * 2 * P) * 16
+    fp3 = nmc.footprint_bytes(N, L, torch.float64, nmc.NMC_MODIFIED3)
+    assert fp + (L - 2) * qdp <= fp3 < (fp + (L - 2) * qdp) * 1.05
+    assert lib.nmc_footprint_bytes_flags(64, 3, 0, nmc.NMC_MODIFIED3, ctypes.byref(out)) == nmc.NMC_OK
+    assert lib.nmc_footprint_bytes_flags(68, 3, 0, nmc.NMC_MODIFIED3, ctypes.byref(out)) == nmc.NMC_EUNSUPPORTED
+    assert lib.nmc_footprint_bytes_flags(128, 2, 0, nmc.NMC_MODIFIED3, ctypes.byref(out)) == nmc.NMC_OK
 
 
 def test_null_context_is_rejected(lib):
