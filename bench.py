@@ -128,11 +128,18 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2301_06763_amd", "csrc", f) for f in
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 of the kernel sources with comments and blank space removed
+    (an edit of a comment leaves the counters valid; any code change does
+    not)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            code = fh.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 

@@ -264,7 +264,7 @@ enum {
   /* fused plane passes (P <= 64, used in place of X+Y and I2+I1): */
   NMC_PASS_XY = 8, NMC_PASS_IYX_SECOND = 9, NMC_PASS_IYX_FULL = 10,
   NMC_PASS_ACCEL = 11,    /* nmc_acceleration */
-  NMC_PASS_IX_DOUBLED = 12, /* NMC_MODIFIED: last pass of the doubled grids (2^3 mean, sums) */
+  NMC_PASS_IX_DOUBLED = 12, /* NMC_MODIFIED(3): last pass of the doubled / quadrupled grids (means, sums) */
   NMC_NUM_PASSES = 13
 };
 

@@ -304,7 +304,7 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
 
 // ---------------------------------------------------------------------------
 // Y pass: C2C along y, inputs y >= n zero, all P outputs kept.  DBL: a
-// launch of doubled grids (kind 3), whose input rows start at ilo.
+// launch of scaled grids (kinds 3 and 5), whose input rows start at ilo.
 template <class R, int P, bool FULLN, bool DBL = false>
 __global__ void __launch_bounds__((Cfg<R, P, kPassY>::WS * Cfg<R, P, kPassY>::TL), (Cfg<R, P, kPassY>::MINW))
 k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
@@ -341,8 +341,9 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
 
 // ---------------------------------------------------------------------------
 // Reduction of the scaled grids (kinds 3 and 5) of the modified method
-// (Sect. 7, Appendix B) to level l, taken in the spectrum.  A doubled (S = 2) or quadrupled (S = 4) grid has S N cells per
-// axis of the finer level's spacing and spans level l: level cell j covers
+// (Sect. 7, Appendix B) to level l, taken in the spectrum.  A doubled
+// (S = 2) or quadrupled (S = 4) grid has S N cells per axis of the finer
+// level's spacing and spans level l: level cell j covers
 // the scaled cells S j .. S j + S - 1 per axis, and its value is the mean of
 // the S^3.  For a line of values x_n of period 2Q with spectrum X
 // (x_n = sum_K X[K] exp(2 pi i K n / 2Q)), the pair means
@@ -1478,7 +1479,7 @@ hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     dim3 grid((units + C::WC - 1) / C::WC, g.nf), block(C::WC * C::TL);
     const bool full = g.N == PP / 2;
     if constexpr (PP >= 16) {
-      if (PP >= 4 * g.N) {  // doubled grids
+      if (PP >= 4 * g.N) {  // scaled grids
         if (pairs) launch(k_fwd_x<R, PP, false, true, true>, grid, block, 0, s, ft, g, tb);
         else launch(k_fwd_x<R, PP, false, false, true>, grid, block, 0, s, ft, g, tb);
         return;
@@ -1498,7 +1499,7 @@ hipError_t launch_fwd_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     using C = Cfg<R, PP, kPassY>;
     dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
     if constexpr (PP >= 16) {
-      if (PP >= 4 * g.N) {  // doubled grids
+      if (PP >= 4 * g.N) {  // scaled grids
         launch(k_fwd_y<R, PP, false, true>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
         return;
       }

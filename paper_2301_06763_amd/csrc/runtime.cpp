@@ -476,8 +476,8 @@ struct PassBytes {
     return nout * nout * half() * c + nout * nout * nout * r + (carry ? NS * NS * NS * r : 0.0) +
            (next ? (kind == 4 ? 1 : 2) * NS * NS * NS * r : 0.0);
   }
-  // doubled grid's folded last pass: N^2 half spectra read, the hole
-  // potential read and Phi(Omega^l) written on N^3 cells, the carry read
+  // a scaled grid's folded last pass: N^2 half spectra read, the potential
+  // so far read and Phi(Omega^l) written on N^3 cells, the carry read
   double ix_doubled(bool carry) const {
     return N * N * half() * c + 2 * N * N * N * r + (carry ? NS * NS * NS * r : 0.0);
   }
@@ -740,9 +740,10 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   const bool fused = nmc::plane_passes_fit<R>(P) && !(reqs[0].flags & NMC_NO_FUSED_PLANES);
   if (mod) {
     // Modified method: hole grids with full output (kind 4) and the finest
-    // full grid on period P, as in the hole pipeline; the doubled grids
-    // (kind 3) on period 2P, independent of them until their last pass,
-    // which adds the 2^3 mean to the hole potential in phi and the carry.
+    // full grid on period P, as in the hole pipeline; the scaled grids
+    // (doubled on period 2P, quadrupled on 4P) independent of them until
+    // their last passes, which add their means to the hole potential in phi
+    // (the doubled grids' pass also the carry).
     if ((rc = restrict_cascade(s))) return rc;
     std::vector<FieldDesc> holes, finest;
     for (const auto& f : fulls) (f.kind == 4 ? holes : finest).push_back(f);
@@ -755,7 +756,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
       NMC_HIP(ctx, for_chunks_p(fs, N, nmc::launch_inv_y_fold<R>, NMC_PASS_IY, st, Pc, tbc));
       return NMC_OK;
     };
-    auto doubled_to_iy = [&](hipStream_t st) -> int {
+    auto scaled_grids_to_iy = [&](hipStream_t st) -> int {
       int r = scaled_to_iy(secs, PD, tbd, st);
       return r ? r : scaled_to_iy(quads, PQ, tbq, st);
     };
@@ -763,7 +764,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     if (fork) {
       NMC_HIP(ctx, hipEventRecord(ctx->ev_fork, s));
       NMC_HIP(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0));
-      if ((rc = doubled_to_iy(aux))) return rc;
+      if ((rc = scaled_grids_to_iy(aux))) return rc;
       NMC_HIP(ctx, hipEventRecord(ctx->ev_join, aux));
     }
     if (fused) {
@@ -780,7 +781,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     }
     if (fork) {
       NMC_HIP(ctx, hipStreamWaitEvent(s, ctx->ev_join, 0));
-    } else if ((rc = doubled_to_iy(s))) {
+    } else if ((rc = scaled_grids_to_iy(s))) {
       return rc;
     }
     if (!secs.empty())

@@ -299,3 +299,35 @@ def test_modified3_batch_and_graph_equal_alone(ctx, MOD, MOD3, dtype):
         ctx.solve(r, h, G, f, out=out)
         torch.cuda.synchronize()
         assert torch.equal(out, alone[0])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_serving_mix_of_methods_equals_alone(dtype, MOD, MOD3):
+    """The continuous-batching loop groups requests by N, precision and
+    method; every request of a mix of the three methods gives bitwise the
+    result it gives alone, within the admission budget."""
+    from paper_2301_06763_amd import nmc
+    shapes = [(16, 3), (32, 4), (16, 4), (32, 3), (16, 5), (32, 2), (16, 3), (32, 4), (16, 2)]
+    methods = [0, MOD, MOD3]
+    items = []
+    for i, (N, L) in enumerate(shapes):
+        w = inputs.random_levels(N, L, seed=1000 + i)
+        items.append((w.rho.to("cuda", dtype), w.h0, 1.0 + 0.05 * i, methods[i % 3]))
+    budget = 128 << 20
+    c = nmc.Context(budget_bytes=budget)
+    try:
+        alone = [c.solve(r, h, G, f | nmc.NMC_NO_GRAPH).clone() for r, h, G, f in items]
+        tickets = []
+        for k, (r, h, G, f) in enumerate(items):
+            tickets.append(c.submit(r, h, G, f))
+            if k % 2 == 1:
+                c.tick()
+        c.drain()
+        for tk, a in zip(tickets, alone):
+            assert c.poll(tk)
+            assert torch.equal(tk.phi, a)
+        st = c.stats()
+        assert st["completed"] == len(items) and st["inflight"] == 0
+        assert st["peak_inflight_bytes"] <= budget
+    finally:
+        c.close()
