@@ -331,3 +331,34 @@ def test_serving_mix_of_methods_equals_alone(dtype, MOD, MOD3):
         assert st["peak_inflight_bytes"] <= budget
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("flag", ["MOD", "MOD3"])
+def test_modified_batch_spanning_several_launches(ctx, MOD, MOD3, flag):
+    """Ten requests of 4 levels: 40 period-P grids, 30 doubled and (three-
+    level) 20 quadrupled grids, more than one launch holds (24 grids); each
+    request matches the oracle and its own solve alone."""
+    from paper_2301_06763_amd import nmc
+    f = MOD if flag == "MOD" else MOD3
+    scheme = "pairs" if flag == "MOD" else "triples"
+    items, refs = [], []
+    for i in range(10):
+        w = inputs.random_levels(8, 4, seed=1100 + i)
+        items.append((w.rho.to("cuda", torch.float64), w.h0, 1.0 + 0.1 * i, f))
+        refs.append(oracle.solve_modified(w.rho.numpy(), w.h0, G=1.0 + 0.1 * i, scheme=scheme))
+    batch = ctx.solve_batch(items)
+    torch.cuda.synchronize()
+    for (r, h, G, fl), b, ref in zip(items, batch, refs):
+        assert np.max(rel_err(b.cpu().numpy(), ref)) < F64_TOL
+        assert torch.equal(ctx.solve(r, h, G, fl | nmc.NMC_NO_GRAPH), b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_modified_period_above_4n(ctx, MOD, MOD3, dtype):
+    """N = 36: period 128 (> 2N), doubled period 256 (> 4N), quadrupled 512."""
+    w = inputs.random_levels(36, 3, seed=36)
+    rho = w.rho.numpy()
+    for f, scheme in ((MOD, "pairs"), (MOD3, "triples")):
+        ref = oracle.solve_modified(rho, w.h0, scheme=scheme)
+        got = run(ctx, rho, w.h0, f, dtype=dtype)
+        assert np.max(rel_err(got, ref)) < tol_of(dtype), scheme
