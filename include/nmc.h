@@ -61,6 +61,13 @@ enum {
    * (mass conserving; the paper leaves the coarse mass under a finer grid
    * unspecified). */
   NMC_NO_RESTRICT = 1u << 0,
+  /* Carry the coarser levels' hole potentials to finer cells with the
+   * tensor-product rule (weights 3/4 and 1/4 per axis over the 8
+   * surrounding coarse cells) instead of the default: Eqs. 3-6 applied to
+   * every fine cell (3/4 of the parent plus 1/4 of the diagonal neighbour).
+   * Both are exact on linear fields (Sect. 4 leaves the interpolation
+   * open). */
+  NMC_PROLONG_TRILINEAR = 1u << 1,
   /* FP32 only: plain FP32 cross-level sums instead of the compensated
    * (two-term) carry.  For ablation. */
   NMC_F32_UNCOMPENSATED = 1u << 2,
@@ -135,7 +142,7 @@ int nmc_footprint_bytes_flags(int N, int L, nmc_precision p, unsigned flags, siz
  *   refine  refinement factor between levels; must be 2
  *   G     gravitational constant (finite)
  *   p     element type of rho and phi and arithmetic of the FFT path
- *   flags NMC_NO_RESTRICT, NMC_F32_UNCOMPENSATED, NMC_NO_GRAPH, NMC_ONE_STREAM,
+ *   flags NMC_NO_RESTRICT, NMC_PROLONG_TRILINEAR, NMC_F32_UNCOMPENSATED, NMC_NO_GRAPH, NMC_ONE_STREAM,
  *         NMC_NO_FUSED_PLANES, NMC_MODIFIED, NMC_MODIFIED3
  *   hip_stream  hipStream_t to enqueue on.  The hole grids and the carry
  *         cascade run on a second, library-owned stream that is forked from
@@ -160,8 +167,8 @@ typedef struct {
 
 /* Solve `count` independent nested meshes (Sect. 4: the grids of a solve are
  * independent, and so are solves).  Requests of equal N, precision and
- * method (original, NMC_MODIFIED, NMC_MODIFIED3) share every FFT pass
- * launch.  Each result is bitwise identical to the same request solved
+ * method (original, NMC_MODIFIED, NMC_MODIFIED3; and carry rule) share
+ * every FFT pass launch.  Each result is bitwise identical to the same request solved
  * alone.  All requests are validated before any work. */
 int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_stream);
 

@@ -323,7 +323,7 @@ def quadrupled_potential(mass_fine: np.ndarray, h_fine: float, G: float = 1.0, m
 
 
 def solve_modified(rho: np.ndarray, h0: float, G: float = 1.0, *, restrict: bool = True,
-                   method: str = "fft", scheme: str = "pairs") -> np.ndarray:
+                   method: str = "fft", scheme: str = "pairs", trilinear: bool = False) -> np.ndarray:
     """The modified convolution method that keeps the dipole moments across
     every pair of neighbouring grids (Sect. 7, Appendix B, Eqs. B.1-B.2):
     Phi(Omega^n) = Phi^n_hole + ~Phi^{n+1}_dbl + (hole potentials of the
@@ -350,7 +350,7 @@ def solve_modified(rho: np.ndarray, h0: float, G: float = 1.0, *, restrict: bool
     for n in range(L):
         h = level_spacing(h0, n)
         M = rr[n] * h ** 3
-        A = prolong(S) if n > 0 else 0.0
+        A = (prolong_trilinear(S) if trilinear else prolong(S)) if n > 0 else 0.0
         if n < L - 1:
             hole_n = conv(hole(M), h, G)
             hf = level_spacing(h0, n + 1)
@@ -366,10 +366,13 @@ def solve_modified(rho: np.ndarray, h0: float, G: float = 1.0, *, restrict: bool
     return phi
 
 
-def solve_points(rho: np.ndarray, h0: float, pts, G: float = 1.0, *, restrict: bool = True) -> np.ndarray:
+def solve_points(rho: np.ndarray, h0: float, pts, G: float = 1.0, *, restrict: bool = True,
+                 trilinear: bool = False) -> np.ndarray:
     """Phi(Omega^(l+1)) at selected cells pts[k] = (l, z, y, x), each by
     direct summation of Eq. (10) on every grid involved and the same carry
     rule as solve() (for spot checks at sizes where the full oracle is slow).
+    The carry is written out per cell here (parent and neighbour per axis),
+    independently of prolong() / prolong_trilinear().
     """
     rho = np.asarray(rho, dtype=np.float64)
     L, N = rho.shape[0], rho.shape[1]
@@ -388,14 +391,20 @@ def solve_points(rho: np.ndarray, h0: float, pts, G: float = 1.0, *, restrict: b
         return potential_at(mass(l, is_hole), level_spacing(h0, l), np.array([p]), G)[0]
 
     def carry(n, p):  # A_n at cell p of level n (n >= 1)
+        pc = [(N // 4 + f // 2, 1 if f % 2 == 1 else -1) for f in p]  # parent, direction per axis
         out = 0.0
-        for w, off in ((0.75, 0), (0.25, 1)):
-            q = []
-            for f in p:
-                c = N // 4 + f // 2
-                s = 1 if f % 2 == 1 else -1
-                q.append(c + off * s)
-            out += w * S_at(n - 1, tuple(q))
+        if not trilinear:  # along the diagonal: all axes at the parent, or all at the neighbour
+            for w, off in ((0.75, 0), (0.25, 1)):
+                out += w * S_at(n - 1, tuple(c + off * d for c, d in pc))
+            return out
+        for oz in (0, 1):  # every corner of the 2^3 block, 3/4 or 1/4 per axis
+            for oy in (0, 1):
+                for ox in (0, 1):
+                    w = 1.0
+                    for o in (oz, oy, ox):
+                        w *= 0.25 if o else 0.75
+                    q = tuple(c + o * d for (c, d), o in zip(pc, (oz, oy, ox)))
+                    out += w * S_at(n - 1, q)
         return out
 
     def S_at(m, p):  # S_m = A_m + Phi^m_hole, with A_0 = 0

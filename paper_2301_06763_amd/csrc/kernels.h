@@ -50,6 +50,7 @@ struct FieldDesc {
   int kind;          // 0 full level, 1 child-region box, 2 level with its child region zeroed,
                      // 3 doubled grid, 4 hole grid with full output
   int comp;          // FP32: compensated (two-term) carry
+  int tri;           // carry by the tensor-product rule (NMC_PROLONG_TRILINEAR), else Eqs. 3-6
 };
 
 // Restriction data (Sect. 2: the density of a level's child region is the
@@ -173,6 +174,10 @@ hipError_t launch_pyramid(const PyramidTable&, int count, int N, int maxL, hipSt
 // Every request of the table has the same comp.
 template <class R>
 hipError_t launch_carry(const CarryTable&, int count, int N, int n0, hipStream_t);
+// S_n for level n alone (1 <= n <= nlev per request) by the tensor-product
+// rule (NMC_PROLONG_TRILINEAR), from S_{n-1} (S_0 = Phi^0_hole).
+template <class R>
+hipError_t launch_carry_tri(const CarryTable&, int count, int N, int n, hipStream_t);
 
 // Gravitational acceleration of a solved nested potential phi [L][N][N][N]
 // into g [L][3][N][N][N] (six-point stencil, Appendix A methods A and B).

@@ -609,26 +609,72 @@ __device__ __forceinline__ void hermitian_inputs(Row row, bool active, int t, cp
   }
 }
 
-// Prolong(S_{l-1}) (Eqs. 3-6) at level cell x of the rows srow_i (parent) and
-// srow_j (diagonal neighbour) of the carried box S, as s + l: FP64 and the
-// uncompensated FP32 path give the plain weighted sum and l = 0; the
-// compensated path gives 3/4 a exactly as p1 + e1 (FMA), 1/4 b (exact) added
-// with TwoSum, and the rounding errors plus the carried lo terms in l.
-template <class R>
-__device__ __forceinline__ void carried(const FieldDesc& F, const R* S, const R* Sl, size_t srow_i,
-                                        size_t srow_j, int x, R& s, R& l) {
+// Rows of the carried box S (NS cells per axis) for level cell (z, y): ii
+// at the parent's z and y, jj at the neighbours' (c + s per axis, Eqs. 3-6);
+// the mixed rows (parent z, neighbour y) and (neighbour z, parent y) are
+// ii + dyn and jj - dyn.
+struct CarryRows {
+  size_t ii, jj;
+  int dyn;
+};
+__device__ __forceinline__ CarryRows carry_rows(int z, int y, int NS) {
+  const int iz = z / 2 + 1, iy = y / 2 + 1;
+  const int jz = iz + ((z & 1) ? 1 : -1), jy = iy + ((y & 1) ? 1 : -1);
+  return CarryRows{((size_t)iz * NS + iy) * NS, ((size_t)jz * NS + jy) * NS, (jy - iy) * NS};
+}
+
+// Prolong(S_{l-1}) at level cell x of the rows cr of the carried box S, as
+// s + l.  Default, Eqs. 3-6 applied to every fine cell: 3/4 of the parent
+// plus 1/4 of the diagonal neighbour.  tri (NMC_PROLONG_TRILINEAR): the
+// tensor-product rule, weights 3/4 (parent) and 1/4 (neighbour) per axis
+// over the 8 surrounding cells.  FP64 and the uncompensated FP32 path give
+// the plain weighted sum and l = 0; the compensated path forms each product
+// exactly (FMA), adds them with TwoSum and keeps the rounding errors plus the
+// carried lo terms in l.
+template <class R, bool TRI>
+__device__ __forceinline__ void carried(bool comp, const R* S, const R* Sl, const CarryRows& cr, int x, R& s,
+                                        R& l) {
   const int ix = x / 2 + 1, jx = ix + ((x & 1) ? 1 : -1);
-  const R a = S[srow_i + ix], b = S[srow_j + jx];
-  if (sizeof(R) == 8 || !F.comp) {
-    s = (R)0.75 * a + (R)0.25 * b;
-    l = 0;
+  if constexpr (!TRI) {
+    const R a = S[cr.ii + ix], b = S[cr.jj + jx];
+    if (sizeof(R) == 8 || !comp) {
+      s = (R)0.75 * a + (R)0.25 * b;
+      l = 0;
+    } else {
+      const R p1 = (R)0.75 * a;
+      const R e1 = fma((R)0.75, a, -p1);
+      R e2;
+      two_sum(p1, (R)0.25 * b, s, e2);
+      l = e1 + e2;
+      if (Sl) l += (R)0.75 * Sl[cr.ii + ix] + (R)0.25 * Sl[cr.jj + jx];
+    }
   } else {
-    const R p1 = (R)0.75 * a;
-    const R e1 = fma((R)0.75, a, -p1);
-    R e2;
-    two_sum(p1, (R)0.25 * b, s, e2);
-    l = e1 + e2;
-    if (Sl) l += (R)0.75 * Sl[srow_i + ix] + (R)0.25 * Sl[srow_j + jx];
+    const size_t ij = cr.ii + cr.dyn, ji = cr.jj - cr.dyn;
+    const size_t at[8] = {cr.ii + ix, cr.ii + jx, ij + ix, ij + jx, ji + ix, ji + jx, cr.jj + ix, cr.jj + jx};
+    const R w[8] = {(R)27 / 64, (R)9 / 64, (R)9 / 64, (R)3 / 64, (R)9 / 64, (R)3 / 64, (R)3 / 64, (R)1 / 64};
+    R a[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = S[at[i]];
+    s = 0;
+    l = 0;
+    if (sizeof(R) == 8 || !comp) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s += w[i] * a[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const R p = w[i] * a[i];
+        const R e = fma(w[i], a[i], -p);
+        R t, e2;
+        two_sum(s, p, t, e2);
+        s = t;
+        l += e + e2;
+      }
+      if (Sl) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) l += w[i] * Sl[at[i]];
+      }
+    }
   }
 }
 
@@ -638,7 +684,7 @@ __device__ __forceinline__ void carried(const FieldDesc& F, const R* S, const R*
 // no carry) and, on the stencil box of a level with a finer one, S_l =
 // Phi(Omega^l) - C_l (child-region boxes) or the hole potential itself
 // (kind 4, C null).
-template <class R, int P, int K>
+template <class R, int P, int K, bool TRI>
 __device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const GridGeo& gg, int z, int y,
                                            int zr, int yr, int t, const cplx<R>* v) {
   constexpr int E = Plan<R, P, K>::E, TL = P / E;
@@ -659,10 +705,7 @@ __device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const Grid
   R* Slo = static_cast<R*>(F.Slo_out);
   const R* Cb = static_cast<const R*>(F.C);
   const bool yz_box = So && z >= blo && z < blo + NS && y >= blo && y < blo + NS;
-  // carry source rows for this (y, z): parent and diagonal neighbour
-  const int iz = z / 2 + 1, iy = y / 2 + 1;
-  const int jz = iz + ((z & 1) ? 1 : -1), jy = iy + ((y & 1) ? 1 : -1);
-  const size_t srow_i = ((size_t)iz * NS + iy) * NS, srow_j = ((size_t)jz * NS + jy) * NS;
+  const CarryRows cr = carry_rows(z, y, NS);  // carry source rows for this (y, z)
   const size_t brow = ((size_t)(z - blo) * NS + (y - blo)) * NS - blo;
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
@@ -672,7 +715,7 @@ __device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const Grid
     R hi = val, lo = 0;  // Phi(Omega^l) as an unevaluated sum hi + lo
     if (S) {
       R s1, l;
-      carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
+      carried<R, TRI>(F.comp, S, Sl, cr, x, s1, l);
       if (sizeof(R) == 8 || !F.comp) {
         hi = val + s1;
       } else {
@@ -706,7 +749,7 @@ __device__ __forceinline__ void ix_outputs(const FieldDesc& F, int N, const Grid
 // Otherwise one line per transform (its imaginary part unused), which keeps
 // twice the workgroups and half the epilogue per thread (measured faster for
 // the full grids' carry epilogue below N = 256).
-template <class R, int P, bool PAIRS>
+template <class R, int P, bool PAIRS, bool TRI>
 __global__ void __launch_bounds__((Cfg<R, P, kPassIX>::WC * Cfg<R, P, kPassIX>::TL))
 k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassIX>;
@@ -757,12 +800,12 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   tws.put(stw);
   fft_line<R, P, +1, false, true, kPassIX>(v, t, lds, stw);
   if (!active) return;
-  ix_outputs<R, P, kPassIX>(F, N, gg, z, y, zr, yr, t, v);
+  ix_outputs<R, P, kPassIX, TRI>(F, N, gg, z, y, zr, yr, t, v);
   if constexpr (PAIRS) {
     T vb[E / 2];
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) vb[q] = T{v[q].y, 0};
-    ix_outputs<R, P, kPassIX>(F, N, gg, z, y + 1, zr, yr + 1, t, vb);
+    ix_outputs<R, P, kPassIX, TRI>(F, N, gg, z, y + 1, zr, yr + 1, t, vb);
   }
 }
 
@@ -804,23 +847,23 @@ k_inv_y_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
 // S is set, Prolong(S_{l-1}); TwoSum on the compensated FP32 path.  For a
 // doubled grid out holds the hole potential, for a quadrupled grid (run
 // after it) the sum so far.
-template <class R>
-__device__ __forceinline__ void scaled_out(const FieldDesc& F, R* orow, const R* S, const R* Sl, size_t srow_i,
-                                           size_t srow_j, int x, R m) {
+template <class R, bool TRI>
+__device__ __forceinline__ void scaled_out(const FieldDesc& F, R* orow, const R* S, const R* Sl,
+                                           const CarryRows& cr, int x, R m) {
   const R base = orow[x];
   R hi, lo = 0;
   if (sizeof(R) == 8 || !F.comp) {
     hi = base + m;
     if (S) {
       R s1, l;
-      carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
+      carried<R, TRI>(F.comp, S, Sl, cr, x, s1, l);
       hi += s1;
     }
   } else {
     two_sum(base, m, hi, lo);
     if (S) {
       R s1, l, s2, e3;
-      carried<R>(F, S, Sl, srow_i, srow_j, x, s1, l);
+      carried<R, TRI>(F.comp, S, Sl, cr, x, s1, l);
       two_sum(hi, s1, s2, e3);
       hi = s2;
       lo += e3 + l;
@@ -833,7 +876,7 @@ __device__ __forceinline__ void scaled_out(const FieldDesc& F, R* orow, const R*
 // (z, y) and (z, y + 1), folded to the packed half spectra of length P and
 // inverted as one complex transform (row y in the real part, y + 1 in the
 // imaginary part); the S^3 means are added to out (scaled_out).
-template <class R, int P, int S>
+template <class R, int P, int S, bool TRI>
 __global__ void __launch_bounds__((Cfg<R, P, kPassIX>::WC * Cfg<R, P, kPassIX>::TL))
 k_inv_x_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassIX>;
@@ -887,17 +930,15 @@ k_inv_x_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
   R* out = static_cast<R*>(F.out);
   const R* Sc = static_cast<const R*>(F.S);
   const R* Sl = static_cast<const R*>(F.Slo);
-  const int iz = z / 2 + 1, jz = iz + ((z & 1) ? 1 : -1);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int yy = y + h;
-    const int iy = yy / 2 + 1, jy = iy + ((yy & 1) ? 1 : -1);
-    const size_t srow_i = ((size_t)iz * NS + iy) * NS, srow_j = ((size_t)jz * NS + jy) * NS;
+    const CarryRows cr = carry_rows(z, yy, NS);
     R* orow = out + ((size_t)z * N + yy) * N;
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int x = t + TL * q;
-      if (x < N) scaled_out<R>(F, orow, Sc, Sl, srow_i, srow_j, x, h == 0 ? v[q].x : v[q].y);
+      if (x < N) scaled_out<R, TRI>(F, orow, Sc, Sl, cr, x, h == 0 ? v[q].x : v[q].y);
     }
   }
 }
@@ -991,7 +1032,7 @@ __global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_fwd_xy(FieldTable ft,
   }
 }
 
-template <class R, int P, bool FULLN>
+template <class R, int P, bool FULLN, bool TRI>
 __global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_inv_yx(FieldTable ft, PassGeom g, Tables<R> tb) {
   using PC = PlaneCfg<R, P>;
   using T = cplx<R>;
@@ -1047,7 +1088,7 @@ __global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_inv_yx(FieldTable ft,
       T v[E];
       hermitian_inputs<R, P, kPassOther>([&](int k) { return T{pre[yc * PS + k], pim[yc * PS + k]}; }, active, t, v);
       fft_line<R, P, +1, false, true, kPassOther>(v, t, lds, stw);
-      if (active) ix_outputs<R, P, kPassOther>(F, N, gg, z, gg.olo + yr, zr, yr, t, v);
+      if (active) ix_outputs<R, P, kPassOther, TRI>(F, N, gg, z, gg.olo + yr, zr, yr, t, v);
     }
   }
 }
@@ -1239,6 +1280,38 @@ __global__ void __launch_bounds__(256) k_carry(CarryTable tab, int N, int n0) {
     case 1: carry_tree<R, COMP, 2>(C, N, n, lhi, llo, bz, by, bx, hi, lo); break;
     case 2: carry_tree<R, COMP, 3>(C, N, n, lhi, llo, bz, by, bx, hi, lo); break;
     default: carry_tree<R, COMP, 4>(C, N, n, lhi, llo, bz, by, bx, hi, lo); break;
+  }
+  R* out = static_cast<R*>(C.S) + (size_t)n * 2 * C.box;
+  out[id] = hi;
+  if (COMP) out[C.box + id] = lo;
+}
+
+// One level n of the carry cascade with the tensor-product rule
+// (NMC_PROLONG_TRILINEAR): S_n = Prolong(S_{n-1}) + Phi^n_hole on the
+// stencil box, S_0 = Phi^0_hole.  Each S_n reads 8 values of S_{n-1}, so the
+// cascade is not unrolled (one launch per level).
+template <class R, bool COMP>
+__global__ void __launch_bounds__(256) k_carry_tri(CarryTable tab, int N, int n) {
+  const int NB = N / 2 + 2, nb3 = NB * NB * NB;
+  const int r = blockIdx.y;
+  if (n > tab.nlev[r]) return;  // uniform: a request with fewer levels
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  if (id >= nb3) return;
+  const CarryDesc& C = tab.r[r];
+  const R* S = static_cast<const R*>(C.S);
+  const R* phi = n == 1 ? static_cast<const R*>(C.hole) : S + (size_t)(n - 1) * 2 * C.box;
+  const R* plo = (n == 1 || !COMP) ? nullptr : phi + C.box;
+  const int off = N / 4 - 1;  // box cell b is level cell b + off
+  const int bz = id / (NB * NB), by = id / NB % NB, bx = id % NB;
+  R s, l, hi, lo = 0;
+  carried<R, true>(COMP, phi, plo, carry_rows(bz + off, by + off, NB), bx + off, s, l);
+  const R h = static_cast<const R*>(C.hole)[(size_t)n * C.box + id];
+  if constexpr (sizeof(R) == 8 || !COMP) {
+    hi = s + h;
+  } else {
+    R e;
+    two_sum(s, h, hi, e);
+    lo = e + l;
   }
   R* out = static_cast<R*>(C.S) + (size_t)n * 2 * C.box;
   out[id] = hi;
@@ -1562,10 +1635,16 @@ hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     using C = Cfg<R, PP, kPassIX>;
     const int units = pairs ? g.n * g.n / 2 : g.n * g.n;
     dim3 grid((units + C::WC - 1) / C::WC, g.nf);
-    if (pairs)
-      launch(k_inv_x<R, PP, true>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+    // a launch's grids share the carry rule (the runtime groups by it)
+    const bool tri = ft.f[0].tri != 0;
+    if (pairs && tri)
+      launch(k_inv_x<R, PP, true, true>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+    else if (pairs)
+      launch(k_inv_x<R, PP, true, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+    else if (tri)
+      launch(k_inv_x<R, PP, false, true>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
     else
-      launch(k_inv_x<R, PP, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+      launch(k_inv_x<R, PP, false, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
   });
 }
 
@@ -1596,10 +1675,13 @@ hipError_t launch_inv_x_fold(const FieldTable& ft, PassGeom g, Tables<R> tb, hip
     if constexpr (PP <= 256) {
       using C = Cfg<R, PP, kPassIX>;
       dim3 grid((g.N * g.N / 2 + C::WC - 1) / C::WC, g.nf);
+      const bool tri = ft.f[0].tri != 0;
       if (g.S == 2) {
-        launch(k_inv_x_fold<R, PP, 2>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+        if (tri) launch(k_inv_x_fold<R, PP, 2, true>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+        else launch(k_inv_x_fold<R, PP, 2, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
       } else if constexpr (PP <= 128) {
-        launch(k_inv_x_fold<R, PP, 4>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+        // quadrupled grids add no carry
+        launch(k_inv_x_fold<R, PP, 4, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
       }
     }
   });
@@ -1637,10 +1719,15 @@ hipError_t launch_inv_yx(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStre
     using PC = PlaneCfg<R, PP>;
     if constexpr (PP <= kPlaneMaxP && PC::LDS <= kPlaneLdsMax) {
       dim3 grid(g.n, g.nf);
-      if (g.N == PP / 2)
-        launch(k_inv_yx<R, PP, true>, grid, dim3(PC::NTH), 0, s, ft, g, tb);
+      const bool tri = ft.f[0].tri != 0;
+      if (g.N == PP / 2 && tri)
+        launch(k_inv_yx<R, PP, true, true>, grid, dim3(PC::NTH), 0, s, ft, g, tb);
+      else if (g.N == PP / 2)
+        launch(k_inv_yx<R, PP, true, false>, grid, dim3(PC::NTH), 0, s, ft, g, tb);
+      else if (tri)
+        launch(k_inv_yx<R, PP, false, true>, grid, dim3(PC::NTH), 0, s, ft, g, tb);
       else
-        launch(k_inv_yx<R, PP, false>, grid, dim3(PC::NTH), 0, s, ft, g, tb);
+        launch(k_inv_yx<R, PP, false, false>, grid, dim3(PC::NTH), 0, s, ft, g, tb);
     }
   });
 }
@@ -1666,6 +1753,16 @@ hipError_t launch_pyramid(const PyramidTable& tab, int count, int N, int maxL, h
     blocks += nc * nc * nc;
   }
   launch(k_pyramid<R>, dim3(blocks, count), dim3(kPyramidThreads), 0, s, tab, N, maxL);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_carry_tri(const CarryTable& tab, int count, int N, int n, hipStream_t s) {
+  const int NB = N / 2 + 2, per = (NB * NB * NB + 255) / 256;
+  if (sizeof(R) == 4 && tab.r[0].comp)
+    launch(k_carry_tri<R, true>, dim3(per, count), dim3(256), 0, s, tab, N, n);
+  else
+    launch(k_carry_tri<R, false>, dim3(per, count), dim3(256), 0, s, tab, N, n);
   return hipGetLastError();
 }
 
@@ -1753,6 +1850,7 @@ hipError_t launch_fft_lines(const void* in, void* out, int P, int nlines, int di
   template hipError_t launch_restrict<R>(const R*, const R*, R*, int, hipStream_t);               \
   template hipError_t launch_pyramid<R>(const PyramidTable&, int, int, int, hipStream_t);          \
   template hipError_t launch_carry<R>(const CarryTable&, int, int, int, hipStream_t);              \
+  template hipError_t launch_carry_tri<R>(const CarryTable&, int, int, int, hipStream_t);          \
   template hipError_t launch_accel<R>(const R*, R*, int, int, double, hipStream_t);                \
   template hipError_t launch_fft_lines<R>(const void*, void*, int, int, int, const void*, hipStream_t); \
   template hipError_t launch_green_layout<R>(int, const double*, R*, R*, hipStream_t);                 \

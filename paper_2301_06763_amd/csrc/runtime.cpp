@@ -57,8 +57,12 @@ bool is_modified(unsigned flags) { return (flags & (NMC_MODIFIED | NMC_MODIFIED3
 // The three-level scheme of Appendix B adds a quadrupled grid (period 4P)
 // per level with two finer levels.
 bool is_modified3(unsigned flags, int L) { return (flags & NMC_MODIFIED3) != 0 && L >= 3; }
-// Which method a request uses (requests of one group share every launch).
-int method_of(unsigned flags) { return (flags & NMC_MODIFIED3) ? 2 : (flags & NMC_MODIFIED) ? 1 : 0; }
+// Which method a request uses (requests of one group share every launch):
+// original / modified / three-level, times two carry rules.
+int method_of(unsigned flags) {
+  const int m = (flags & NMC_MODIFIED3) ? 2 : (flags & NMC_MODIFIED) ? 1 : 0;
+  return m + ((flags & NMC_PROLONG_TRILINEAR) ? 3 : 0);
+}
 // Largest period a solve with these flags needs.
 int max_period(int N, int L, unsigned flags) {
   const int P = period_of(N);
@@ -588,6 +592,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
       f.scale = -q.G * h * h / P3;
       f.kind = hole_full ? 4 : 0;
       f.comp = comp ? 1 : 0;
+      f.tri = (q.flags & NMC_PROLONG_TRILINEAR) ? 1 : 0;
       fulls.push_back(f);
       full_level.push_back(l);
       // three-level scheme (Appendix B): a level with two finer levels takes
@@ -608,6 +613,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
         c.scale = -q.G * hq * hq / PQ3;
         c.kind = 3;
         c.comp = f.comp;
+        c.tri = f.tri;
         quads.push_back(c);
       }
       if (finer && mod) {
@@ -629,6 +635,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
         c.scale = -q.G * hf * hf / PD3;
         c.kind = triple ? 5 : 3;
         c.comp = f.comp;
+        c.tri = f.tri;
         secs.push_back(c);
       } else if (finer) {
         FieldDesc c{};
@@ -642,6 +649,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
         c.scale = f.scale;
         c.kind = boxes ? 1 : 2;
         c.comp = f.comp;
+        c.tri = f.tri;
         secs.push_back(c);
       }
     }
@@ -695,6 +703,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
     }
     return NMC_OK;
   };
+  const bool tri = (reqs[0].flags & NMC_PROLONG_TRILINEAR) != 0;  // shared by the group (method_of)
   auto carry_cascade = [&](hipStream_t st) -> int {
     const double ns3 = std::pow((double)NC, 3);
     // one launch sequence per kind of sum (compensated or plain)
@@ -707,6 +716,25 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
       while (a + cnt < order.size() && cnt < nmc::kMaxCarriesPerLaunch &&
              carries[order[a + cnt]].comp == carries[order[a]].comp)
         ++cnt;
+      if (tri) {
+        // tensor-product rule: one launch per level
+        nmc::CarryTable tab{};
+        int maxlev = 0;
+        for (int k = 0; k < cnt; ++k) {
+          tab.r[k] = carries[order[a + k]];
+          tab.nlev[k] = carry_levels[order[a + k]];
+          maxlev = std::max(maxlev, tab.nlev[k]);
+        }
+        for (int n = 1; n <= maxlev; ++n) {
+          double bytes = 0;
+          for (int k = 0; k < cnt; ++k)
+            if (n <= tab.nlev[k]) bytes += ns3 * sizeof(R) * (tab.r[k].comp ? 5 : 3);  // S_{n-1}, hole read; S_n written
+          ProfScope ps(ctx, st, NMC_PASS_CARRY, bytes);
+          NMC_HIP(ctx, nmc::launch_carry_tri<R>(tab, cnt, N, n, st));
+        }
+        a += cnt;
+        continue;
+      }
       for (int n0 = 1;; n0 += nmc::kMaxCarryDepth) {
         nmc::CarryTable tab{};
         int any = 0;

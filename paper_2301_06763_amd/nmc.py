@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("NMC_LIBRARY") or os.path.join(HERE, "libnmc.so")
 NMC_F64, NMC_F32 = 0, 1
 NMC_OK, NMC_EINVAL, NMC_ENOMEM, NMC_EDEVICE, NMC_EUNSUPPORTED, NMC_EAGAIN = 0, -1, -2, -3, -4, -5
 NMC_NO_RESTRICT = 1 << 0
+NMC_PROLONG_TRILINEAR = 1 << 1
 NMC_F32_UNCOMPENSATED = 1 << 2
 NMC_NO_GRAPH = 1 << 3
 NMC_ONE_STREAM = 1 << 4

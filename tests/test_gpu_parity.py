@@ -448,3 +448,61 @@ def test_acceleration_rejects_bad_arguments(ctx):
     assert L.nmc_acceleration(h, phi.data_ptr(), g.data_ptr(), 260, 2, 0.1, 0, s) == nmc.NMC_EUNSUPPORTED
     torch.cuda.synchronize()
     assert torch.all(g == 5.0)
+
+
+# --- the tensor-product carry rule (NMC_PROLONG_TRILINEAR) -------------------
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("N,L,extra", [(8, 3, 0), (12, 3, 0), (16, 4, 0), (16, 6, 0), (32, 4, 0), (32, 4, 1)])
+def test_trilinear_carry(ctx, dtype, N, L, extra):
+    """Hole-grid formulation with the tensor-product carry (one cascade
+    launch per level), fused plane passes and (extra) the separate ones."""
+    from paper_2301_06763_amd import nmc
+    w = inputs.random_levels(N, L, seed=1200 + N + L)
+    rho = w.rho.numpy()
+    ref = oracle.solve(rho, w.h0, trilinear=True)
+    flags = nmc.NMC_PROLONG_TRILINEAR | (nmc.NMC_NO_FUSED_PLANES if extra else 0)
+    got = run(ctx, rho, w.h0, dtype=dtype, flags=flags)
+    tol = F64_TOL if dtype == torch.float64 else F32_TOL
+    assert np.max(rel_err(got, ref)) < tol
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_trilinear_carry_child_region_boxes(ctx, dtype):
+    """N = 128: child-region boxes, S_l = Phi(Omega^l) - C_l left by each
+    level's last pass with the tensor-product carry."""
+    from paper_2301_06763_amd import nmc
+    w = inputs.random_levels(128, 3, seed=1300)
+    rho = w.rho.numpy()
+    ref = oracle.solve(rho, w.h0, trilinear=True)
+    got = run(ctx, rho, w.h0, dtype=dtype, flags=nmc.NMC_PROLONG_TRILINEAR)
+    tol = F64_TOL if dtype == torch.float64 else F32_TOL
+    assert np.max(rel_err(got, ref)) < tol
+
+
+@pytest.mark.parametrize("scheme", ["pairs", "triples"])
+def test_trilinear_carry_modified(ctx, scheme):
+    from paper_2301_06763_amd import nmc
+    w = inputs.random_levels(16, 4, seed=1400)
+    rho = w.rho.numpy()
+    ref = oracle.solve_modified(rho, w.h0, scheme=scheme, trilinear=True)
+    f = nmc.NMC_MODIFIED if scheme == "pairs" else nmc.NMC_MODIFIED3
+    for dtype, tol in ((torch.float64, F64_TOL), (torch.float32, F32_TOL)):
+        got = run(ctx, rho, w.h0, dtype=dtype, flags=f | nmc.NMC_PROLONG_TRILINEAR)
+        assert np.max(rel_err(got, ref)) < tol
+
+
+def test_trilinear_and_default_in_one_batch(ctx):
+    """Requests with either carry rule in one batch fall into separate
+    groups; each equals its solve alone."""
+    from paper_2301_06763_amd import nmc
+    items = []
+    for i in range(4):
+        w = inputs.random_levels(16, 4, seed=1500 + i)
+        items.append((w.rho.to("cuda", torch.float32), w.h0, 1.0, nmc.NMC_PROLONG_TRILINEAR if i % 2 else 0))
+    alone = [ctx.solve(r, h, G, f | nmc.NMC_NO_GRAPH).clone() for r, h, G, f in items]
+    batch = ctx.solve_batch(items)
+    torch.cuda.synchronize()
+    for a, b in zip(alone, batch):
+        assert torch.equal(a, b)
+    assert not torch.equal(alone[0], ctx.solve(items[0][0], items[0][1], 1.0, nmc.NMC_PROLONG_TRILINEAR))

@@ -279,13 +279,18 @@ def test_mass_only_on_finest_level():
     assert abs(parts["restricted"][0].sum() * h0 ** 3 - 1.0) < 1e-13
 
 
-def test_solve_points_matches_solve():
-    rho = RNG.random((3, 8, 8, 8))
-    phi = oracle.solve(rho, 0.4)
-    pts = [(0, 0, 0, 0), (1, 3, 4, 5), (2, 7, 0, 6), (2, 4, 4, 3), (1, 0, 7, 7)]
-    got = oracle.solve_points(rho, 0.4, pts)
+@pytest.mark.parametrize("trilinear", [False, True])
+def test_solve_points_matches_solve(trilinear):
+    """The FFT route with the carry arrays of prolong() / prolong_trilinear()
+    against direct sums at single cells with the carry written per cell."""
+    rho = RNG.random((4, 8, 8, 8))
+    phi = oracle.solve(rho, 0.4, trilinear=trilinear)
+    pts = [(0, 0, 0, 0), (1, 3, 4, 5), (2, 7, 0, 6), (2, 4, 4, 3), (1, 0, 7, 7), (3, 2, 5, 1), (3, 7, 7, 0)]
+    got = oracle.solve_points(rho, 0.4, pts, trilinear=trilinear)
     want = np.array([phi[p] for p in pts])
     assert np.max(np.abs(got - want) / np.abs(want)) < 1e-13
+    if trilinear:  # the two rules differ on the finer levels
+        assert np.max(np.abs(phi[1:] - oracle.solve(rho, 0.4)[1:])) > 1e-6 * np.max(np.abs(phi))
 
 
 def test_no_restrict_keeps_coarse_density():
