@@ -107,9 +107,13 @@ enum {
 };
 
 /* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
- * library's workspace (0 = no cap); the Green-spectrum cache is extra.
- * *out receives the context.  Errors: NMC_EINVAL (out null, bad device),
- * NMC_EDEVICE. */
+ * library's workspace and its cached Green-spectrum tables together (0 = no
+ * cap; the short-lived buffers of a table's first build are not counted).
+ * Over the budget the context releases cached workspace blocks and then the
+ * least recently used tables of periods the current work does not need
+ * (after synchronising the device; captured graph replays are dropped with
+ * them and recaptured on demand).  *out receives the context.  Errors:
+ * NMC_EINVAL (out null, bad device), NMC_EDEVICE. */
 int nmc_create(nmc_ctx** out, int hip_device, size_t hbm_budget_bytes);
 
 /* Destroy a context after synchronising its device work; frees every
@@ -206,6 +210,7 @@ typedef struct {
   size_t inflight_bytes;    /* workspace held by in-flight batches */
   size_t budget_bytes;      /* admission budget (0 = unlimited) */
   size_t peak_inflight_bytes;
+  size_t green_cache_bytes; /* Green-spectrum tables held by the context */
 } nmc_serve_stats;
 
 int nmc_serve_stats_get(nmc_ctx* ctx, nmc_serve_stats* out);

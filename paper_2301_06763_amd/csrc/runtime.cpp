@@ -163,6 +163,8 @@ struct PerP {
   float* g32 = nullptr;
   double *gz64 = nullptr, *gn64 = nullptr;  // z-pass layouts
   float *gz32 = nullptr, *gn32 = nullptr;
+  size_t bytes = 0;   // device bytes of the spectrum tables (0 while not built)
+  uint64_t used = 0;  // last use (context clock), for the LRU eviction
 };
 
 struct ServeItem {
@@ -206,6 +208,7 @@ struct nmc_ctx {
   size_t budget = 0;
   std::string err = "no error";
   std::map<int, PerP> perp;
+  size_t green_bytes = 0;  // Green tables held (counted against the budget)
   // workspace pool
   std::vector<Block> free_blocks;
   std::deque<Lease> leases;  // outstanding (event not yet observed complete)
@@ -284,6 +287,14 @@ double self_cell_integral() {
   return (double)(3.0L * logl(2.0L + sqrtl(3.0L)) - pi / 2.0L);
 }
 
+// Device bytes of the Green tables of period P: the FP64 and FP32 spectrum
+// octants and their z-pass layouts (the twiddles are small and not counted).
+size_t green_table_bytes(int P) {
+  const size_t H = P / 2 + 1;
+  return H * H * H * 12 + (nmc::green_layout_elems<double>(P) + H * H) * 8 +
+         (nmc::green_layout_elems<float>(P) + H * H) * 4;
+}
+
 int ensure_green(nmc_ctx* ctx, int P, hipStream_t s) {
   PerP& pp = ctx->perp[P];
   int rc = ensure_twiddles(ctx, P, pp);
@@ -316,7 +327,20 @@ int ensure_green(nmc_ctx* ctx, int P, hipStream_t s) {
     pp.gz32 = pp.gn32 = nullptr;
     return hip_fail(ctx, e, "green spectrum build");
   }
+  pp.bytes = green_table_bytes(P);
+  ctx->green_bytes += pp.bytes;
   return NMC_OK;
+}
+
+void free_green(nmc_ctx* ctx, PerP& pp) {
+  for (void* q : {(void*)pp.g64, (void*)pp.g32, (void*)pp.gz64, (void*)pp.gn64, (void*)pp.gz32, (void*)pp.gn32})
+    (void)hipFree(q);
+  pp.g64 = nullptr;
+  pp.g32 = nullptr;
+  pp.gz64 = pp.gn64 = nullptr;
+  pp.gz32 = pp.gn32 = nullptr;
+  ctx->green_bytes -= pp.bytes;
+  pp.bytes = 0;
 }
 
 // --- workspace pool ------------------------------------------------------------
@@ -350,14 +374,14 @@ int pool_alloc(nmc_ctx* ctx, size_t bytes, Block* out) {
       return NMC_OK;
     }
     // release cached blocks while over budget (or before a fresh allocation fails)
-    while (ctx->budget && ctx->allocated + bytes > ctx->budget && !ctx->free_blocks.empty()) {
+    while (ctx->budget && ctx->allocated + ctx->green_bytes + bytes > ctx->budget && !ctx->free_blocks.empty()) {
       auto it = std::max_element(ctx->free_blocks.begin(), ctx->free_blocks.end(),
                                  [](const Block& a, const Block& b) { return a.bytes < b.bytes; });
       (void)hipFree(it->ptr);
       ctx->allocated -= it->bytes;
       ctx->free_blocks.erase(it);
     }
-    if (!ctx->budget || ctx->allocated + bytes <= ctx->budget) {
+    if (!ctx->budget || ctx->allocated + ctx->green_bytes + bytes <= ctx->budget) {
       void* p = nullptr;
       hipError_t e = hipMalloc(&p, bytes);
       if (e == hipSuccess) {
@@ -384,7 +408,8 @@ int pool_alloc(nmc_ctx* ctx, size_t bytes, Block* out) {
     reap_leases(ctx, true);  // wait for the oldest outstanding solve, then retry
   }
   return fail(ctx, NMC_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes does not fit (budget " +
-                                   std::to_string(ctx->budget) + ")");
+                                   std::to_string(ctx->budget) + "; held: " + std::to_string(ctx->allocated) +
+                                   " workspace, " + std::to_string(ctx->green_bytes) + " Green tables)");
 }
 
 int lease_close(nmc_ctx* ctx, Lease&& lease, hipStream_t s, std::deque<Lease>* into) {
@@ -870,19 +895,74 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   return NMC_OK;
 }
 
-int prepare(nmc_ctx* ctx, int N, unsigned flags, hipStream_t s) {
+void drop_graph(nmc_ctx* ctx, std::map<GraphKey, GraphEntry>::iterator it);
+
+// Under a budget, until `need` more bytes fit: release cached workspace
+// blocks, then the captured graphs (they hold workspace and the tables'
+// addresses), then the least recently used Green tables whose period is not
+// in `keep` (after the device has finished every use).  What still does not
+// fit is reported by the allocation that follows.
+void make_room(nmc_ctx* ctx, size_t need, const std::vector<int>& keep) {
+  if (!ctx->budget) return;
+  auto over = [&] { return ctx->allocated + ctx->green_bytes + need > ctx->budget; };
+  bool synced = false;
+  reap_leases(ctx, false);
+  while (over()) {
+    if (!ctx->free_blocks.empty()) {
+      auto it = std::max_element(ctx->free_blocks.begin(), ctx->free_blocks.end(),
+                                 [](const Block& a, const Block& b) { return a.bytes < b.bytes; });
+      (void)hipFree(it->ptr);
+      ctx->allocated -= it->bytes;
+      ctx->free_blocks.erase(it);
+      continue;
+    }
+    if (!synced) {
+      (void)hipDeviceSynchronize();
+      reap_leases(ctx, false);
+      while (!ctx->graphs.empty()) drop_graph(ctx, ctx->graphs.begin());
+      synced = true;
+      continue;  // completed leases and the dropped graphs' workspace are free now
+    }
+    PerP* lru = nullptr;
+    for (auto& kv : ctx->perp)
+      if (kv.second.bytes && std::find(keep.begin(), keep.end(), kv.first) == keep.end() &&
+          (!lru || kv.second.used < lru->used))
+        lru = &kv.second;
+    if (!lru) return;
+    free_green(ctx, *lru);
+  }
+}
+
+// Green tables (and twiddles) of every period a group needs, and room for
+// its workspace of ws_bytes, under the budget.
+int prepare(nmc_ctx* ctx, int N, unsigned flags, hipStream_t s, size_t ws_bytes) {
   const int P = period_of(N);
-  int rc = ensure_green(ctx, P, s);
-  if (rc == NMC_OK && is_modified(flags)) rc = ensure_green(ctx, 2 * P, s);
-  if (rc == NMC_OK && (flags & NMC_MODIFIED3) && 4 * P <= kMaxP) rc = ensure_green(ctx, 4 * P, s);
-  return rc;
+  std::vector<int> keep{P};
+  if (is_modified(flags)) keep.push_back(2 * P);
+  if ((flags & NMC_MODIFIED3) && 4 * P <= kMaxP) keep.push_back(4 * P);
+  size_t need = 0;
+  for (int q : keep)
+    if (!ctx->perp[q].bytes) need += green_table_bytes(q);
+  make_room(ctx, need, keep);
+  for (int q : keep) {
+    int rc = ensure_green(ctx, q, s);
+    if (rc) return rc;
+    ctx->perp[q].used = ++ctx->clock;
+  }
+  // a cached block the pool will reuse for the workspace needs no room
+  const size_t ws = align_up(ws_bytes, 2u << 20);
+  reap_leases(ctx, false);
+  const bool reusable = std::any_of(ctx->free_blocks.begin(), ctx->free_blocks.end(),
+                                    [&](const Block& b) { return b.bytes >= ws && b.bytes < 2 * ws; });
+  if (!reusable) make_room(ctx, ws, keep);
+  return NMC_OK;
 }
 
 // Launch requests that share N and precision, on one workspace block.
 int launch_group(nmc_ctx* ctx, const Req* reqs, int count, hipStream_t s, Lease* lease, hipStream_t aux) {
   size_t total = 0;
   for (int i = 0; i < count; ++i) total += make_layout(reqs[i].N, reqs[i].L, reqs[i].p, reqs[i].flags).total;
-  int rc = prepare(ctx, reqs[0].N, reqs[0].flags, s);
+  int rc = prepare(ctx, reqs[0].N, reqs[0].flags, s, total);
   if (rc) return rc;
   Block b{};
   rc = pool_alloc(ctx, total, &b);
@@ -922,7 +1002,7 @@ void drop_graph(nmc_ctx* ctx, std::map<GraphKey, GraphEntry>::iterator it) {
 }
 
 int build_graph(nmc_ctx* ctx, const Req& r, const GraphKey& key, hipStream_t s) {
-  int rc = prepare(ctx, r.N, r.flags, s);
+  int rc = prepare(ctx, r.N, r.flags, s, make_layout(r.N, r.L, r.p, r.flags).total);
   if (rc) return rc;
   if (!ctx->cap_stream) NMC_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   while (ctx->graphs.size() >= kMaxGraphs) {
@@ -1299,6 +1379,7 @@ int nmc_serve_stats_get(nmc_ctx* ctx, nmc_serve_stats* out) {
   if (!ctx || !out) return NMC_EINVAL;
   *out = ctx->stats;
   out->budget_bytes = ctx->budget;
+  out->green_cache_bytes = ctx->green_bytes;
   return NMC_OK;
 }
 

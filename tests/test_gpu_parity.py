@@ -506,3 +506,47 @@ def test_trilinear_and_default_in_one_batch(ctx):
     for a, b in zip(alone, batch):
         assert torch.equal(a, b)
     assert not torch.equal(alone[0], ctx.solve(items[0][0], items[0][1], 1.0, nmc.NMC_PROLONG_TRILINEAR))
+
+
+def test_green_cache_evicted_under_budget():
+    """The budget covers the workspace and the cached Green tables: with room
+    for one three-level 64^3 solve and its tables (periods 128, 256, 512)
+    but not for the period-64 tables as well, alternating it with a 32^3
+    solve evicts and rebuilds those tables, and every result equals the
+    unlimited context's."""
+    from paper_2301_06763_amd import nmc
+    wv = inputs.random_levels(32, 1, seed=1600)
+    wy = inputs.random_levels(64, 3, seed=1601)
+    V = (wv.rho.to("cuda", torch.float32), wv.h0, 1.0, 0)
+    Y = (wy.rho.to("cuda", torch.float32), wy.h0, 1.0, nmc.NMC_MODIFIED3)
+    free = nmc.Context()
+    try:
+        ref_v = free.solve(*V).clone()
+        ref_y = free.solve(*Y).clone()
+    finally:
+        free.close()
+    only_y = nmc.Context()
+    try:
+        only_y.solve(*Y)
+        torch.cuda.synchronize()
+        green_y = only_y.stats()["green_cache_bytes"]
+    finally:
+        only_y.close()
+    ws_y = nmc.footprint_bytes(64, 3, torch.float32, nmc.NMC_MODIFIED3)
+    ws_y = (ws_y + (2 << 20) - 1) // (2 << 20) * (2 << 20)
+    budget = ws_y + green_y + (512 << 10)
+    c = nmc.Context(budget_bytes=budget)
+    try:
+        greens = []
+        # direct solves and (repeated calls) captured graphs, which hold workspace
+        for (r, h, G, f), ref in ((V, ref_v), (Y, ref_y), (V, ref_v), (Y, ref_y), (Y, ref_y), (V, ref_v)):
+            out = c.solve(r, h, G, f)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref)
+            g = c.stats()["green_cache_bytes"]
+            assert g <= budget
+            greens.append(g)
+        assert greens[1] == green_y and greens[3] == green_y  # the period-64 tables were evicted
+        assert greens[2] > green_y and greens[5] > green_y     # and rebuilt for the 32^3 solve
+    finally:
+        c.close()
