@@ -242,6 +242,27 @@ def bench_serving(args):
     print(json.dumps(line), flush=True)
 
 
+def copy_bandwidth(torch, reps=20):
+    """Attainable HBM rate on this GPU for context beside the 8 TB/s peak:
+    a 1 GiB device-to-device copy (1 GiB read + 1 GiB written) timed with
+    events on the current stream, median over the repetitions."""
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * (1 << 30) / (pct(sorted(times), 50) * 1e-3) / 1e9
+
+
 def bench_copyref(args):
     """A plain device copy of known size (1 GiB read + 1 GiB written per
     launch), used to scale the FETCH_SIZE / WRITE_SIZE counters."""
@@ -324,6 +345,9 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, args.dtype),
                 "kernel": "k_z (fused forward-z, Green multiply, inverse-z)",
                 "avg_launch_ms": round(z_ms, 5), "algo_bytes_per_launch": int(z_bytes)}
+    copy_gbs = copy_bandwidth(torch)
+    roofline["copy_GB_s"] = round(copy_gbs, 1)        # measured 1 GiB device copy, same GPU
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
     total_bytes = sum(st["bytes"] for st in prim["prof"].values()) / args.steps
     line = {
         "metric": "nested-mesh solves/s + FFT HBM GB/s, FP32 vs FP64 at \u22641e-5 rel err; p50/p99",

@@ -191,7 +191,10 @@ int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_
 int nmc_serve_submit(nmc_ctx* ctx, const nmc_request* req, uint64_t* ticket);
 
 /* One scheduler step (non-blocking).  *launched (may be NULL) receives the
- * number of requests launched in this step. */
+ * number of requests launched in this step.  On an error return every request
+ * that was not launched stays queued, in arrival order: NMC_ENOMEM when a
+ * batch does not fit the budget with nothing in flight, NMC_EDEVICE when a
+ * launch failed (message in nmc_last_error). */
 int nmc_serve_tick(nmc_ctx* ctx, int* launched);
 
 /* *done = 1 once the ticket's result is complete on the device (the

@@ -273,10 +273,20 @@ int ensure_twiddles(nmc_ctx* ctx, int P, PerP& pp) {
     t32[2 * j] = (float)c;
     t32[2 * j + 1] = (float)s;
   }
-  NMC_HIP(ctx, hipMalloc(&pp.tw64, sizeof(double) * 2 * P));
-  NMC_HIP(ctx, hipMalloc(&pp.tw32, sizeof(float) * 2 * P));
-  NMC_HIP(ctx, hipMemcpy(pp.tw64, t64.data(), sizeof(double) * 2 * P, hipMemcpyHostToDevice));
-  NMC_HIP(ctx, hipMemcpy(pp.tw32, t32.data(), sizeof(float) * 2 * P, hipMemcpyHostToDevice));
+  // the tables are published only when both are complete: a failed call
+  // leaves none behind, and the next call builds them again
+  void *d64 = nullptr, *d32 = nullptr;
+  hipError_t e = hipMalloc(&d64, sizeof(double) * 2 * P);
+  if (e == hipSuccess) e = hipMalloc(&d32, sizeof(float) * 2 * P);
+  if (e == hipSuccess) e = hipMemcpy(d64, t64.data(), sizeof(double) * 2 * P, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d32, t32.data(), sizeof(float) * 2 * P, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d64);
+    (void)hipFree(d32);
+    return hip_fail(ctx, e, "twiddle tables");
+  }
+  pp.tw64 = d64;
+  pp.tw32 = d32;
   return NMC_OK;
 }
 
@@ -302,16 +312,20 @@ int ensure_green(nmc_ctx* ctx, int P, hipStream_t s) {
   if (pp.g64) return NMC_OK;
   const size_t H = P / 2 + 1, n = H * H * H;
   double *t1 = nullptr, *t2 = nullptr;
-  NMC_HIP(ctx, hipMalloc(&pp.g64, n * sizeof(double)));
-  NMC_HIP(ctx, hipMalloc(&pp.g32, n * sizeof(float)));
-  NMC_HIP(ctx, hipMalloc(&t1, n * sizeof(double)));
-  NMC_HIP(ctx, hipMalloc(&t2, n * sizeof(double)));
   const size_t nz64 = nmc::green_layout_elems<double>(P), nz32 = nmc::green_layout_elems<float>(P);
-  NMC_HIP(ctx, hipMalloc(&pp.gz64, nz64 * sizeof(double)));
-  NMC_HIP(ctx, hipMalloc(&pp.gn64, H * H * sizeof(double)));
-  NMC_HIP(ctx, hipMalloc(&pp.gz32, nz32 * sizeof(float)));
-  NMC_HIP(ctx, hipMalloc(&pp.gn32, H * H * sizeof(float)));
-  hipError_t e = nmc::launch_green(P, self_cell_integral(), (const double2*)pp.tw64, t1, t2, pp.g64, s);
+  // pp.g64 marks the tables as built: on any failure below every table is
+  // freed and its pointer cleared, so a later call builds the set again
+  hipError_t e = hipSuccess;
+  for (auto [ptr, bytes] : {std::pair<void**, size_t>{(void**)&pp.g64, n * sizeof(double)},
+                            {(void**)&pp.g32, n * sizeof(float)},
+                            {(void**)&t1, n * sizeof(double)},
+                            {(void**)&t2, n * sizeof(double)},
+                            {(void**)&pp.gz64, nz64 * sizeof(double)},
+                            {(void**)&pp.gn64, H * H * sizeof(double)},
+                            {(void**)&pp.gz32, nz32 * sizeof(float)},
+                            {(void**)&pp.gn32, H * H * sizeof(float)}})
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  if (e == hipSuccess) e = nmc::launch_green(P, self_cell_integral(), (const double2*)pp.tw64, t1, t2, pp.g64, s);
   if (e == hipSuccess) e = nmc::launch_round_f32(pp.g64, pp.g32, n, s);
   if (e == hipSuccess) e = nmc::launch_green_layout<double>(P, pp.g64, pp.gz64, pp.gn64, s);
   if (e == hipSuccess) e = nmc::launch_green_layout<float>(P, pp.g64, pp.gz32, pp.gn32, s);
@@ -412,9 +426,17 @@ int pool_alloc(nmc_ctx* ctx, size_t bytes, Block* out) {
                                    " workspace, " + std::to_string(ctx->green_bytes) + " Green tables)");
 }
 
+// The lease's blocks return to the pool when the event recorded after the
+// solve has completed; without an event, once the stream has drained.
 int lease_close(nmc_ctx* ctx, Lease&& lease, hipStream_t s, std::deque<Lease>* into) {
-  NMC_HIP(ctx, hipEventCreateWithFlags(&lease.ev, hipEventDisableTiming));
-  NMC_HIP(ctx, hipEventRecord(lease.ev, s));
+  hipError_t e = hipEventCreateWithFlags(&lease.ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(lease.ev, s);
+  if (e != hipSuccess) {
+    if (lease.ev) (void)hipEventDestroy(lease.ev);
+    (void)hipStreamSynchronize(s);
+    for (auto& b : lease.blocks) ctx->free_blocks.push_back(b);
+    return hip_fail(ctx, e, "solve completion event");
+  }
   into->push_back(std::move(lease));
   return NMC_OK;
 }
@@ -1109,8 +1131,9 @@ int serve_tick(nmc_ctx* ctx, int* launched) {
     if (!cur.empty()) batches.push_back(std::move(cur));
   }
   std::vector<uint64_t> requeue;
+  int err = NMC_OK;  // a failed launch: it and every later batch stay queued
   for (auto& ts : batches) {
-    if (!requeue.empty()) {  // an earlier batch did not fit: keep arrival order
+    if (!requeue.empty() || err) {  // an earlier batch did not fit or failed: keep arrival order
       requeue.insert(requeue.end(), ts.begin(), ts.end());
       continue;
     }
@@ -1119,17 +1142,26 @@ int serve_tick(nmc_ctx* ctx, int* launched) {
     for (uint64_t t : ts) rs.push_back(ctx->items[t].r);
     hipStream_t s = ctx->streams[ctx->next_stream];
     int rc = launch_group(ctx, rs.data(), (int)rs.size(), s, &b.lease, nullptr);
-    if (rc == NMC_ENOMEM) {
-      // the pool could not place it next to the work in flight (block sizes
-      // differ from footprints): nothing was enqueued, retry on a later tick
+    if (rc == NMC_OK) {
+      hipError_t e = hipEventCreateWithFlags(&b.lease.ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventRecord(b.lease.ev, s);
+      if (e != hipSuccess) {
+        if (b.lease.ev) (void)hipEventDestroy(b.lease.ev);
+        rc = hip_fail(ctx, e, "serving batch event");
+      }
+    }
+    if (rc) {
+      // a failed launch may have enqueued part of the group: its blocks are
+      // free once the stream has drained
+      if (rc != NMC_ENOMEM) (void)hipStreamSynchronize(s);
+      // ENOMEM: the pool could not place it next to the work in flight (block
+      // sizes differ from footprints); nothing was enqueued, retry on a later tick
       for (auto& blk : b.lease.blocks) ctx->free_blocks.push_back(blk);
       requeue.insert(requeue.end(), ts.begin(), ts.end());
+      if (rc != NMC_ENOMEM) err = rc;
       continue;
     }
-    if (rc) return rc;
     ctx->next_stream = (ctx->next_stream + 1) % kServeStreams;
-    NMC_HIP(ctx, hipEventCreateWithFlags(&b.lease.ev, hipEventDisableTiming));
-    NMC_HIP(ctx, hipEventRecord(b.lease.ev, s));
     b.tickets = ts;
     b.bytes = 0;
     for (auto& blk : b.lease.blocks) b.bytes += blk.bytes;  // what the device really holds
@@ -1142,15 +1174,14 @@ int serve_tick(nmc_ctx* ctx, int* launched) {
     n_launched += (int)ts.size();
     ctx->inflight.push_back(std::move(b));
   }
-  if (!requeue.empty()) {
-    if (ctx->inflight.empty())
-      return fail(ctx, NMC_ENOMEM, "serving: a batch does not fit the budget with nothing in flight");
-    // back to the front of the queue, in arrival order
-    std::sort(requeue.begin(), requeue.end());
-    for (auto it = requeue.rbegin(); it != requeue.rend(); ++it) ctx->queue.push_front(*it);
-  }
+  // back to the front of the queue, in arrival order
+  std::sort(requeue.begin(), requeue.end());
+  for (auto it = requeue.rbegin(); it != requeue.rend(); ++it) ctx->queue.push_front(*it);
   ctx->stats.queued = ctx->queue.size();
   if (launched) *launched = n_launched;
+  if (err) return err;
+  if (!requeue.empty() && ctx->inflight.empty())
+    return fail(ctx, NMC_ENOMEM, "serving: a batch does not fit the budget with nothing in flight");
   return NMC_OK;
 }
 
