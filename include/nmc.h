@@ -180,10 +180,11 @@ int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_
  * Requests are queued by nmc_serve_submit.  Every nmc_serve_tick retires
  * finished batches (returning their workspace), then admits queued requests
  * in arrival order while the summed nmc_footprint_bytes of in-flight work
- * stays within the budget, groups the admitted ones by (N, precision) and
- * launches each group as one batched solve on the next serving stream, so
- * new work overlaps the work already on the device.  rho/phi of a submitted
- * request must stay valid until it is reported done. */
+ * stays within the budget, groups the admitted ones as nmc_solve_batch does
+ * (N, precision, method and carry rule) and launches each group as one
+ * batched solve on the next serving stream, so new work overlaps the work
+ * already on the device.  rho/phi of a submitted request must stay valid
+ * until it is reported done. */
 
 /* Queue a request; *ticket receives its id.  NMC_ENOMEM if the request alone
  * exceeds the budget (it could never be admitted); NMC_EINVAL/EUNSUPPORTED as
