@@ -396,12 +396,26 @@ __device__ __forceinline__ void z_unit(int b, int U, int nf, int TP, int& u, int
 // ---------------------------------------------------------------------------
 // Z pass: forward along z (inputs z >= n zero), multiply by the real Green
 // spectrum times the level scale, inverse along z, keep rows z < n.
-// A workgroup owns the rows ky and -ky (mod P) of W adjacent kx columns: the
-// packed DC/Nyquist column needs the value at (-ky, -kz) to separate the two
-// real planes before they are multiplied by different spectra.  SC > 1: a
-// launch of scaled grids (kinds 3 and 5) of scale SC, whose input rows start
-// at ilo; after the multiply their spectrum is folded SC times shorter and
-// inverted at P / SC, which leaves the N rows of level l (the z means).
+// A workgroup owns the rows ky and -ky (mod P) of W adjacent kx columns.
+// The packed DC/Nyquist column kx = 0 needs the value at (-ky, -kz) to
+// separate the two real planes before they are multiplied by different
+// spectra, an exchange through LDS with two barriers.  By default the
+// workgroups of the first tile do it for their lane kx = 0.  With
+// z_col0_split (P = 128 outside the scaled grids: measured faster there; at
+// P = 64 the extra workgroups' latency and from P = 256 their scattered
+// column accesses cost more than they save) workgroups of their own at the
+// start of the grid do it, each owning column 0 of the row pairs of W values
+// of p, and the other workgroups skip it (their lane kx = 0 stores nothing).
+// SC > 1: a launch of scaled grids (kinds 3 and 5) of scale SC, whose input
+// rows start at ilo; after the multiply their spectrum is folded SC times
+// shorter and inverted at P / SC, which leaves the N rows of level l (the z
+// means).
+template <int P, int SC>
+constexpr bool z_col0_split() { return P == 128 && SC == 1; }
+// Column-0 workgroups of a launch of nf grids, rounded up to a multiple of 8
+// so that the other workgroups keep their XCD (blockIdx mod 8, see z_unit).
+__host__ __device__ constexpr int z_col0_blocks(int NT, int nf) { return (NT * nf + 7) / 8 * 8; }
+
 template <class R, int P, bool FULLN, int SC = 1>
 __global__ void __launch_bounds__((2 * Cfg<R, P, SC == 1 ? kPassZ : kPassZScaled>::WZ *
                                    Cfg<R, P, SC == 1 ? kPassZ : kPassZScaled>::TL),
@@ -417,17 +431,30 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ cplx<R> stw[P];
   const TwStage<R, P, 2 * C::WZ * C::TL> tws(tb.tw);
   constexpr int TP = W * (int)sizeof(T) < 128 ? 2 : 1;  // tiles sharing a 128-byte line
-  int unit, f;
-  z_unit(blockIdx.x, NT * (P / 2), g.nf, TP, unit, f);
+  const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
+  constexpr bool SPLIT = z_col0_split<P, SC>();
+  const int nc0 = SPLIT ? z_col0_blocks(NT, g.nf) : 0;
+  const bool col0 = SPLIT && (int)blockIdx.x < nc0;  // uniform: a column-0 workgroup
+  int f, tile, p;
+  if (col0) {
+    if ((int)blockIdx.x >= NT * g.nf) return;  // padding
+    f = blockIdx.x / NT;
+    tile = 0;
+    p = (blockIdx.x % NT) * W + w;
+  } else {
+    int unit;
+    z_unit(blockIdx.x - nc0, NT * (P / 2), g.nf, TP, unit, f);
+    tile = unit % NT;
+    p = unit / NT;
+  }
   const FieldDesc& F = ft.f[f];
   const bool full_in = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks on loads
   const bool full = FULLN && F.kind == 0;     // nout = N = P/2 as well
   const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N, g.S);
   const int n = gg.nin;
-  const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
-  const int tile = unit % NT, p = unit / NT;
   const int ky = side == 0 ? p : (p == 0 ? P / 2 : P - p);
-  const int kx = tile * W + w;
+  const int kx = col0 ? 0 : tile * W + w;
+  const bool owner = !SPLIT || col0 || kx != 0;  // this lane stores its line
   const int kyp = ky <= P / 2 ? ky : P - ky;
   T* B = static_cast<T*>(F.B) + (size_t)ky * (P / 2) + kx;  // row z at + z * P * (P/2)
   constexpr size_t ZS = (size_t)P * (P / 2);
@@ -446,7 +473,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   // spectrum values of this thread's points (the spectrum is even in kz:
   // kz = t + TL q reads row kz for q < E/2 and row P - kz = P/2 - t - TL (q - E/2)
   // above)
-  const R* gcol = tb.gz + (size_t)(kyp * NT + tile) * H * W + w;
+  const R* gcol = tb.gz + (size_t)(kyp * NT + tile) * H * W + (col0 ? 0 : w);
   const R* glo = gcol + t * W;
   const R* ghi = gcol + (P / 2 - t) * W;
   // FP32: fetched after the forward transform, so that they hold no
@@ -468,19 +495,22 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   if constexpr (late) fetch_spectrum();
 
   const R sc = (R)F.scale;
+  // the exchange: every lane of a column-0 workgroup, else lane kx = 0 of the
+  // first tile; point kz of line (side, w) goes to LDS at (side P + kz) XW + w
+  constexpr int XW = SPLIT ? W : 1;
   bool plain = true;
-  if (tile == 0) {  // uniform per workgroup: column kx = 0 needs the row -ky
-    __syncthreads();
-    if (w == 0) {
+  if (SPLIT ? col0 : tile == 0) {  // uniform per workgroup
+    __syncthreads();  // the forward transform's last LDS reads are done
+    if (SPLIT || w == 0) {
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         const int kz = t + TL * q;
-        sre[side * P + kz] = v[q].x;
-        sim[side * P + kz] = v[q].y;
+        sre[(side * P + kz) * XW + w] = v[q].x;
+        sim[(side * P + kz) * XW + w] = v[q].y;
       }
     }
     __syncthreads();
-    plain = w != 0;
+    plain = !SPLIT && w != 0;
   }
   if (plain) {
 #pragma unroll
@@ -498,7 +528,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
     for (int q = 0; q < E; ++q) {
       const int kz = t + TL * q;
       const int nkz = (P - kz) & (P - 1);
-      const T cm = T{sre[ps * P + nkz], -sim[ps * P + nkz]};
+      const T cm = T{sre[(ps * P + nkz) * XW + w], -sim[(ps * P + nkz) * XW + w]};
       const R g0 = ga[q], gnv = gn[kz <= P / 2 ? kz : P - kz];
       const R a = sc * (R)0.5 * (g0 + gnv), b = sc * (R)0.5 * (g0 - gnv);
       v[q] = T{a * v[q].x + b * cm.x, a * v[q].y + b * cm.y};
@@ -509,7 +539,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
     for (int q = 0; q < E / 2; ++q) {
       const int zz = t + TL * q;
-      if (full || (zz >= gg.olo && zz < gg.olo + gg.nout)) B[zz * ZS] = v[q];
+      if (owner && (full || (zz >= gg.olo && zz < gg.olo + gg.nout))) B[zz * ZS] = v[q];
     }
   } else {
     // fold: point kz + (P/SC) s of this thread is its slot q + s E/SC
@@ -535,7 +565,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
 #pragma unroll
     for (int q = 0; q < EF / 2; ++q) {
       const int zz = t + TL * q;
-      if (zz < Nl) B[(size_t)zz * ZS] = u[q];
+      if (owner && zz < Nl) B[(size_t)zz * ZS] = u[q];
     }
   }
 }
@@ -1589,10 +1619,12 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
   return dispatch_p(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassZ>;
-    dim3 grid(((PP / 2) / C::WZ) * (PP / 2) * g.nf);  // one dimension: see z_unit
+    constexpr int NT = (PP / 2) / C::WZ;
+    dim3 grid(NT * (PP / 2) * g.nf);  // one dimension: see k_z, z_unit
     if (PP >= 4 * g.N) {  // scaled grids
       using CS = Cfg<R, PP, kPassZScaled>;
       const dim3 block(2 * CS::WZ * CS::TL);
+      static_assert(!z_col0_split<PP, 2>() && !z_col0_split<PP, 4>(), "scaled z launches keep one workgroup kind");
       if constexpr (PP >= 16) {
         if (g.S == 2) launch(k_z<R, PP, false, 2>, grid, block, 0, s, ft, g, tb);
       }
@@ -1601,6 +1633,7 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
       }
       return;
     }
+    if constexpr (z_col0_split<PP, 1>()) grid.x += z_col0_blocks(NT, g.nf);
     if (g.N == PP / 2)
       launch(k_z<R, PP, true>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
     else
