@@ -401,17 +401,18 @@ __device__ __forceinline__ void z_unit(int b, int U, int nf, int TP, int& u, int
 // separate the two real planes before they are multiplied by different
 // spectra, an exchange through LDS with two barriers.  By default the
 // workgroups of the first tile do it for their lane kx = 0.  With
-// z_col0_split (P = 128 outside the scaled grids: measured faster there; at
-// P = 64 the extra workgroups' latency and from P = 256 their scattered
-// column accesses cost more than they save) workgroups of their own at the
-// start of the grid do it, each owning column 0 of the row pairs of W values
-// of p, and the other workgroups skip it (their lane kx = 0 stores nothing).
+// z_col0_split workgroups of their own at the start of the grid do it, each
+// owning column 0 of the row pairs of W values of p, and the other
+// workgroups skip it (their lane kx = 0 stores nothing).  Measured faster
+// at P = 128 for the level grids and from P = 256 for the scaled grids;
+// elsewhere the extra workgroups' latency (small launches) or their
+// scattered column accesses cost more than the exchange they remove.
 // SC > 1: a launch of scaled grids (kinds 3 and 5) of scale SC, whose input
 // rows start at ilo; after the multiply their spectrum is folded SC times
 // shorter and inverted at P / SC, which leaves the N rows of level l (the z
 // means).
 template <int P, int SC>
-constexpr bool z_col0_split() { return P == 128 && SC == 1; }
+constexpr bool z_col0_split() { return SC == 1 ? P == 128 : P >= 256; }
 // Column-0 workgroups of a launch of nf grids, rounded up to a multiple of 8
 // so that the other workgroups keep their XCD (blockIdx mod 8, see z_unit).
 __host__ __device__ constexpr int z_col0_blocks(int NT, int nf) { return (NT * nf + 7) / 8 * 8; }
@@ -1624,7 +1625,8 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
     if (PP >= 4 * g.N) {  // scaled grids
       using CS = Cfg<R, PP, kPassZScaled>;
       const dim3 block(2 * CS::WZ * CS::TL);
-      static_assert(!z_col0_split<PP, 2>() && !z_col0_split<PP, 4>(), "scaled z launches keep one workgroup kind");
+      static_assert(z_col0_split<PP, 2>() == z_col0_split<PP, 4>(), "one grid size for both scales");
+      if constexpr (z_col0_split<PP, 2>()) grid.x += z_col0_blocks(NT, g.nf);
       if constexpr (PP >= 16) {
         if (g.S == 2) launch(k_z<R, PP, false, 2>, grid, block, 0, s, ft, g, tb);
       }
