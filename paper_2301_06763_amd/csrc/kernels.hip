@@ -404,15 +404,16 @@ __device__ __forceinline__ void z_unit(int b, int U, int nf, int TP, int& u, int
 // z_col0_split workgroups of their own at the start of the grid do it, each
 // owning column 0 of the row pairs of W values of p, and the other
 // workgroups skip it (their lane kx = 0 stores nothing).  Measured faster
-// at P = 128 for the level grids and from P = 256 for the scaled grids;
+// for the FP64 level grids at P = 128 and the scaled grids from P = 256;
 // elsewhere the extra workgroups' latency (small launches) or their
-// scattered column accesses cost more than the exchange they remove.
+// scattered column accesses cost as much as (FP32 level grids at P = 128)
+// or more than the exchange they remove.
 // SC > 1: a launch of scaled grids (kinds 3 and 5) of scale SC, whose input
 // rows start at ilo; after the multiply their spectrum is folded SC times
 // shorter and inverted at P / SC, which leaves the N rows of level l (the z
 // means).
-template <int P, int SC>
-constexpr bool z_col0_split() { return SC == 1 ? P == 128 : P >= 256; }
+template <class R, int P, int SC>
+constexpr bool z_col0_split() { return SC == 1 ? P == 128 && sizeof(R) == 8 : P >= 256; }
 // Column-0 workgroups of a launch of nf grids, rounded up to a multiple of 8
 // so that the other workgroups keep their XCD (blockIdx mod 8, see z_unit).
 __host__ __device__ constexpr int z_col0_blocks(int NT, int nf) { return (NT * nf + 7) / 8 * 8; }
@@ -433,7 +434,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   const TwStage<R, P, 2 * C::WZ * C::TL> tws(tb.tw);
   constexpr int TP = W * (int)sizeof(T) < 128 ? 2 : 1;  // tiles sharing a 128-byte line
   const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
-  constexpr bool SPLIT = z_col0_split<P, SC>();
+  constexpr bool SPLIT = z_col0_split<R, P, SC>();
   const int nc0 = SPLIT ? z_col0_blocks(NT, g.nf) : 0;
   const bool col0 = SPLIT && (int)blockIdx.x < nc0;  // uniform: a column-0 workgroup
   int f, tile, p;
@@ -1625,8 +1626,8 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
     if (PP >= 4 * g.N) {  // scaled grids
       using CS = Cfg<R, PP, kPassZScaled>;
       const dim3 block(2 * CS::WZ * CS::TL);
-      static_assert(z_col0_split<PP, 2>() == z_col0_split<PP, 4>(), "one grid size for both scales");
-      if constexpr (z_col0_split<PP, 2>()) grid.x += z_col0_blocks(NT, g.nf);
+      static_assert(z_col0_split<R, PP, 2>() == z_col0_split<R, PP, 4>(), "one grid size for both scales");
+      if constexpr (z_col0_split<R, PP, 2>()) grid.x += z_col0_blocks(NT, g.nf);
       if constexpr (PP >= 16) {
         if (g.S == 2) launch(k_z<R, PP, false, 2>, grid, block, 0, s, ft, g, tb);
       }
@@ -1635,7 +1636,7 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
       }
       return;
     }
-    if constexpr (z_col0_split<PP, 1>()) grid.x += z_col0_blocks(NT, g.nf);
+    if constexpr (z_col0_split<R, PP, 1>()) grid.x += z_col0_blocks(NT, g.nf);
     if (g.N == PP / 2)
       launch(k_z<R, PP, true>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
     else
