@@ -75,9 +75,10 @@ def test_green_spectrum_matches_oracle(ctx, N):
 
 # (N, L) with N a multiple of 2^L take the block-mean pyramid restriction,
 # the others the cascaded one; L >= 7 below N = 128 needs two carry launches;
-# N = 64 (P = 128) takes the z pass with separate column-0 workgroups.
+# N = 48 and 64 (P = 128) take the z pass with separate column-0 workgroups
+# (N = 48 with input and output rows below the period's half).
 @pytest.mark.parametrize("N,L", [(4, 1), (4, 2), (4, 3), (8, 1), (8, 3), (8, 4), (12, 1), (12, 2),
-                                 (16, 3), (16, 5), (16, 7), (20, 2), (32, 4), (32, 5), (64, 2)])
+                                 (16, 3), (16, 5), (16, 7), (20, 2), (32, 4), (32, 5), (48, 3), (64, 2)])
 def test_random_levels_fp64(ctx, N, L):
     w = inputs.random_levels(N, L, seed=100 + N + L)
     rho = w.rho.numpy()
