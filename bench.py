@@ -27,6 +27,10 @@ WORKLOADS = {
 }
 
 
+# default timed solves per precision (about 50-100 ms of work each)
+WORKLOAD_STEPS = {"plummer32": 500, "ellipsoid64": 400, "binary128": 50, "clumps256": 10}
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -34,18 +38,22 @@ def parse():
                     help="timed solves (default: about 50 ms of work per precision for the workload)")
     ap.add_argument("--flags", type=int, default=0, help="nmc flag bits passed to every solve")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ellipsoid64", choices=sorted(WORKLOADS) + ["serving", "copyref"])
+    ap.add_argument("--workload", default="clumps256", choices=sorted(WORKLOADS) + ["serving", "copyref"])
     ap.add_argument("--requests", type=int, default=1000, help="serving: number of requests")
     ap.add_argument("--budget-gb", type=float, default=24.0, help="serving: HBM admission budget")
-    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"],
+    ap.add_argument("--dtype", default="f64", choices=["f32", "f64"],
                     help="precision of the primary line (the other is reported beside it)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="wall-clock budget of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--side", default="binary128",
+                    help="workload reported in a sub-object beside the primary one ('none' to skip)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving sub-object of a solve workload's line")
     ap.add_argument("--no-oracle-check", action="store_true")
     a = ap.parse_args()
     if a.steps is None:
-        a.steps = {"plummer32": 500, "ellipsoid64": 400, "binary128": 50, "clumps256": 10}.get(a.workload, 20)
+        a.steps = WORKLOAD_STEPS.get(a.workload, 20)
         if a.workload in ("serving",):
             a.steps = a.requests
         if a.workload == "copyref":
@@ -175,12 +183,12 @@ def cpu_oracle_baseline(rho_np, h0, budget_s):
                       f"workers={cores}) in {el:.1f} s"}
 
 
-def bench_serving(args):
+def serving_run(args, torch):
     """Continuous-batching serving of a seeded stream of mixed nested solves
     (N in {32, 64, 128}, L in 2..8, 1-4 Plummer/ellipsoid components, FP32),
-    against the same requests solved one at a time in FP64."""
+    against the same requests solved one at a time in FP64.  Returns the
+    serving record (saturated rate, p50/p99 under Poisson arrivals, baseline)."""
     import numpy as np
-    import torch
     from paper_2301_06763_amd import inputs, nmc, serve
 
     n = args.requests
@@ -205,40 +213,56 @@ def bench_serving(args):
         arr = serve.poisson_arrivals(n, frac * X, seed=5)
         r = serve.run_stream(ctx, reqs32, arr, outs)
         runs[f"poisson_{frac}X"] = dict(r.summary(), rate_per_s=frac * X)
+        print(f"serving: poisson {frac}X done", file=sys.stderr, flush=True)
     st = ctx.stats()
     # spot check: results in the mix equal the same request solved alone
     same = 0
-    for i in range(0, n, max(1, n // 16)):
+    picks = list(range(0, n, max(1, n // 16)))
+    for i in picks:
         alone = ctx.solve(reqs32[i][0], reqs32[i][1], flags=nmc.NMC_NO_GRAPH)
         torch.cuda.synchronize()
         same += int(torch.equal(alone, outs[i]))
-    checked = len(range(0, n, max(1, n // 16)))
-    # baseline: the same requests one at a time in FP64
+    # baseline: the same requests one at a time in FP64 (each synchronised)
     ctx64 = nmc.Context()
     for i in warm.values():
         ctx64.solve(ws[i].rho, ws[i].h0)
     torch.cuda.synchronize()
     svc = serve.one_at_a_time(ctx64, [(w.rho, w.h0, 1.0, nmc.NMC_NO_GRAPH) for w in ws])
-    base = {"solves_per_s": n / svc.sum(), "mean_service_ms": float(svc.mean() * 1e3)}
+    base = {"solves_per_s": n / svc.sum(), "mean_service_ms": float(svc.mean() * 1e3),
+            "latency_model": "p50/p99 under the same Poisson arrivals are computed from the measured "
+                             "per-request service times as a single FIFO server (not replayed live)"}
     for frac in (0.5, 0.9):
         arr = serve.poisson_arrivals(n, frac * X, seed=5)
         comp = serve.fifo_latencies(arr, svc)
         lat = np.sort((comp - arr) * 1e3)
         base[f"poisson_{frac}X"] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
-    line = {
-        "metric": "serving: nested-mesh solves/s with p50/p99 latency (continuous batching, FP32)",
-        "value": round(X, 3), "unit": "solves/s", "n_gpus": 1, "steps": n, "warmup": len(warm),
-        "ms_per_step": round(1e3 / X, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic (seeded Plummer/ellipsoid superpositions, inputs resident in HBM)",
-        "config": {"workload": "serving", "requests": n, "N": [32, 64, 128], "L": [2, 8],
-                   "admission_budget_GB": args.budget_gb, "serving_streams": 4},
-        "runs": runs,
-        "scheduler": {k: st[k] for k in ("batches", "peak_inflight_bytes", "budget_bytes", "completed")},
-        "mix_equals_alone": f"{same}/{checked} bitwise",
-        "baseline_one_at_a_time_f64": base,
-    }
     ctx.close()
     ctx64.close()
+    return {
+        "what": "continuous batching of mixed nested solves, FP32 (native scheduler: footprint admission, "
+                "grouping by N / precision / method, four serving streams)",
+        "workload": {"requests": n, "N": [32, 64, 128], "L": [2, 8], "admission_budget_GB": args.budget_gb,
+                     "serving_streams": 4},
+        "solves_per_s": round(X, 3), "runs": runs,
+        "scheduler": {k: st[k] for k in ("batches", "peak_inflight_bytes", "budget_bytes", "completed")},
+        "mix_equals_alone": f"{same}/{len(picks)} bitwise",
+        "baseline_one_at_a_time_f64": base,
+    }
+
+
+def bench_serving(args):
+    """The serving record as the primary line (--workload serving)."""
+    import torch
+    rec = serving_run(args, torch)
+    X = rec["solves_per_s"]
+    line = {
+        "metric": "serving: nested-mesh solves/s with p50/p99 latency (continuous batching, FP32)",
+        "value": X, "unit": "solves/s", "n_gpus": 1, "steps": args.requests, "warmup": 3,
+        "ms_per_step": round(1e3 / X, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded Plummer/ellipsoid superpositions, inputs resident in HBM)",
+        "config": {"workload": "serving", **rec["workload"]},
+    }
+    line.update({k: v for k, v in rec.items() if k not in ("workload", "solves_per_s")})
     print(json.dumps(line), flush=True)
 
 
@@ -284,6 +308,86 @@ def bench_copyref(args):
                       "config": {"workload": "copyref"}}), flush=True)
 
 
+def z_roofline(prof):
+    """The z pass (forward z, Green multiply, inverse z: the dominant kernel)
+    of a profiled run: algorithmic bytes per launch over its average launch
+    duration (HIP events recorded by the kernel launch itself)."""
+    z = prof["z"]
+    z_ms = z["total_ms"] / z["launches"]
+    z_bytes = z["bytes"] / z["launches"]
+    achieved = z_bytes / (z_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "kernel": "k_z (fused forward-z, Green multiply, inverse-z)",
+            "avg_launch_ms": round(z_ms, 5), "algo_bytes_per_launch": int(z_bytes), "launches": z["launches"]}
+
+
+def run_workload(ctx, name, steps, warmup, flags, torch, with_modified=True, with_accel=True):
+    """Both precisions of one workload: timed solves, pass table, FP32 error
+    against FP64, and (where the scaled grids fit) the modified methods."""
+    from paper_2301_06763_amd import inputs, nmc
+    desc, N, L = WORKLOADS[name]
+    print(f"bench: {name} (N={N}, L={L}): generating input", file=sys.stderr, flush=True)
+    w = inputs.WORKLOADS[name](device="cuda")
+    res, outs, accel = {}, {}, {}
+    modified, mouts, modified3 = {}, {}, {}
+    mod_steps = max(10, steps // 4)
+    mod3_steps = max(10, steps // 16)
+    for tag, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        rho = w.rho.to(dt).contiguous()
+        out, el, prof, lat = time_solves(ctx, rho, w.h0, steps, warmup, torch, flags)
+        print(f"bench: {name} {tag}: {steps / el:.2f} solves/s", file=sys.stderr, flush=True)
+        if with_accel:
+            accel[tag] = time_acceleration(ctx, out, w.h0, min(steps, 50), torch)
+        outs[tag] = out.double()
+        res[tag] = {"solves_per_s": steps / el, "ms_per_step": el / steps * 1e3,
+                    "passes": pass_table(prof), "lat": lat, "prof": prof}
+        if with_modified and 2 * nmc.period(N) <= 512:  # the modified method's doubled grids fit
+            mo, mel, mprof, mlat = time_solves(ctx, rho, w.h0, mod_steps, warmup, torch, flags | nmc.NMC_MODIFIED)
+            mouts[tag] = mo.double()
+            modified[tag] = {"solves_per_s": round(mod_steps / mel, 3), "ms_per_step": round(mel / mod_steps * 1e3, 4),
+                             "latency_ms": {"p50": round(pct(mlat, 50), 4), "p99": round(pct(mlat, 99), 4)},
+                             "steps": mod_steps, "passes": pass_table(mprof)}
+        if with_modified and L >= 3 and 4 * nmc.period(N) <= 512:  # quadrupled grids fit
+            _, m3el, m3prof, m3lat = time_solves(ctx, rho, w.h0, mod3_steps, warmup, torch,
+                                                 flags | nmc.NMC_MODIFIED3)
+            modified3[tag] = {"solves_per_s": round(mod3_steps / m3el, 3),
+                              "ms_per_step": round(m3el / mod3_steps * 1e3, 4),
+                              "latency_ms": {"p50": round(pct(m3lat, 50), 4), "p99": round(pct(m3lat, 99), 4)},
+                              "steps": mod3_steps, "passes": pass_table(m3prof)}
+        del rho
+    # FP32 against the FP64 GPU result (the FP64 path is checked against the oracle in tests)
+    e = ((outs["f32"] - outs["f64"]).abs() / outs["f64"].abs())
+    err32 = {"max_rel_err": float(e.max()), "rms_rel_err": float(e.pow(2).mean().sqrt()),
+             "per_level_max": [float(e[l].max()) for l in range(L)],
+             "per_level_rms": [float(e[l].pow(2).mean().sqrt()) for l in range(L)], "tolerance": 1e-5}
+    del e
+    rec = {"w": w, "desc": desc, "N": N, "L": L, "res": res, "err32": err32, "accel": accel}
+    if modified:
+        em = ((mouts["f32"] - mouts["f64"]).abs() / mouts["f64"].abs())
+        rec["modified"] = {
+            "what": "the dipole-preserving method of Sect. 7 / Appendix B (NMC_MODIFIED): per level pair a "
+                    "doubled grid of period 2P (2N cells of the finer spacing) in addition to the hole grids; "
+                    "z and x..inv_y pass rows mix both periods",
+            "doubled_period": 2 * nmc.period(N),
+            "f32": modified["f32"], "f64": modified["f64"],
+            "fp32_vs_fp64": {"max_rel_err": float(em.max()), "rms_rel_err": float(em.pow(2).mean().sqrt())}}
+    if modified3:
+        rec["modified3"] = {
+            "what": "the three-level dipole scheme of Appendix B (NMC_MODIFIED3): in addition, a quadrupled grid "
+                    "of period 4P per level with two finer levels",
+            "quadrupled_period": 4 * nmc.period(N), "f32": modified3["f32"], "f64": modified3["f64"]}
+    return rec
+
+
+def precision_summary(r):
+    z = z_roofline(r["prof"])
+    return {"solves_per_s": round(r["solves_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 4),
+            "latency_ms": {"p50": round(pct(r["lat"], 50), 4), "p99": round(pct(r["lat"], 99), 4)},
+            "z_pass": {k: z[k] for k in ("achieved", "frac", "avg_launch_ms", "algo_bytes_per_launch")},
+            "passes": r["passes"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -292,62 +396,25 @@ def main():
         sys.exit(2)
     import torch
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-    from paper_2301_06763_amd import inputs, nmc
+    from paper_2301_06763_amd import nmc
+    torch.cuda.set_device(0)
     if args.workload == "serving":
-        torch.cuda.set_device(0)
         return bench_serving(args)
     if args.workload == "copyref":
-        torch.cuda.set_device(0)
         return bench_copyref(args)
 
-    torch.cuda.set_device(0)
-    desc, N, L = WORKLOADS[args.workload]
-    w = inputs.WORKLOADS[args.workload](device="cuda")
     ctx = nmc.Context()
-    res = {}
-    outs = {}
-    accel = {}
-    modified, mouts, modified3 = {}, {}, {}
-    mod_steps = max(10, args.steps // 4)
-    mod3_steps = max(10, args.steps // 16)
-    for tag, dt in (("f32", torch.float32), ("f64", torch.float64)):
-        rho = w.rho.to(dt).contiguous()
-        out, el, prof, lat = time_solves(ctx, rho, w.h0, args.steps, args.warmup, torch, args.flags)
-        accel[tag] = time_acceleration(ctx, out, w.h0, min(args.steps, 50), torch)
-        outs[tag] = out.double()
-        res[tag] = {"solves_per_s": args.steps / el, "ms_per_step": el / args.steps * 1e3,
-                    "passes": pass_table(prof), "lat": lat, "prof": prof}
-        if 2 * nmc.period(N) <= 512:  # the modified method's doubled grids fit
-            mo, mel, mprof, mlat = time_solves(ctx, rho, w.h0, mod_steps, args.warmup, torch,
-                                               args.flags | nmc.NMC_MODIFIED)
-            mouts[tag] = mo.double()
-            modified[tag] = {"solves_per_s": round(mod_steps / mel, 3), "ms_per_step": round(mel / mod_steps * 1e3, 4),
-                             "latency_ms": {"p50": round(pct(mlat, 50), 4), "p99": round(pct(mlat, 99), 4)},
-                             "steps": mod_steps, "passes": pass_table(mprof)}
-        if L >= 3 and 4 * nmc.period(N) <= 512:  # the three-level scheme's quadrupled grids fit
-            _, m3el, m3prof, m3lat = time_solves(ctx, rho, w.h0, mod3_steps, args.warmup, torch,
-                                                 args.flags | nmc.NMC_MODIFIED3)
-            modified3[tag] = {"solves_per_s": round(mod3_steps / m3el, 3),
-                              "ms_per_step": round(m3el / mod3_steps * 1e3, 4),
-                              "latency_ms": {"p50": round(pct(m3lat, 50), 4), "p99": round(pct(m3lat, 99), 4)},
-                              "steps": mod3_steps, "passes": pass_table(m3prof)}
-    # FP32 against the FP64 GPU result (the FP64 path is checked against the oracle in tests)
-    e = ((outs["f32"] - outs["f64"]).abs() / outs["f64"].abs())
-    err32 = {"max": float(e.max()), "rms": float(e.pow(2).mean().sqrt()),
-             "per_level_max": [float(e[l].max()) for l in range(L)]}
-
+    rec = run_workload(ctx, args.workload, args.steps, args.warmup, args.flags, torch)
+    N, L, w = rec["N"], rec["L"], rec["w"]
+    res = rec["res"]
     prim = res[args.dtype]
-    z = prim["prof"]["z"]
-    z_ms = z["total_ms"] / z["launches"]
-    z_bytes = z["bytes"] / z["launches"]
-    achieved = z_bytes / (z_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, args.dtype),
-                "kernel": "k_z (fused forward-z, Green multiply, inverse-z)",
-                "avg_launch_ms": round(z_ms, 5), "algo_bytes_per_launch": int(z_bytes)}
+    roofline = z_roofline(prim["prof"])
+    roofline["traffic"] = measured_traffic(args.workload, args.dtype)
+    roofline["bytes_convention"] = ("per grid (n_in + n_out) P (P/2) complex values moved, the spectrum octant "
+                                    "(P/2+1)^3 reals once per launch")
     copy_gbs = copy_bandwidth(torch)
     roofline["copy_GB_s"] = round(copy_gbs, 1)        # measured 1 GiB device copy, same GPU
-    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
     total_bytes = sum(st["bytes"] for st in prim["prof"].values()) / args.steps
     line = {
         "metric": "nested-mesh solves/s + FFT HBM GB/s, FP32 vs FP64 at \u22641e-5 rel err; p50/p99",
@@ -362,43 +429,40 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic (seeded analytic densities sampled at cell centres, inputs resident in HBM)",
-        "config": {"workload": args.workload, "description": desc, "N": N, "L": L, "grids_per_solve": 2 * L - 1,
-                   "padded_period": nmc.period(N), "batch": 1, "parallelism": "none (1 GPU)"},
+        "config": {"workload": args.workload, "description": rec["desc"], "N": N, "L": L,
+                   "grids_per_solve": 2 * L - 1, "padded_period": nmc.period(N), "batch": 1,
+                   "parallelism": "none (1 GPU)"},
         "roofline": roofline,
         "latency_ms": {"p50": round(pct(prim["lat"], 50), 4), "p99": round(pct(prim["lat"], 99), 4)},
         "effective_GB_s": round(total_bytes / (prim["ms_per_step"] * 1e-3) / 1e9, 1),
         "passes": prim["passes"],
-        "fp32_vs_fp64": {"max_rel_err": err32["max"], "rms_rel_err": err32["rms"],
-                         "per_level_max": err32["per_level_max"], "tolerance": 1e-5},
+        "fp32_vs_fp64": rec["err32"],
         "acceleration": {"what": "nmc_acceleration on the solved potential (six-point stencil with the "
                                  "interface rules of Appendix A); a separate call, not in the solve step",
-                         "f32": accel["f32"], "f64": accel["f64"]},
+                         **rec["accel"]},
     }
-    if modified:
-        em = ((mouts["f32"] - mouts["f64"]).abs() / mouts["f64"].abs())
-        line["modified"] = {
-            "what": "the dipole-preserving method of Sect. 7 / Appendix B (NMC_MODIFIED): per level pair a "
-                    "doubled grid of period 2P (2N cells of the finer spacing) in addition to the hole grids; "
-                    "z and x..inv_y pass rows mix both periods",
-            "doubled_period": 2 * nmc.period(N),
-            "f32": modified["f32"], "f64": modified["f64"],
-            "fp32_vs_fp64": {"max_rel_err": float(em.max()), "rms_rel_err": float(em.pow(2).mean().sqrt())}}
-    if modified3:
-        line["modified3"] = {
-            "what": "the three-level dipole scheme of Appendix B (NMC_MODIFIED3): in addition, a quadrupled grid "
-                    "of period 4P per level with two finer levels",
-            "quadrupled_period": 4 * nmc.period(N), "f32": modified3["f32"], "f64": modified3["f64"]}
     other = "f64" if args.dtype == "f32" else "f32"
-    o = res[other]
-    oz = o["prof"]["z"]
-    line[other] = {"solves_per_s": round(o["solves_per_s"], 3), "ms_per_step": round(o["ms_per_step"], 4),
-                   "latency_ms": {"p50": round(pct(o["lat"], 50), 4), "p99": round(pct(o["lat"], 99), 4)},
-                   "z_pass_GB_s": round(oz["bytes"] / oz["launches"] / (oz["total_ms"] / oz["launches"] * 1e-3) / 1e9, 1),
-                   "passes": o["passes"]}
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_oracle_baseline(w.rho.cpu().numpy(), w.h0, args.cpu_seconds)
-        line["cpu_baseline"]["gpu_speedup_f64"] = round(res["f64"]["solves_per_s"] / line["cpu_baseline"]["value"], 1)
+    line[other] = precision_summary(res[other])
+    for k in ("modified", "modified3"):
+        if k in rec:
+            line[k] = rec[k]
+    del rec, res, prim
+    if args.side and args.side != "none" and args.side != args.workload:
+        side = run_workload(ctx, args.side, max(10, WORKLOAD_STEPS.get(args.side, 20) // 2), args.warmup,
+                            args.flags, torch, with_modified=False, with_accel=False)
+        line["side"] = {"workload": args.side, "description": side["desc"], "N": side["N"], "L": side["L"],
+                        "f64": precision_summary(side["res"]["f64"]), "f32": precision_summary(side["res"]["f32"]),
+                        "fp32_vs_fp64": side["err32"]}
+        del side
     ctx.close()
+    torch.cuda.empty_cache()
+    if not args.no_serving:
+        line["serving"] = serving_run(args, torch)
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_oracle_baseline(w.rho.cpu().numpy(), w.h0, args.cpu_seconds)
+        f64_rate = line["value"] if args.dtype == "f64" else line["f64"]["solves_per_s"]
+        line["cpu_baseline"]["gpu_speedup_f64"] = round(f64_rate / line["cpu_baseline"]["value"], 1)
     print(json.dumps(line), flush=True)
 
 

@@ -186,10 +186,17 @@ int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_
  * already on the device.  rho/phi of a submitted request must stay valid
  * until it is reported done. */
 
-/* Queue a request; *ticket receives its id.  NMC_ENOMEM if the request alone
- * exceeds the budget (it could never be admitted); NMC_EINVAL/EUNSUPPORTED as
- * for nmc_solve. */
-int nmc_serve_submit(nmc_ctx* ctx, const nmc_request* req, uint64_t* ticket);
+/* Queue a request; *ticket receives its id.  hip_stream is the stream on
+ * which the caller wrote req->rho (and last used req->phi): an event is
+ * recorded on it here, and the batch that solves the request waits for that
+ * event on its serving stream, so work the caller enqueued on hip_stream
+ * before this call is ordered before the solve.  The result is complete (and
+ * may be read from any stream) once nmc_serve_poll reports it done or
+ * nmc_serve_take_completed returns its ticket.  NMC_ENOMEM if the request
+ * alone exceeds the budget (it could never be admitted); NMC_EINVAL /
+ * NMC_EUNSUPPORTED as for nmc_solve; NMC_EDEVICE if the event cannot be
+ * recorded. */
+int nmc_serve_submit(nmc_ctx* ctx, const nmc_request* req, void* hip_stream, uint64_t* ticket);
 
 /* One scheduler step (non-blocking).  *launched (may be NULL) receives the
  * number of requests launched in this step.  On an error return every request

@@ -171,6 +171,9 @@ struct ServeItem {
   Req r;
   size_t bytes;
   int state;  // 0 queued, 1 in flight, 2 done
+  // recorded on the submitting stream: the request's rho is written and its
+  // phi free once this event has completed
+  hipEvent_t ready = nullptr;
 };
 
 struct Batch {
@@ -221,6 +224,7 @@ struct nmc_ctx {
   std::deque<uint64_t> queue;
   std::deque<Batch> inflight;
   std::deque<uint64_t> completed;
+  std::vector<hipEvent_t> ev_pool;  // reusable submit events
   nmc_serve_stats stats{};
   // second stream of a solve (hole grids and carry cascade) and its fork/join events
   hipStream_t aux_stream = nullptr;
@@ -511,7 +515,10 @@ struct PassBytes {
     return in * r + nin * nin * half() * c;
   }
   double y() const { return nin * nin * half() * c + nin * P * half() * c; }
-  double z() const { return (nin + nout) * P * half() * c + H * H * H * r; }
+  // the spectrum octant is shared by every grid of a launch: spectrum() is
+  // added once per launch
+  double z() const { return (nin + nout) * P * half() * c; }
+  double spectrum() const { return H * H * H * r; }
   double iy() const {
     return nout * P * half() * c + nout * nout * half() * c;
   }
@@ -722,6 +729,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
           default: bytes += pb.ix(ft.f[k].S != nullptr, ft.f[k].Sout != nullptr); break;
         }
       }
+      if (pass == NMC_PASS_Z) bytes += PassBytes(N, Pc, sizeof(R), 0).spectrum();
       PassGeom g{N, Pc, n, cnt, Pc / P};
       ProfScope ps(ctx, st, pass, bytes);
       hipError_t e = launch(ft, g, tbc, st);
@@ -1084,7 +1092,11 @@ int serve_tick(nmc_ctx* ctx, int* launched) {
     if (q == hipErrorNotReady) break;
     if (q != hipSuccess) return hip_fail(ctx, q, "serving batch");
     for (uint64_t t : b.tickets) {
-      ctx->items[t].state = 2;
+      ServeItem& it = ctx->items[t];
+      // the batch waited for this event, so it has completed
+      if (it.ready) ctx->ev_pool.push_back(it.ready);
+      it.ready = nullptr;
+      it.state = 2;
       ctx->completed.push_back(t);
       ctx->stats.completed++;
     }
@@ -1141,7 +1153,16 @@ int serve_tick(nmc_ctx* ctx, int* launched) {
     std::vector<Req> rs;
     for (uint64_t t : ts) rs.push_back(ctx->items[t].r);
     hipStream_t s = ctx->streams[ctx->next_stream];
-    int rc = launch_group(ctx, rs.data(), (int)rs.size(), s, &b.lease, nullptr);
+    // order the batch after the callers' work on its inputs and outputs
+    int rc = NMC_OK;
+    for (uint64_t t : ts) {
+      hipError_t e = hipStreamWaitEvent(s, ctx->items[t].ready, 0);
+      if (e != hipSuccess) {
+        rc = hip_fail(ctx, e, "serving: wait for the submitting stream");
+        break;
+      }
+    }
+    if (rc == NMC_OK) rc = launch_group(ctx, rs.data(), (int)rs.size(), s, &b.lease, nullptr);
     if (rc == NMC_OK) {
       hipError_t e = hipEventCreateWithFlags(&b.lease.ev, hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventRecord(b.lease.ev, s);
@@ -1257,6 +1278,9 @@ void nmc_destroy(nmc_ctx* ctx) {
     (void)hipFree(kv.second.gz32);
     (void)hipFree(kv.second.gn32);
   }
+  for (auto& kv : ctx->items)
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (auto& s : ctx->streams) (void)hipStreamDestroy(s);
   if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
@@ -1354,7 +1378,7 @@ int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_
   return lease_close(ctx, std::move(lease), s, &ctx->leases);
 }
 
-int nmc_serve_submit(nmc_ctx* ctx, const nmc_request* req, uint64_t* ticket) {
+int nmc_serve_submit(nmc_ctx* ctx, const nmc_request* req, void* hip_stream, uint64_t* ticket) {
   if (!ctx) return NMC_EINVAL;
   if (!req || !ticket) return fail(ctx, NMC_EINVAL, "null request or ticket");
   Req r{req->rho, req->phi, req->N, req->L, req->h0, req->G, req->p, req->flags};
@@ -1363,8 +1387,21 @@ int nmc_serve_submit(nmc_ctx* ctx, const nmc_request* req, uint64_t* ticket) {
   const size_t bytes = align_up(make_layout(r.N, r.L, r.p, r.flags).total, 2u << 20);
   if (ctx->budget && bytes > ctx->budget)
     return fail(ctx, NMC_ENOMEM, "request footprint " + std::to_string(bytes) + " exceeds the budget");
+  if ((rc = set_device(ctx))) return rc;
+  hipEvent_t ev = nullptr;
+  if (!ctx->ev_pool.empty()) {
+    ev = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+  } else {
+    NMC_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  }
+  hipError_t e = hipEventRecord(ev, (hipStream_t)hip_stream);
+  if (e != hipSuccess) {
+    ctx->ev_pool.push_back(ev);
+    return hip_fail(ctx, e, "serving: record on the submitting stream");
+  }
   const uint64_t t = ctx->next_ticket++;
-  ctx->items[t] = ServeItem{r, bytes, 0};
+  ctx->items[t] = ServeItem{r, bytes, 0, ev};
   ctx->queue.push_back(t);
   ctx->stats.submitted++;
   ctx->stats.queued = ctx->queue.size();
@@ -1433,9 +1470,12 @@ int nmc_green_spectrum(nmc_ctx* ctx, int N, nmc_precision p, void* out, void* hi
   int rc = set_device(ctx);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)hip_stream;
+  // the tables count against the budget like those of a solve
+  if (!ctx->perp[P].bytes) make_room(ctx, green_table_bytes(P), {P});
   if ((rc = ensure_green(ctx, P, s))) return rc;
   const size_t H = P / 2 + 1, n = H * H * H;
   PerP& pp = ctx->perp[P];
+  pp.used = ++ctx->clock;
   if (p == NMC_F64)
     NMC_HIP(ctx, hipMemcpyAsync(out, pp.g64, n * 8, hipMemcpyDeviceToDevice, s));
   else

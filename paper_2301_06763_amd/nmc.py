@@ -78,7 +78,7 @@ def lib() -> ctypes.CDLL:
         "nmc_footprint_bytes_flags": (i, [i, i, i, ctypes.c_uint, ctypes.POINTER(sz)]),
         "nmc_solve": (i, [vp, vp, vp, i, i, d, i, d, i, u, vp]),
         "nmc_solve_batch": (i, [vp, ctypes.POINTER(Request), i, vp]),
-        "nmc_serve_submit": (i, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "nmc_serve_submit": (i, [vp, ctypes.POINTER(Request), vp, ctypes.POINTER(ctypes.c_uint64)]),
         "nmc_serve_tick": (i, [vp, ctypes.POINTER(i)]),
         "nmc_serve_poll": (i, [vp, ctypes.c_uint64, ctypes.POINTER(i)]),
         "nmc_serve_stats_get": (i, [vp, ctypes.POINTER(ServeStats)]),
@@ -230,12 +230,15 @@ class Context:
 
     # -- serving ---------------------------------------------------------------
     def submit(self, rho: torch.Tensor, h0: float, G: float = 1.0, flags: int = 0,
-               out: torch.Tensor | None = None) -> Ticket:
+               out: torch.Tensor | None = None, stream=None) -> Ticket:
+        """Queue a request for the serving loop; the solve is ordered after the
+        work enqueued so far on `stream` (default: the current stream)."""
         if out is None:
             out = torch.empty_like(rho)
         req = self._request(rho, h0, G, flags, out)
         t = ctypes.c_uint64()
-        rc = lib().nmc_serve_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        rc = lib().nmc_serve_submit(self._h, ctypes.byref(req), _stream_ptr(stream, self.device),
+                                    ctypes.byref(t))
         if rc:
             self._err(rc, "nmc_serve_submit")
         tk = Ticket(t.value, rho, out)
