@@ -156,6 +156,32 @@ int nmc_footprint_bytes_flags(int N, int L, nmc_precision p, unsigned flags, siz
 int nmc_solve(nmc_ctx* ctx, const void* rho, void* phi, int N, int L, double h0, int refine,
               double G, nmc_precision p, unsigned flags, void* hip_stream);
 
+/* Largest workspace nmc_solve_noalloc serves (64 MiB): e.g. N = 32 at any L
+ * in FP64 and FP32, N = 64 up to L = 3 (FP64) or L = 5 (FP32). */
+#define NMC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* nmc_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, semantics and results as nmc_solve (the same kernels; every grid
+ * on hip_stream, never a graph replay), but it calls no hipMalloc, hipFree or
+ * other allocating routine.
+ *   Workspace: a static array of NMC_SCRATCH_BYTES in the library's device
+ *   code, one per GPU (held until the process ends; its address is looked up
+ *   once per device by nmc_create).  Every call on one GPU uses the same
+ *   array and leaves its contents behind: calls whose work overlaps on one
+ *   GPU (other streams, other contexts, other host threads) race and must be
+ *   ordered by the caller.  Nothing in it needs clearing between calls.
+ *   Tables: the Green tables of every period the solve needs (P, and 2P / 4P
+ *   with NMC_MODIFIED / NMC_MODIFIED3) must already be resident in ctx, built
+ *   by an earlier nmc_solve of the same N and method or by nmc_green_spectrum
+ *   of that N (and 2N, 4N); a table evicted under the context's budget must be
+ *   rebuilt the same way.
+ * Errors: as nmc_solve; NMC_ENOMEM when the workspace
+ * (nmc_footprint_bytes_flags) exceeds NMC_SCRATCH_BYTES or a table is not
+ * resident (nothing is enqueued then). */
+int nmc_solve_noalloc(nmc_ctx* ctx, const void* rho, void* phi, int N, int L, double h0, int refine,
+                      double G, nmc_precision p, unsigned flags, void* hip_stream);
+
 /* One request of a batch (same meaning as the nmc_solve arguments; the
  * refinement factor is 2). */
 typedef struct {

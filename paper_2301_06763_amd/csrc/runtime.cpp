@@ -10,6 +10,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <unordered_map>
@@ -30,6 +31,7 @@ constexpr int kMaxP = 512;
 constexpr size_t kAlign = 256;
 constexpr int kServeStreams = 4;
 constexpr int kMaxBatchRequests = 32;
+constexpr int kMaxDevices = 64;
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
@@ -228,6 +230,8 @@ struct nmc_ctx {
   nmc_serve_stats stats{};
   // second stream of a solve (hole grids and carry cascade) and its fork/join events
   hipStream_t aux_stream = nullptr;
+  // this device's static scratch array (nmc_solve_noalloc)
+  char* scratch = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // captured solves
   hipStream_t cap_stream = nullptr;
@@ -1081,6 +1085,37 @@ int set_device(nmc_ctx* ctx) {
   return NMC_OK;
 }
 
+// --- static scratch (nmc_solve_noalloc) -------------------------------------------
+
+}  // namespace
+
+// Workspace of nmc_solve_noalloc: a fixed array in the library's device code,
+// one copy per GPU the library runs on, held until the process ends.  Host
+// code never passes `scratch` itself to a kernel (on the host it names a
+// stand-in, not device memory): it uses the address hipGetSymbolAddress gives
+// for the current device.
+__device__ __align__(256) char scratch[NMC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// Device address of this device's `scratch`, looked up once per device (the
+// device must be current).
+int scratch_address(nmc_ctx* ctx, int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ctx, NMC_EINVAL, "device index above the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch[dev];
+  return NMC_OK;
+}
+
 // --- serving ------------------------------------------------------------------
 
 int serve_tick(nmc_ctx* ctx, int* launched) {
@@ -1252,6 +1287,11 @@ int nmc_create(nmc_ctx** out, int hip_device, size_t hbm_budget_bytes) {
     delete ctx;
     return NMC_EDEVICE;
   }
+  // set-up of nmc_solve_noalloc: this device's scratch address (device current)
+  if (scratch_address(ctx, hip_device, &ctx->scratch) != NMC_OK) {
+    nmc_destroy(ctx);
+    return NMC_EDEVICE;
+  }
   *out = ctx;
   return NMC_OK;
 }
@@ -1328,6 +1368,41 @@ int nmc_solve(nmc_ctx* ctx, const void* rho, void* phi, int N, int L, double h0,
     return rc;
   }
   return lease_close(ctx, std::move(lease), s, &ctx->leases);
+}
+
+int nmc_solve_noalloc(nmc_ctx* ctx, const void* rho, void* phi, int N, int L, double h0, int refine,
+                      double G, nmc_precision p, unsigned flags, void* hip_stream) {
+  if (!ctx) return NMC_EINVAL;
+  Req r{rho, phi, N, L, h0, G, p, flags};
+  int rc = validate(ctx, r, refine);
+  if (rc) return rc;
+  const size_t need = make_layout(N, L, p, flags).total;
+  if (need > NMC_SCRATCH_BYTES)
+    return fail(ctx, NMC_ENOMEM, "nmc_solve_noalloc: workspace of " + std::to_string(need) +
+                                     " bytes exceeds the static scratch of " + std::to_string(NMC_SCRATCH_BYTES) +
+                                     " bytes");
+  // every table the solve reads must already be resident: building one allocates
+  const int P = period_of(N);
+  int periods[3] = {P, 0, 0};
+  if (is_modified(flags)) periods[1] = 2 * P;
+  if (is_modified3(flags, L)) periods[2] = 4 * P;
+  for (int q : periods) {
+    if (!q) continue;
+    auto it = ctx->perp.find(q);
+    if (it == ctx->perp.end() || !it->second.g64 || !it->second.tw64)
+      return fail(ctx, NMC_ENOMEM, "nmc_solve_noalloc: the Green tables of period " + std::to_string(q) +
+                                       " are not resident (build them first with nmc_solve or "
+                                       "nmc_green_spectrum of this N and method)");
+  }
+  if ((rc = set_device(ctx))) return rc;
+  if (!ctx->scratch) return fail(ctx, NMC_EDEVICE, "nmc_solve_noalloc: no scratch address for this device");
+  for (int q : periods)
+    if (q) ctx->perp.find(q)->second.used = ++ctx->clock;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // every grid on the caller's stream; the kernels write every workspace
+  // value before reading it, so nothing needs clearing between calls
+  return p == NMC_F64 ? run_group<double>(ctx, &r, 1, ctx->scratch, s, s)
+                      : run_group<float>(ctx, &r, 1, ctx->scratch, s, s);
 }
 
 int nmc_acceleration(nmc_ctx* ctx, const void* phi, void* g, int N, int L, double h0, nmc_precision p,

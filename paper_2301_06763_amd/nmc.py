@@ -26,6 +26,7 @@ NMC_ONE_STREAM = 1 << 4
 NMC_NO_FUSED_PLANES = 1 << 5
 NMC_MODIFIED = 1 << 6  # the dipole-preserving method of Sect. 7 / Appendix B
 NMC_MODIFIED3 = 1 << 7  # ... with Appendix B's three-level scheme
+NMC_SCRATCH_BYTES = 64 << 20  # largest workspace of solve_noalloc
 
 _CODES = {NMC_EINVAL: "EINVAL", NMC_ENOMEM: "ENOMEM", NMC_EDEVICE: "EDEVICE",
           NMC_EUNSUPPORTED: "EUNSUPPORTED", NMC_EAGAIN: "EAGAIN"}
@@ -77,6 +78,7 @@ def lib() -> ctypes.CDLL:
         "nmc_footprint_bytes": (i, [i, i, i, ctypes.POINTER(sz)]),
         "nmc_footprint_bytes_flags": (i, [i, i, i, ctypes.c_uint, ctypes.POINTER(sz)]),
         "nmc_solve": (i, [vp, vp, vp, i, i, d, i, d, i, u, vp]),
+        "nmc_solve_noalloc": (i, [vp, vp, vp, i, i, d, i, d, i, u, vp]),
         "nmc_solve_batch": (i, [vp, ctypes.POINTER(Request), i, vp]),
         "nmc_serve_submit": (i, [vp, ctypes.POINTER(Request), vp, ctypes.POINTER(ctypes.c_uint64)]),
         "nmc_serve_tick": (i, [vp, ctypes.POINTER(i)]),
@@ -186,6 +188,22 @@ class Context:
                              float(G), precision_of(rho.dtype), flags, _stream_ptr(stream, self.device))
         if rc:
             self._err(rc, "nmc_solve")
+        return out
+
+    def solve_noalloc(self, rho: torch.Tensor, h0: float, G: float = 1.0, flags: int = 0,
+                      out: torch.Tensor | None = None, stream=None, refine: int = 2) -> torch.Tensor:
+        """nmc_solve_noalloc: the solve on the library's static per-device
+        scratch, without any device allocation by the library (the Green
+        tables of this N must be resident; `out` is the caller's)."""
+        _check_levels(rho, "rho")
+        if out is None:
+            out = torch.empty_like(rho)
+        _check_levels(out, "out")
+        L, N = rho.shape[0], rho.shape[1]
+        rc = lib().nmc_solve_noalloc(self._h, rho.data_ptr(), out.data_ptr(), N, L, float(h0), refine,
+                                     float(G), precision_of(rho.dtype), flags, _stream_ptr(stream, self.device))
+        if rc:
+            self._err(rc, "nmc_solve_noalloc")
         return out
 
     def acceleration(self, phi: torch.Tensor, h0: float, out: torch.Tensor | None = None,

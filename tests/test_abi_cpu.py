@@ -123,3 +123,15 @@ def test_pass_names(lib):
     assert names == ["restrict", "x", "y", "z", "inv_y", "inv_x_second", "carry", "inv_x_full",
                      "xy", "inv_yx_second", "inv_yx_full", "acceleration", "inv_x_doubled"]
     assert lib.nmc_pass_name(99) == b"?"
+
+
+def test_scratch_size_matches_binding():
+    from paper_2301_06763_amd import nmc
+    src = open(HEADER).read()
+    m = re.search(r"#define NMC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
+    assert m, "NMC_SCRATCH_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == nmc.NMC_SCRATCH_BYTES
+
+
+def test_noalloc_rejects_null_context(lib):
+    assert lib.nmc_solve_noalloc(None, None, None, 8, 2, 1.0, 2, 1.0, 0, 0, None) == -1
