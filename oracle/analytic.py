@@ -33,6 +33,39 @@ def uniform_sphere(x, y, z, M, R, centre=(0.0, 0.0, 0.0), G=1.0):
     return np.where(r < R, inside, outside)
 
 
+def uniform_sphere_acceleration(x, y, z, M, R, centre=(0.0, 0.0, 0.0), G=1.0):
+    """g = -grad Phi of `uniform_sphere` as (g_x, g_y, g_z): -G M d / r^3
+    outside, -G M d / R^3 inside, d the offset from the centre."""
+    dx, dy, dz = x - centre[0], y - centre[1], z - centre[2]
+    r = _r(x, y, z, centre)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        f = np.where(r < R, -G * M / R ** 3, -G * M / r ** 3)
+    return f * dx, f * dy, f * dz
+
+
+def binary_spheres(x, y, z, R=0.2, sep=0.5, rho_left=2.0, rho_right=1.0, G=1.0):
+    """Phi of the binary star of Sect. 2: two homogeneous spheres of radius R
+    centred at x = -sep and x = +sep, the left one twice as massive (its
+    density twice the right one's)."""
+    m = 4.0 / 3.0 * math.pi * R ** 3
+    return (uniform_sphere(x, y, z, rho_left * m, R, (-sep, 0.0, 0.0), G)
+            + uniform_sphere(x, y, z, rho_right * m, R, (sep, 0.0, 0.0), G))
+
+
+def binary_spheres_acceleration(x, y, z, R=0.2, sep=0.5, rho_left=2.0, rho_right=1.0, G=1.0):
+    """g of `binary_spheres` as (g_x, g_y, g_z)."""
+    m = 4.0 / 3.0 * math.pi * R ** 3
+    a = uniform_sphere_acceleration(x, y, z, rho_left * m, R, (-sep, 0.0, 0.0), G)
+    b = uniform_sphere_acceleration(x, y, z, rho_right * m, R, (sep, 0.0, 0.0), G)
+    return tuple(u + v for u, v in zip(a, b))
+
+
+def binary_spheres_density(x, y, z, R=0.2, sep=0.5, rho_left=2.0, rho_right=1.0):
+    """The binary's density sampled at the points (cell centres)."""
+    return (rho_left * ((x + sep) ** 2 + y ** 2 + z ** 2 <= R * R)
+            + rho_right * ((x - sep) ** 2 + y ** 2 + z ** 2 <= R * R)).astype(float)
+
+
 def plummer(x, y, z, M, a, centre=(0.0, 0.0, 0.0), G=1.0):
     """Phi of a Plummer sphere: -GM / sqrt(r^2 + a^2)."""
     r = _r(x, y, z, centre)

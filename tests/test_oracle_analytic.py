@@ -163,3 +163,104 @@ def test_ellipsoid_acceleration_is_the_gradient():
         num = np.array([-(an.ellipsoid(*(p + d * e), a=axes, rho=1.7, G=0.9)
                           - an.ellipsoid(*(p - d * e), a=axes, rho=1.7, G=0.9)) / (2 * d) for e in np.eye(3)])
         assert np.max(np.abs(g - num)) < 1e-7 * max(1.0, np.max(np.abs(g)))
+
+
+def test_sphere_acceleration_is_the_gradient():
+    """The closed-form acceleration of the sphere and of the binary equals
+    minus the central difference of their closed-form potentials, inside
+    and outside the spheres."""
+    d = 1e-6
+    for p in RNG.uniform(-1.0, 1.0, size=(40, 3)):
+        g = np.array(an.uniform_sphere_acceleration(*p, M=1.3, R=0.4, centre=(0.1, -0.2, 0.05), G=0.7))
+        num = np.array([-(an.uniform_sphere(*(p + d * e), M=1.3, R=0.4, centre=(0.1, -0.2, 0.05), G=0.7)
+                          - an.uniform_sphere(*(p - d * e), M=1.3, R=0.4, centre=(0.1, -0.2, 0.05), G=0.7))
+                        / (2 * d) for e in np.eye(3)])
+        assert np.max(np.abs(g - num)) < 1e-6 * max(1.0, np.max(np.abs(g)))
+        gb = np.array(an.binary_spheres_acceleration(*p))
+        numb = np.array([-(an.binary_spheres(*(p + d * e)) - an.binary_spheres(*(p - d * e))) / (2 * d)
+                         for e in np.eye(3)])
+        assert np.max(np.abs(gb - numb)) < 1e-6 * max(1.0, np.max(np.abs(gb)))
+
+
+def test_binary_is_two_spheres_of_mass_ratio_two():
+    """Far field of the binary: -G (M_l + M_r)/r with M_l = 2 M_r, and the
+    dipole toward the heavier (left) sphere."""
+    m = 4 / 3 * math.pi * 0.2 ** 3
+    far = an.binary_spheres(np.array([0.0]), np.array([0.0]), np.array([1e4]))
+    assert abs(far[0] * 1e4 + 3 * m) < 1e-9
+    left, right = an.binary_spheres(-2.0, 0.0, 0.0), an.binary_spheres(2.0, 0.0, 0.0)
+    assert left < right  # deeper on the heavier side
+
+
+@pytest.fixture(scope="module")
+def table_binary():
+    """Sect. 2 / Sect. 5 binary star (two homogeneous spheres, radius 0.2,
+    centres at x = -0.5 and +0.5, mass ratio 2:1, sampled at cell centres)
+    on four nested grids of 128^3 in [-2.25, 2.25]^3, solved by the oracle."""
+    N, L, B = 128, 4, 4.5
+    h0 = B / N
+    rho = np.empty((L, N, N, N))
+    for l in range(L):
+        Z, Y, X = _level_coords(N, h0 / 2 ** l)
+        rho[l] = an.binary_spheres_density(X, Y, Z)
+    phi = oracle.solve(rho, h0)
+    return N, L, h0, phi, oracle.acceleration(phi, h0)
+
+
+def _binary_plane_errors(table_binary):
+    """err_Phi and err_g (percent) on the x-z plane next to y = 0, all levels."""
+    N, L, h0, phi, g = table_binary
+    ep, eg = [], []
+    for l in range(L):
+        x = oracle.cell_centres(N, h0 / 2 ** l)
+        j = N // 2
+        Z, X = np.meshgrid(x, x, indexing="ij")
+        Y = np.full_like(X, x[j])
+        ep.append(an.relative_error(phi[l][:, j, :], an.binary_spheres(X, Y, Z)).ravel())
+        ga = np.sqrt(sum(c ** 2 for c in an.binary_spheres_acceleration(X, Y, Z)))
+        gn = np.sqrt((g[l][:, :, j, :] ** 2).sum(axis=0))
+        eg.append((np.abs(gn - ga) / ga).ravel())
+    return np.concatenate(ep) * 100, np.concatenate(eg) * 100
+
+
+@pytest.mark.slow
+def test_paper_tables_3_4_binary(table_binary):
+    """Sect. 5, Tables 3 and 4 (convolution row), binary-star columns: with
+    the spheres sampled at cell centres the oracle lands on the paper's
+    potential errors (max 0.85 %, mean 0.43 %, sigma 0.078 %) within 25 %,
+    its mean acceleration error (0.38 %) within 25 % and its max and sigma
+    (9.4 %, 0.29 %) within a factor 2."""
+    with open(os.path.join(GOLDEN, "table3_convolution.json")) as fh:
+        t3 = json.load(fh)["binary_r0.2_x_pm0.5_mass_2to1"]
+    with open(os.path.join(GOLDEN, "table4_convolution.json")) as fh:
+        t4 = json.load(fh)["binary_r0.2_x_pm0.5_mass_2to1"]
+    ep, eg = _binary_plane_errors(table_binary)
+    print("binary potential max/mean/std %", ep.max(), ep.mean(), ep.std())
+    print("binary acceleration max/mean/std %", eg.max(), eg.mean(), eg.std())
+    for got, ref in ((ep.max(), t3["max_percent"]), (ep.mean(), t3["mean_percent"]),
+                     (ep.std(), t3["sigma_percent"]), (eg.mean(), t4["mean_percent"])):
+        assert 0.75 * ref < got < 1.25 * ref, (got, ref)
+    for got, ref in ((eg.max(), t4["max_percent"]), (eg.std(), t4["sigma_percent"])):
+        assert 0.5 * ref < got < 2.0 * ref, (got, ref)
+
+
+@pytest.mark.slow
+def test_paper_fig11_ellipsoid_errors_mostly_small(table_ellipsoid):
+    """Sect. 5, Fig. 11: on the x-z plane the ellipsoid's errors are mostly
+    below 0.01 % (potential) and 0.1 % (acceleration).  Reading of "mostly":
+    at least three quarters of the plane's cells, over all levels."""
+    N, L, h0, axes, phi = table_ellipsoid
+    g = oracle.acceleration(phi, h0)
+    ep, eg = [], []
+    for l in range(L):
+        x = oracle.cell_centres(N, h0 / 2 ** l)
+        j = N // 2
+        Z, X = np.meshgrid(x, x, indexing="ij")
+        Y = np.full_like(X, x[j])
+        ep.append(an.relative_error(phi[l][:, j, :], an.ellipsoid(X, Y, Z, a=axes, rho=1.0)).ravel())
+        ga = np.sqrt(sum(c ** 2 for c in an.ellipsoid_acceleration(X, Y, Z, a=axes, rho=1.0)))
+        eg.append((np.abs(np.sqrt((g[l][:, :, j, :] ** 2).sum(axis=0)) - ga) / ga).ravel())
+    ep, eg = np.concatenate(ep) * 100, np.concatenate(eg) * 100
+    fp, fg = np.mean(ep < 0.01), np.mean(eg < 0.1)
+    print(f"fraction below 0.01 % (potential) {fp:.3f}, below 0.1 % (acceleration) {fg:.3f}")
+    assert fp >= 0.75 and fg >= 0.75
