@@ -18,6 +18,7 @@
 
 #include "../../include/nmc.h"
 #include "kernels.h"
+#include "serve_core.hpp"
 
 namespace {
 
@@ -27,7 +28,8 @@ using nmc::PassGeom;
 
 constexpr int kMinN = 4;
 constexpr int kMaxL = 16;
-constexpr int kMaxP = 512;
+constexpr int kMaxP = 512;         // level grids: N <= 256
+constexpr int kMaxScaledP = 1024;  // doubled grids of N = 256, quadrupled grids of N = 128
 constexpr size_t kAlign = 256;
 constexpr int kServeStreams = 4;
 constexpr int kMaxBatchRequests = 32;
@@ -169,19 +171,12 @@ struct PerP {
   uint64_t used = 0;  // last use (context clock), for the LRU eviction
 };
 
-struct ServeItem {
+// A serving request as the device side needs it: the solve and the event
+// recorded on the submitting stream (its rho is written and its phi free once
+// the event has completed).
+struct ServeReq {
   Req r;
-  size_t bytes;
-  int state;  // 0 queued, 1 in flight, 2 done
-  // recorded on the submitting stream: the request's rho is written and its
-  // phi free once this event has completed
   hipEvent_t ready = nullptr;
-};
-
-struct Batch {
-  std::vector<uint64_t> tickets;
-  Lease lease;
-  size_t bytes;
 };
 
 // A repeated nmc_solve call, identified by every argument.
@@ -218,16 +213,12 @@ struct nmc_ctx {
   std::vector<Block> free_blocks;
   std::deque<Lease> leases;  // outstanding (event not yet observed complete)
   size_t allocated = 0;      // pool + leased
-  // serving
+  // serving: the scheduler core (host logic) and the device side's records
+  std::unique_ptr<nmc::ServeCore> serve;
+  std::unordered_map<uint64_t, ServeReq> sreq;
   hipStream_t streams[kServeStreams] = {};
   int next_stream = 0;
-  uint64_t next_ticket = 1;
-  std::unordered_map<uint64_t, ServeItem> items;
-  std::deque<uint64_t> queue;
-  std::deque<Batch> inflight;
-  std::deque<uint64_t> completed;
   std::vector<hipEvent_t> ev_pool;  // reusable submit events
-  nmc_serve_stats stats{};
   // second stream of a solve (hole grids and carry cascade) and its fork/join events
   hipStream_t aux_stream = nullptr;
   // this device's static scratch array (nmc_solve_noalloc)
@@ -455,10 +446,10 @@ int validate(nmc_ctx* ctx, const Req& r, int refine) {
   if (!r.rho || !r.phi) return fail(ctx, NMC_EINVAL, "rho and phi must be non-null device pointers");
   if (r.N < kMinN || r.N % 4 != 0) return fail(ctx, NMC_EINVAL, "N must be a multiple of 4, >= 4");
   if (!period_of(r.N)) return fail(ctx, NMC_EUNSUPPORTED, "N above 256 (padded period above 512)");
-  if (max_period(r.N, r.L, r.flags) > kMaxP)
+  if (max_period(r.N, r.L, r.flags) > kMaxScaledP)
     return fail(ctx, NMC_EUNSUPPORTED, is_modified3(r.flags, r.L)
-                                           ? "NMC_MODIFIED3: N above 64 (quadrupled-grid period above 512)"
-                                           : "NMC_MODIFIED: N above 128 (doubled-grid period above 512)");
+                                           ? "NMC_MODIFIED3: N above 128 (quadrupled-grid period above 1024)"
+                                           : "NMC_MODIFIED: N above 256 (doubled-grid period above 1024)");
   if (r.L < 1 || r.L > kMaxL) return fail(ctx, NMC_EINVAL, "L must be in [1, 16]");
   if (!(r.h0 > 0) || !std::isfinite(r.h0)) return fail(ctx, NMC_EINVAL, "h0 must be positive and finite");
   if (!std::isfinite(r.G)) return fail(ctx, NMC_EINVAL, "G must be finite");
@@ -572,7 +563,7 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
   const nmc::Tables<R> tb = tables(P);
   const nmc::Tables<R> tbd = mod ? tables(PD) : tb;
   const int PQ = 4 * P;  // period of the quadrupled grids (three-level scheme)
-  const bool any_mod3 = mod && (reqs[0].flags & NMC_MODIFIED3) && PQ <= kMaxP;
+  const bool any_mod3 = mod && (reqs[0].flags & NMC_MODIFIED3) && PQ <= kMaxScaledP;
   const nmc::Tables<R> tbq = any_mod3 ? tables(PQ) : tb;
   std::vector<FieldDesc> quads;  // quadrupled grids
   const size_t lvl = (size_t)N * N * N;
@@ -973,7 +964,7 @@ int prepare(nmc_ctx* ctx, int N, unsigned flags, hipStream_t s, size_t ws_bytes)
   const int P = period_of(N);
   std::vector<int> keep{P};
   if (is_modified(flags)) keep.push_back(2 * P);
-  if ((flags & NMC_MODIFIED3) && 4 * P <= kMaxP) keep.push_back(4 * P);
+  if ((flags & NMC_MODIFIED3) && 4 * P <= kMaxScaledP) keep.push_back(4 * P);
   size_t need = 0;
   for (int q : keep)
     if (!ctx->perp[q].bytes) need += green_table_bytes(q);
@@ -1118,127 +1109,79 @@ int scratch_address(nmc_ctx* ctx, int dev, char** out) {
 
 // --- serving ------------------------------------------------------------------
 
-int serve_tick(nmc_ctx* ctx, int* launched) {
-  int n_launched = 0;
-  // 1. retire finished batches
-  while (!ctx->inflight.empty()) {
-    Batch& b = ctx->inflight.front();
-    hipError_t q = hipEventQuery(b.lease.ev);
-    if (q == hipErrorNotReady) break;
-    if (q != hipSuccess) return hip_fail(ctx, q, "serving batch");
-    for (uint64_t t : b.tickets) {
-      ServeItem& it = ctx->items[t];
-      // the batch waited for this event, so it has completed
-      if (it.ready) ctx->ev_pool.push_back(it.ready);
-      it.ready = nullptr;
-      it.state = 2;
-      ctx->completed.push_back(t);
-      ctx->stats.completed++;
-    }
-    for (auto& blk : b.lease.blocks) ctx->free_blocks.push_back(blk);
-    (void)hipEventDestroy(b.lease.ev);
-    ctx->stats.inflight_bytes -= b.bytes;
-    ctx->stats.inflight -= b.tickets.size();
-    ctx->inflight.pop_front();
+// The serving scheduler's device side: each batch is one batched solve on
+// the next serving stream, ordered after the events recorded at submission,
+// and completes with an event recorded after it.
+class HipServeDevice final : public nmc::ServeDevice {
+ public:
+  explicit HipServeDevice(nmc_ctx* c) : ctx_(c) {}
+  int poll(const nmc::ServeBatch& b) override {
+    const hipError_t q = hipEventQuery(static_cast<const Lease*>(b.dev)->ev);
+    if (q == hipErrorNotReady) return 0;
+    if (q != hipSuccess) return hip_fail(ctx_, q, "serving batch");
+    return 1;
   }
-  // 2. admit in arrival order while the footprint fits
-  std::vector<uint64_t> admitted;
-  size_t bytes = ctx->stats.inflight_bytes;
-  while (!ctx->queue.empty()) {
-    const uint64_t t = ctx->queue.front();
-    const ServeItem& it = ctx->items[t];
-    if (ctx->budget && bytes + it.bytes > ctx->budget) break;
-    bytes += it.bytes;
-    admitted.push_back(t);
-    ctx->queue.pop_front();
-  }
-  // 3. batches per (N, precision, method) group, each on the next serving stream.  A
-  // batch holds at most a quarter of the budget so that several batches are
-  // in flight and overlap on the device.
-  const size_t max_batch_bytes = ctx->budget ? std::max<size_t>(ctx->budget / 4, 1) : SIZE_MAX;
-  std::map<std::tuple<int, int, int>, std::vector<uint64_t>> groups;
-  for (uint64_t t : admitted) {
-    const Req& r = ctx->items[t].r;
-    groups[std::make_tuple(r.N, (int)r.p, method_of(r.flags))].push_back(t);
-  }
-  std::vector<std::vector<uint64_t>> batches;
-  for (auto& kv : groups) {
-    std::vector<uint64_t> cur;
-    size_t cur_bytes = 0;
-    for (uint64_t t : kv.second) {
-      const size_t b = ctx->items[t].bytes;
-      if (!cur.empty() && ((int)cur.size() >= kMaxBatchRequests || cur_bytes + b > max_batch_bytes)) {
-        batches.push_back(std::move(cur));
-        cur.clear();
-        cur_bytes = 0;
-      }
-      cur.push_back(t);
-      cur_bytes += b;
-    }
-    if (!cur.empty()) batches.push_back(std::move(cur));
-  }
-  std::vector<uint64_t> requeue;
-  int err = NMC_OK;  // a failed launch: it and every later batch stay queued
-  for (auto& ts : batches) {
-    if (!requeue.empty() || err) {  // an earlier batch did not fit or failed: keep arrival order
-      requeue.insert(requeue.end(), ts.begin(), ts.end());
-      continue;
-    }
-    Batch b;
+  int launch(nmc::ServeBatch& b) override {
+    auto lease = std::make_unique<Lease>();
     std::vector<Req> rs;
-    for (uint64_t t : ts) rs.push_back(ctx->items[t].r);
-    hipStream_t s = ctx->streams[ctx->next_stream];
+    for (uint64_t t : b.tickets) rs.push_back(ctx_->sreq.at(t).r);
+    hipStream_t s = ctx_->streams[ctx_->next_stream];
     // order the batch after the callers' work on its inputs and outputs
     int rc = NMC_OK;
-    for (uint64_t t : ts) {
-      hipError_t e = hipStreamWaitEvent(s, ctx->items[t].ready, 0);
+    for (uint64_t t : b.tickets) {
+      hipError_t e = hipStreamWaitEvent(s, ctx_->sreq.at(t).ready, 0);
       if (e != hipSuccess) {
-        rc = hip_fail(ctx, e, "serving: wait for the submitting stream");
+        rc = hip_fail(ctx_, e, "serving: wait for the submitting stream");
         break;
       }
     }
-    if (rc == NMC_OK) rc = launch_group(ctx, rs.data(), (int)rs.size(), s, &b.lease, nullptr);
+    if (rc == NMC_OK) rc = launch_group(ctx_, rs.data(), (int)rs.size(), s, lease.get(), nullptr);
     if (rc == NMC_OK) {
-      hipError_t e = hipEventCreateWithFlags(&b.lease.ev, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventRecord(b.lease.ev, s);
+      hipError_t e = hipEventCreateWithFlags(&lease->ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventRecord(lease->ev, s);
       if (e != hipSuccess) {
-        if (b.lease.ev) (void)hipEventDestroy(b.lease.ev);
-        rc = hip_fail(ctx, e, "serving batch event");
+        if (lease->ev) (void)hipEventDestroy(lease->ev);
+        lease->ev = nullptr;
+        rc = hip_fail(ctx_, e, "serving batch event");
       }
     }
     if (rc) {
       // a failed launch may have enqueued part of the group: its blocks are
-      // free once the stream has drained
+      // free once the stream has drained.  ENOMEM: the pool could not place
+      // it next to the work in flight (block sizes differ from footprints);
+      // nothing was enqueued, and a later tick retries
       if (rc != NMC_ENOMEM) (void)hipStreamSynchronize(s);
-      // ENOMEM: the pool could not place it next to the work in flight (block
-      // sizes differ from footprints); nothing was enqueued, retry on a later tick
-      for (auto& blk : b.lease.blocks) ctx->free_blocks.push_back(blk);
-      requeue.insert(requeue.end(), ts.begin(), ts.end());
-      if (rc != NMC_ENOMEM) err = rc;
-      continue;
+      for (auto& blk : lease->blocks) ctx_->free_blocks.push_back(blk);
+      return rc;
     }
-    ctx->next_stream = (ctx->next_stream + 1) % kServeStreams;
-    b.tickets = ts;
+    ctx_->next_stream = (ctx_->next_stream + 1) % kServeStreams;
     b.bytes = 0;
-    for (auto& blk : b.lease.blocks) b.bytes += blk.bytes;  // what the device really holds
-    for (uint64_t t : ts) ctx->items[t].state = 1;
-    ctx->stats.admitted += ts.size();
-    ctx->stats.inflight += ts.size();
-    ctx->stats.batches++;
-    ctx->stats.inflight_bytes += b.bytes;
-    ctx->stats.peak_inflight_bytes = std::max(ctx->stats.peak_inflight_bytes, ctx->stats.inflight_bytes);
-    n_launched += (int)ts.size();
-    ctx->inflight.push_back(std::move(b));
+    for (auto& blk : lease->blocks) b.bytes += blk.bytes;  // what the device really holds
+    b.dev = lease.release();
+    return NMC_OK;
   }
-  // back to the front of the queue, in arrival order
-  std::sort(requeue.begin(), requeue.end());
-  for (auto it = requeue.rbegin(); it != requeue.rend(); ++it) ctx->queue.push_front(*it);
-  ctx->stats.queued = ctx->queue.size();
-  if (launched) *launched = n_launched;
-  if (err) return err;
-  if (!requeue.empty() && ctx->inflight.empty())
-    return fail(ctx, NMC_ENOMEM, "serving: a batch does not fit the budget with nothing in flight");
-  return NMC_OK;
+  void release(nmc::ServeBatch& b) override {
+    Lease* l = static_cast<Lease*>(b.dev);
+    for (uint64_t t : b.tickets) {  // the batch waited for these events: complete
+      ServeReq& q = ctx_->sreq.at(t);
+      if (q.ready) ctx_->ev_pool.push_back(q.ready);
+      q.ready = nullptr;
+    }
+    for (auto& blk : l->blocks) ctx_->free_blocks.push_back(blk);
+    (void)hipEventDestroy(l->ev);
+    delete l;
+    b.dev = nullptr;
+  }
+
+ private:
+  nmc_ctx* ctx_;
+};
+
+int serve_tick(nmc_ctx* ctx, int* launched) {
+  HipServeDevice dev(ctx);
+  const int rc = ctx->serve->tick(dev, launched);
+  if (rc == NMC_ENOMEM) return fail(ctx, NMC_ENOMEM, "serving: a batch does not fit the budget with nothing in flight");
+  return rc;
 }
 
 }  // namespace
@@ -1253,7 +1196,7 @@ int nmc_footprint_bytes_flags(int N, int L, nmc_precision p, unsigned flags, siz
   if (!bytes || N < kMinN || N % 4 != 0 || L < 1 || L > kMaxL || (p != NMC_F64 && p != NMC_F32))
     return NMC_EINVAL;
   if (!period_of(N)) return NMC_EUNSUPPORTED;
-  if (max_period(N, L, flags) > kMaxP) return NMC_EUNSUPPORTED;
+  if (max_period(N, L, flags) > kMaxScaledP) return NMC_EUNSUPPORTED;
   *bytes = make_layout(N, L, p, flags).total;
   return NMC_OK;
 }
@@ -1270,7 +1213,7 @@ int nmc_create(nmc_ctx** out, int hip_device, size_t hbm_budget_bytes) {
   auto* ctx = new nmc_ctx();
   ctx->device = hip_device;
   ctx->budget = hbm_budget_bytes;
-  ctx->stats.budget_bytes = hbm_budget_bytes;
+  ctx->serve = std::make_unique<nmc::ServeCore>(hbm_budget_bytes, kMaxBatchRequests);
   if (hipSetDevice(hip_device) != hipSuccess) {
     delete ctx;
     return NMC_EDEVICE;
@@ -1303,8 +1246,15 @@ void nmc_destroy(nmc_ctx* ctx) {
   reap_leases(ctx, false);
   while (!ctx->graphs.empty()) drop_graph(ctx, ctx->graphs.begin());
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-  for (auto& b : ctx->inflight)
-    for (auto& blk : b.lease.blocks) (void)hipFree(blk.ptr);
+  if (ctx->serve) {
+    for (const auto& b : ctx->serve->inflight()) {
+      Lease* l = static_cast<Lease*>(b.dev);
+      if (!l) continue;
+      for (auto& blk : l->blocks) (void)hipFree(blk.ptr);
+      if (l->ev) (void)hipEventDestroy(l->ev);
+      delete l;
+    }
+  }
   for (auto& l : ctx->leases)
     for (auto& blk : l.blocks) (void)hipFree(blk.ptr);
   for (auto& b : ctx->free_blocks) (void)hipFree(b.ptr);
@@ -1318,7 +1268,7 @@ void nmc_destroy(nmc_ctx* ctx) {
     (void)hipFree(kv.second.gz32);
     (void)hipFree(kv.second.gn32);
   }
-  for (auto& kv : ctx->items)
+  for (auto& kv : ctx->sreq)
     if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (auto& s : ctx->streams) (void)hipStreamDestroy(s);
@@ -1475,11 +1425,8 @@ int nmc_serve_submit(nmc_ctx* ctx, const nmc_request* req, void* hip_stream, uin
     ctx->ev_pool.push_back(ev);
     return hip_fail(ctx, e, "serving: record on the submitting stream");
   }
-  const uint64_t t = ctx->next_ticket++;
-  ctx->items[t] = ServeItem{r, bytes, 0, ev};
-  ctx->queue.push_back(t);
-  ctx->stats.submitted++;
-  ctx->stats.queued = ctx->queue.size();
+  const uint64_t t = ctx->serve->submit(nmc::ServeKey{r.N, (int)r.p, method_of(r.flags)}, bytes);
+  ctx->sreq[t] = ServeReq{r, ev};
   *ticket = t;
   return NMC_OK;
 }
@@ -1493,13 +1440,13 @@ int nmc_serve_tick(nmc_ctx* ctx, int* launched) {
 
 int nmc_serve_poll(nmc_ctx* ctx, uint64_t ticket, int* done) {
   if (!ctx || !done) return NMC_EINVAL;
-  auto it = ctx->items.find(ticket);
-  if (it == ctx->items.end()) return fail(ctx, NMC_EINVAL, "unknown ticket");
-  if (it->second.state != 2) {
+  const nmc::ServeCore::Item* it = ctx->serve->find(ticket);
+  if (!it) return fail(ctx, NMC_EINVAL, "unknown ticket");
+  if (it->state != nmc::ServeCore::kDone) {
     int rc = nmc_serve_tick(ctx, nullptr);
     if (rc) return rc;
   }
-  *done = ctx->items[ticket].state == 2 ? 1 : 0;
+  *done = ctx->serve->find(ticket)->state == nmc::ServeCore::kDone ? 1 : 0;
   return NMC_OK;
 }
 
@@ -1507,20 +1454,15 @@ int nmc_serve_take_completed(nmc_ctx* ctx, uint64_t* out, int cap, int* n) {
   if (!ctx || !n || cap < 0 || (cap > 0 && !out)) return NMC_EINVAL;
   int rc = nmc_serve_tick(ctx, nullptr);
   if (rc) return rc;
-  int k = 0;
-  while (k < cap && !ctx->completed.empty()) {
-    const uint64_t t = ctx->completed.front();
-    ctx->completed.pop_front();
-    out[k++] = t;
-    ctx->items.erase(t);
-  }
+  const int k = ctx->serve->take_completed(out, cap);
+  for (int i = 0; i < k; ++i) ctx->sreq.erase(out[i]);
   *n = k;
   return NMC_OK;
 }
 
 int nmc_serve_stats_get(nmc_ctx* ctx, nmc_serve_stats* out) {
   if (!ctx || !out) return NMC_EINVAL;
-  *out = ctx->stats;
+  *out = ctx->serve->stats();
   out->budget_bytes = ctx->budget;
   out->green_cache_bytes = ctx->green_bytes;
   return NMC_OK;
@@ -1530,9 +1472,10 @@ int nmc_serve_drain(nmc_ctx* ctx) {
   if (!ctx) return NMC_EINVAL;
   int rc = set_device(ctx);
   if (rc) return rc;
-  while (!ctx->queue.empty() || !ctx->inflight.empty()) {
+  while (!ctx->serve->idle()) {
     if ((rc = serve_tick(ctx, nullptr))) return rc;
-    if (!ctx->inflight.empty()) NMC_HIP(ctx, hipEventSynchronize(ctx->inflight.front().lease.ev));
+    if (const nmc::ServeBatch* b = ctx->serve->oldest_inflight())
+      NMC_HIP(ctx, hipEventSynchronize(static_cast<const Lease*>(b->dev)->ev));
   }
   return serve_tick(ctx, nullptr);
 }
