@@ -93,8 +93,8 @@ enum {
    * masses convolved on the doubled grid (2N cells of level l+1's spacing
    * spanning level l, period 2P) and averaged over the 2^3 doubled cells of
    * each level-l cell + the coarser hole potentials carried down as in
-   * Eq. 14; the finest level is unchanged.  Needs 2P <= 512 (N <= 128) and
-   * a larger workspace (nmc_footprint_bytes_flags). */
+   * Eq. 14; the finest level is unchanged.  Needs 2P <= 1024 (every N up to
+   * 256) and a larger workspace (nmc_footprint_bytes_flags). */
   NMC_MODIFIED = 1u << 6,
   /* The modified method with Appendix B's scheme for dipoles across three
    * neighbouring grids (implies NMC_MODIFIED): every level l with two finer
@@ -102,7 +102,7 @@ enum {
    * zeroed on the doubled grid + level l+2's density on a quadrupled grid
    * (4N cells of level l+2's spacing spanning level l, period 4P, averaged
    * over the 4^3 cells of each level-l cell) + the carry; the two finest
-   * levels as with NMC_MODIFIED.  Needs 4P <= 512 (N <= 64) when L >= 3. */
+   * levels as with NMC_MODIFIED.  Needs 4P <= 1024 (N <= 128) when L >= 3. */
   NMC_MODIFIED3 = 1u << 7
 };
 
@@ -131,8 +131,8 @@ int nmc_footprint_bytes(int N, int L, nmc_precision p, size_t* bytes);
 
 /* The same for a solve with these flags (NMC_MODIFIED adds the doubled
  * grids' FFT buffers, NMC_MODIFIED3 also the quadrupled grids').  Errors:
- * NMC_EINVAL, NMC_EUNSUPPORTED (also for NMC_MODIFIED with N above 128 and
- * NMC_MODIFIED3 with N above 64 and L >= 3). */
+ * NMC_EINVAL, NMC_EUNSUPPORTED (also for NMC_MODIFIED3 with N above 128
+ * and L >= 3). */
 int nmc_footprint_bytes_flags(int N, int L, nmc_precision p, unsigned flags, size_t* bytes);
 
 /* Solve one nested mesh (Sect. 4, Eq. 14).

@@ -12,5 +12,6 @@ from .nested import (BETA, cell_centres, child_region, green_periodic, hole,  # 
                      kernel_value, level_spacing, potential_at, potential_direct,
                      potential_fft, prolong, prolong_trilinear, restrict_cascade,
                      solve, solve_points, acceleration,
-                     doubled_potential, quadrupled_potential, solve_modified)
+                     doubled_potential, quadrupled_potential, scaled_potential_at,
+                     solve_modified)
 from . import analytic  # noqa: F401

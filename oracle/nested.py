@@ -322,6 +322,34 @@ def quadrupled_potential(mass_fine: np.ndarray, h_fine: float, G: float = 1.0, m
     return Pq.reshape(N, 4, N, 4, N, 4).mean(axis=(1, 3, 5))
 
 
+def scaled_potential_at(mass_fine: np.ndarray, h_fine: float, S: int, cells, G: float = 1.0) -> np.ndarray:
+    """The reduced potential of a scaled grid at selected coarse cells, by
+    direct summation (the point form of doubled_potential, S = 2, and
+    quadrupled_potential, S = 4; readings R18, R20): the fine masses sit at
+    cells [(S-1) N/2, (S+1) N/2) per axis of a grid of S N cells of the fine
+    spacing spanning the coarse level, and coarse cell c = (z, y, x) takes
+    the mean of Eq. (10) over its S^3 fine cells S c + (0..S-1)^3."""
+    N = mass_fine.shape[0]
+    off = (S - 1) * N // 2
+    nz = np.nonzero(mass_fine)
+    m = mass_fine[nz]
+    sz, sy, sx = (a.astype(np.float64) + off for a in nz)
+    out = np.empty(len(cells), dtype=np.float64)
+    for k, (z, y, x) in enumerate(np.asarray(cells)):
+        acc = 0.0
+        for oz in range(S):
+            for oy in range(S):
+                for ox in range(S):
+                    tz, ty, tx = S * z + oz, S * y + oy, S * x + ox
+                    r2 = (sz - tz) ** 2 + (sy - ty) ** 2 + (sx - tx) ** 2
+                    with np.errstate(divide="ignore"):
+                        gv = 1.0 / np.sqrt(r2)
+                    gv[r2 == 0] = BETA
+                    acc += float(np.dot(gv, m))
+        out[k] = -(G / h_fine) * acc / S ** 3
+    return out
+
+
 def solve_modified(rho: np.ndarray, h0: float, G: float = 1.0, *, restrict: bool = True,
                    method: str = "fft", scheme: str = "pairs", trilinear: bool = False) -> np.ndarray:
     """The modified convolution method that keeps the dipole moments across
@@ -367,13 +395,20 @@ def solve_modified(rho: np.ndarray, h0: float, G: float = 1.0, *, restrict: bool
 
 
 def solve_points(rho: np.ndarray, h0: float, pts, G: float = 1.0, *, restrict: bool = True,
-                 trilinear: bool = False) -> np.ndarray:
+                 trilinear: bool = False, scheme: str = "original") -> np.ndarray:
     """Phi(Omega^(l+1)) at selected cells pts[k] = (l, z, y, x), each by
     direct summation of Eq. (10) on every grid involved and the same carry
     rule as solve() (for spot checks at sizes where the full oracle is slow).
     The carry is written out per cell here (parent and neighbour per axis),
     independently of prolong() / prolong_trilinear().
-    """
+
+    scheme "pairs" / "triples" gives solve_modified's levels instead: a
+    level with a finer one takes its hole potential plus the reduced
+    doubled-grid potential of the next level (with that level's child
+    region zeroed when a quadrupled grid of the level after it is added,
+    "triples"), by scaled_potential_at; the carry is the same."""
+    if scheme not in ("original", "pairs", "triples"):
+        raise ValueError("scheme must be 'original', 'pairs' or 'triples'")
     rho = np.asarray(rho, dtype=np.float64)
     L, N = rho.shape[0], rho.shape[1]
     rr = restrict_cascade(rho) if restrict else rho
@@ -413,9 +448,21 @@ def solve_points(rho: np.ndarray, h0: float, pts, G: float = 1.0, *, restrict: b
             v += carry(m, p)
         return v
 
+    def level_value(l, p):
+        if scheme == "original" or l == L - 1:
+            return phi_grid(l, False, p)
+        hf = level_spacing(h0, l + 1)
+        triple = scheme == "triples" and l < L - 2
+        fine = rr[l + 1] * hf ** 3
+        v = phi_grid(l, True, p) + scaled_potential_at(hole(fine) if triple else fine, hf, 2, [p], G)[0]
+        if triple:
+            hq = level_spacing(h0, l + 2)
+            v += scaled_potential_at(rr[l + 2] * hq ** 3, hq, 4, [p], G)[0]
+        return v
+
     res = []
     for (l, z, y, x) in pts:
-        v = phi_grid(l, False, (z, y, x))
+        v = level_value(l, (z, y, x))
         if l > 0:
             v += carry(l, (z, y, x))
         res.append(v)

@@ -38,43 +38,52 @@ __device__ __forceinline__ T c_mul_tw(T a, T w) {
   else return T{a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
 }
 
-// cos and sin of 2 pi j / 16 for j = 0..15 (exact decimal expansions,
+// cos and sin of 2 pi j / 32 for j = 0..31 (exact decimal expansions,
 // rounded once to the working precision).
-struct Angle16 {
-  static constexpr double c[16] = {
-      1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
-      0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
-      -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
-      0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
-  static constexpr double s[16] = {
-      0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
-      1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
-      0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
-      -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+struct Angle32 {
+  static constexpr double c[32] = {
+      1.0, 0.9807852804032304491262, 0.9238795325112867561282, 0.8314696123025452370788,
+      0.7071067811865475244008, 0.5555702330196022247428, 0.3826834323650897717285, 0.1950903220161282678483,
+      0.0, -0.1950903220161282678483, -0.3826834323650897717285, -0.5555702330196022247428,
+      -0.7071067811865475244008, -0.8314696123025452370788, -0.9238795325112867561282, -0.9807852804032304491262,
+      -1.0, -0.9807852804032304491262, -0.9238795325112867561282, -0.8314696123025452370788,
+      -0.7071067811865475244008, -0.5555702330196022247428, -0.3826834323650897717285, -0.1950903220161282678483,
+      0.0, 0.1950903220161282678483, 0.3826834323650897717285, 0.5555702330196022247428,
+      0.7071067811865475244008, 0.8314696123025452370788, 0.9238795325112867561282, 0.9807852804032304491262};
+  static constexpr double s[32] = {
+      0.0, 0.1950903220161282678483, 0.3826834323650897717285, 0.5555702330196022247428,
+      0.7071067811865475244008, 0.8314696123025452370788, 0.9238795325112867561282, 0.9807852804032304491262,
+      1.0, 0.9807852804032304491262, 0.9238795325112867561282, 0.8314696123025452370788,
+      0.7071067811865475244008, 0.5555702330196022247428, 0.3826834323650897717285, 0.1950903220161282678483,
+      0.0, -0.1950903220161282678483, -0.3826834323650897717285, -0.5555702330196022247428,
+      -0.7071067811865475244008, -0.8314696123025452370788, -0.9238795325112867561282, -0.9807852804032304491262,
+      -1.0, -0.9807852804032304491262, -0.9238795325112867561282, -0.8314696123025452370788,
+      -0.7071067811865475244008, -0.5555702330196022247428, -0.3826834323650897717285, -0.1950903220161282678483};
 };
 
-// a * exp(DIR * 2 pi i K / RR) for compile-time K/RR with RR | 16.
+// a * exp(DIR * 2 pi i K / RR) for compile-time K/RR with RR | 32.
 template <int DIR, int K, int RR, class T>
 __device__ __forceinline__ T c_rot(T a) {
   using R = decltype(a.x);
-  constexpr int j0 = ((K % RR) + RR) % RR * (16 / RR);
-  constexpr int j = DIR < 0 ? (16 - j0) % 16 : j0;  // angle 2 pi j / 16
+  static_assert(RR >= 1 && 32 % RR == 0, "rotation by a 32nd of a turn");
+  constexpr int j0 = ((K % RR) + RR) % RR * (32 / RR);
+  constexpr int j = DIR < 0 ? (32 - j0) % 32 : j0;  // angle 2 pi j / 32
   if constexpr (j == 0) return a;
-  else if constexpr (j == 4) return T{-a.y, a.x};   // * i
-  else if constexpr (j == 8) return T{-a.x, -a.y};  // * -1
-  else if constexpr (j == 12) return T{a.y, -a.x};  // * -i
-  else if constexpr (j == 2) { constexpr R h = (R)Angle16::c[2]; return T{(a.x - a.y) * h, (a.x + a.y) * h}; }
-  else if constexpr (j == 6) { constexpr R h = (R)Angle16::c[2]; return T{-(a.x + a.y) * h, (a.x - a.y) * h}; }
-  else if constexpr (j == 10) { constexpr R h = (R)Angle16::c[2]; return T{(a.y - a.x) * h, -(a.x + a.y) * h}; }
-  else if constexpr (j == 14) { constexpr R h = (R)Angle16::c[2]; return T{(a.x + a.y) * h, (a.y - a.x) * h}; }
+  else if constexpr (j == 8) return T{-a.y, a.x};   // * i
+  else if constexpr (j == 16) return T{-a.x, -a.y};  // * -1
+  else if constexpr (j == 24) return T{a.y, -a.x};  // * -i
+  else if constexpr (j == 4) { constexpr R h = (R)Angle32::c[4]; return T{(a.x - a.y) * h, (a.x + a.y) * h}; }
+  else if constexpr (j == 12) { constexpr R h = (R)Angle32::c[4]; return T{-(a.x + a.y) * h, (a.x - a.y) * h}; }
+  else if constexpr (j == 20) { constexpr R h = (R)Angle32::c[4]; return T{(a.y - a.x) * h, -(a.x + a.y) * h}; }
+  else if constexpr (j == 28) { constexpr R h = (R)Angle32::c[4]; return T{(a.x + a.y) * h, (a.y - a.x) * h}; }
   else {
-    constexpr R c = (R)Angle16::c[j];
-    constexpr R s = (R)Angle16::s[j];
+    constexpr R c = (R)Angle32::c[j];
+    constexpr R s = (R)Angle32::s[j];
     return T{a.x * c - a.y * s, a.x * s + a.y * c};
   }
 }
 
-// In-register DFT of length RR (power of two <= 16) by radix-2 decimation in
+// In-register DFT of length RR (power of two <= 32) by radix-2 decimation in
 // time; inputs with index >= NZ are taken as zero and never read, and only
 // the outputs below NOUT (RR or RR/2) are formed.
 // DIR = -1: forward exp(-2 pi i jk/RR); DIR = +1: inverse (unnormalised).
@@ -239,6 +248,8 @@ template <int P> struct WidePlan;
 template <> struct WidePlan<128> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8>(); } };
 template <> struct WidePlan<256> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 16>(); } };
 template <> struct WidePlan<512> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<8, 8, 8>(); } };
+// period 1024 (the scaled grids of the modified methods, their Green tables)
+template <> struct WidePlan<1024> { static constexpr int E = 16; template <class F> __device__ static void run(F f) { f.template go<16, 8, 8>(); } };
 
 #ifndef NMC_WIDE_PASSES_F64
 #define NMC_WIDE_PASSES_F64 ((1 << kPassY) | (1 << kPassZ))
@@ -249,7 +260,8 @@ template <> struct WidePlan<512> { static constexpr int E = 16; template <class 
 // precisions, so that the fold leaves at least 4 points per thread there.
 template <class R, int P, int K>
 constexpr bool wide_plan() {
-  if constexpr (K == kPassZScaled) return P >= 128;
+  if constexpr (P >= 1024) return true;  // 16 points per thread: a line within one wavefront
+  else if constexpr (K == kPassZScaled) return P >= 128;
   else if constexpr (sizeof(R) == 4) return P >= 128 && ((NMC_WIDE_PASSES >> K) & 1) != 0;
   else return P >= 128 && P <= 256 && ((NMC_WIDE_PASSES_F64 >> K) & 1) != 0;
 }

@@ -43,6 +43,17 @@ namespace nmc {
 #ifndef NMC_MIN_WAVES_F64_WIDE
 #define NMC_MIN_WAVES_F64_WIDE 1
 #endif
+// FP32 z pass at P = 512 through staged tiles (k_zs) and its resident waves
+// per SIMD
+#ifndef NMC_Z_STAGED
+#define NMC_Z_STAGED 1
+#endif
+#ifndef NMC_ZS_MINW_F64
+#define NMC_ZS_MINW_F64 2
+#endif
+#ifndef NMC_ZS_MINW_F32
+#define NMC_ZS_MINW_F32 4
+#endif
 template <class R, int P, int K>
 struct Cfg {
   static constexpr int E = Plan<R, P, K>::E;
@@ -569,6 +580,271 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
       const int zz = t + TL * q;
       if (owner && zz < Nl) B[(size_t)zz * ZS] = u[q];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Z pass at P = 512 through staged tiles (level grids; used for FP32, where
+// it runs the 256^3 x 6 launch in 1.72 ms against k_z's 1.81 ms; for FP64
+// its 220 registers leave two wavefronts per SIMD and k_z stays faster,
+// 3.47 against 3.73 ms).
+//
+// A grid's z rows are 2 MB apart (one z row of B holds P (P/2) values), and
+// what HBM delivers for such rows depends on the contiguous run each memory
+// instruction covers: a plain read and write of B on the GPU moves 2.7 TB/s
+// with 64-byte runs (k_z's: 4 FP64 or 8 FP32 adjacent columns per lane group),
+// 4.0 TB/s with 128-byte runs and 5.0 TB/s with 256-byte runs.  Here a
+// workgroup first stages the tile [row ky, -ky][z][CS columns] through LDS
+// with 128-byte runs, then each wavefront transforms four whole lines with
+// 32 points per lane: radix 16 then radix 32, one exchange per transform,
+// through LDS rows of its own in the same space (no workgroup barrier between
+// the staging steps).  The results leave through the tile the same way.
+// Wavefront j owns columns 4 (j % (NW/2)) + w of the tile in row ky = p
+// (j < NW/2) or -p (-0 is row P/2); lane (w, t) = (lane % 4, lane / 4)
+// holds the points kz = t + 16 q, q = 0..31.  Tile 0 (with column kx = 0,
+// which packs the real DC and Nyquist planes) is left to a launch of its own
+// (COL0), where the two rows' column-0 lines meet after the forward
+// transform.
+namespace zs {
+constexpr int P = 512, E = 32, TL = 16, LW = 4;
+constexpr int ROWS = P + P / 16;  // exchange rows of a wavefront: a padding row after every 16 points
+template <class R>
+struct Geo {
+  static constexpr int CS = 128 / (2 * (int)sizeof(R));  // columns per row: one 128-byte run
+  static constexpr int NW = 2 * CS / LW;                  // wavefronts (both rows, four lines each)
+  static constexpr int NT = 64 * NW;
+  static constexpr int TILES = (P / 2) / CS;
+  static constexpr int UNITS = (P / 2) * TILES;           // (row pair p, tile) per grid
+  static constexpr int XM = CS / LW - 1;                   // column swizzle of the tile by z
+  static constexpr int ZR = NT / (2 * CS);                // z rows per staging round
+  static constexpr int TILE_BYTES = 2 * (P / 2) * CS * 2 * (int)sizeof(R);
+  static constexpr int EX_BYTES = NW * ROWS * LW * (int)sizeof(R);
+  static constexpr int LDS = TILE_BYTES > EX_BYTES ? TILE_BYTES : EX_BYTES;
+  static_assert(ZR == 16, "staging rounds of 16 z rows");
+};
+}  // namespace zs
+
+// Makes this wavefront's LDS writes visible to all its lanes and keeps the
+// compiler from moving LDS accesses across it (every lane reaches it).
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// w^i, i = 0..31, for w = exp(-2 pi i t / 512) (the table entry t; DIR = +1
+// uses the conjugates): w^(8a + b) = w^(8a) w^b, with w^b (b < 8) products
+// of at most three table values and w^(8a) from the table.  Applied to u[i]
+// in place.  The lane index is made opaque first, so that each transform
+// forms its own (cheap) instead of holding the forward's across the multiply.
+template <int DIR, class R>
+__device__ __forceinline__ void zs_twiddle(cplx<R>* u, int t, const cplx<R>* __restrict__ tw) {
+  using T = cplx<R>;
+  auto mul = [](T a, T b) { return T{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; };
+  asm volatile("" : "+v"(t));
+  T p[8];
+  p[1] = tw[t];
+  p[2] = mul(p[1], p[1]);
+  p[3] = mul(p[1], p[2]);
+  p[4] = mul(p[2], p[2]);
+  p[5] = mul(p[1], p[4]);
+  p[6] = mul(p[2], p[4]);
+  p[7] = mul(p[3], p[4]);
+#pragma unroll
+  for (int b = 1; b < 8; ++b) u[b] = c_mul_tw<DIR>(u[b], p[b]);
+#pragma unroll
+  for (int a = 1; a < 4; ++a) {
+    const T wa = tw[(8 * a * t) & (zs::P - 1)];
+    u[8 * a] = c_mul_tw<DIR>(u[8 * a], wa);
+#pragma unroll
+    for (int b = 1; b < 8; ++b) u[8 * a + b] = c_mul_tw<DIR>(u[8 * a + b], mul(wa, p[b]));
+  }
+}
+
+// The exchange between the two stages: slot s = 16 m + i of this lane holds
+// point n = 16 (t + 16 m) + i of its line; afterwards slot q holds point
+// t + 16 q.  Point n lives in row n + n / 16 of `ex` (this wavefront's
+// ROWS x LW values); one component at a time, every address a lane base
+// plus a constant.
+template <class R>
+__device__ __forceinline__ void zs_exchange(cplx<R>* v, R* ex, int w, int t) {
+  using namespace zs;
+  R tmp[E];
+  R* const wb = ex + (17 * t) * LW + w;  // row of n = 16 t + 256 m + i: 17 t + 272 m + i
+  R* const rb = ex + (t + (t >> 4)) * LW + w;  // row of t + 16 q: t + 17 q (t < 16)
+#pragma unroll
+  for (int s = 0; s < E; ++s) wb[(272 * (s / 16) + s % 16) * LW] = v[s].x;
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < E; ++q) tmp[q] = rb[17 * q * LW];
+  wave_lds_sync();
+#pragma unroll
+  for (int s = 0; s < E; ++s) wb[(272 * (s / 16) + s % 16) * LW] = v[s].y;
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[q] = cplx<R>{tmp[q], rb[17 * q * LW]};
+  wave_lds_sync();
+}
+
+// One transform of a line held as v[q] = x[t + 16 q] (natural order out, in
+// the same slots).  Forward: inputs q >= 16 are zero (PIN).  Inverse: only
+// the outputs q < 16 are formed (POUT).  Stockham stages: radix 16 over the
+// butterflies b = t + 16 m (inputs x[b + 32 i] = slot m + 2 i, outputs
+// y[16 b + i]), then radix 32 over b = t (inputs y[t + 16 i], twiddles w^i
+// with w = exp(-+2 pi i t / 512), outputs x[t + 16 i]).
+template <int DIR, class R>
+__device__ __forceinline__ void zs_fft(cplx<R>* v, R* ex, int w, int t, const cplx<R>* __restrict__ tw) {
+  using T = cplx<R>;
+  constexpr bool PIN = DIR < 0, POUT = DIR > 0;
+  T y[zs::E];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    T u[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (!PIN || i < 8) u[i] = v[m + 2 * i];
+    dft<16, DIR, PIN ? 8 : 16>(u);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) y[16 * m + i] = u[i];
+  }
+  zs_exchange<R>(y, ex, w, t);
+  zs_twiddle<DIR, R>(y, t, tw);
+  dft<32, DIR, 32, POUT ? 16 : 32>(y);
+#pragma unroll
+  for (int q = 0; q < (POUT ? 16 : 32); ++q) v[q] = y[q];
+}
+
+template <class R, bool FULLN, bool COL0>
+__device__ __forceinline__ void zs_tile(const FieldTable& ft, const PassGeom& g, const Tables<R>& tb, int f, int p,
+                                        int tl, char* lds) {
+  using namespace zs;
+  using G = Geo<R>;
+  using T = cplx<R>;
+  constexpr int CS = G::CS, NW = G::NW, XM = G::XM, ZR = G::ZR;
+  constexpr int H = P / 2 + 1, W = Cfg<R, P, kPassZ>::WZ, NTL = (P / 2) / W;  // spectrum layout tiles
+  T* const tile = reinterpret_cast<T*>(lds);  // [side][z][column ^ swizzle]
+  const int lane = threadIdx.x % 64, j = threadIdx.x / 64;
+  const int w = lane % LW, t = lane / LW;
+  const FieldDesc& F = ft.f[f];
+  const bool full_in = FULLN && F.kind != 1;
+  const bool full = FULLN && F.kind == 0;
+  const GridGeo gg = grid_geo<false>(F.kind, FULLN ? P / 2 : g.N);
+  const int n = gg.nin;
+  auto row_of = [&](int side) { return side == 0 ? p : (p == 0 ? P / 2 : P - p); };
+  constexpr unsigned ZS = (unsigned)(P * (P / 2) * sizeof(T));  // bytes between z rows of B
+  char* const B = static_cast<char*>(F.B);
+  // staging lanes: column c, z rows zr + 16 k, row `sside` of the pair
+  const int c = threadIdx.x % CS, zr = (threadIdx.x / CS) % ZR, sside = threadIdx.x / (CS * ZR);
+  const unsigned gb = (unsigned)((row_of(sside) * (P / 2) + tl * CS + c) * sizeof(T)) + (unsigned)zr * ZS;
+  T* const st = tile + (sside * (P / 2) + zr) * CS + (c ^ ((zr & XM) << 2));
+#pragma unroll
+  for (int k = 0; k < (P / 2) / ZR; ++k) {
+    const int z = zr + ZR * k;
+    T val = T{0, 0};
+    if (full_in || z < n) val = *reinterpret_cast<const T*>(B + gb + (unsigned)k * ZR * ZS);
+    st[k * ZR * CS] = val;
+  }
+  __syncthreads();
+  // this wavefront's four lines: row `side`, tile columns 4 q4 + w
+  const int side = j / (NW / 2), q4 = j % (NW / 2);
+  const int col = 4 * q4 + w, kx = tl * CS + col;
+  const int ky = row_of(side), kyp = ky <= P / 2 ? ky : P - ky;
+  T v[E];
+  {
+    const T* const rt = tile + (side * (P / 2) + t) * CS + (col ^ ((t & XM) << 2));
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) v[q] = rt[q * TL * CS];
+#pragma unroll
+    for (int q = E / 2; q < E; ++q) v[q] = T{0, 0};
+  }
+  __syncthreads();  // the tile's space is the wavefronts' exchange rows from here
+  R* const ex = reinterpret_cast<R*>(lds) + j * ROWS * LW;
+  // spectrum of this lane's points: row kz = t + 16 q for q < 16, and
+  // P - kz = (P - t) - 16 q from q = 16 on
+  const char* const gz = reinterpret_cast<const char*>(tb.gz);
+  const unsigned goff = (unsigned)(((kyp * NTL + kx / W) * H * W + kx % W) * sizeof(R));
+  const unsigned glo = goff + (unsigned)(t * W * sizeof(R)), ghi = goff + (unsigned)((P - t) * W * sizeof(R));
+  auto spectrum = [&](int q) {
+    constexpr unsigned RS = TL * W * sizeof(R);  // bytes per 16 spectrum rows
+    return *reinterpret_cast<const R*>(gz + (q < E / 2 ? glo + q * RS : ghi - q * RS));
+  };
+  zs_fft<-1, R>(v, ex, w, t, tb.tw);
+  const R sc = (R)F.scale;
+  if constexpr (!COL0) {
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const R gv = sc * spectrum(q);
+      v[q] = T{v[q].x * gv, v[q].y * gv};
+    }
+  } else {
+    // kx = 0 holds U + iV (U, V: spectra of the real DC and Nyquist planes);
+    // with Cm = conj(value at (-ky, -kz)): U = (C + Cm)/2, V = (C - Cm)/(2i),
+    // and the product g0 U + i gN V is (g0 + gN)/2 C + (g0 - gN)/2 Cm.  The
+    // rows' column-0 lines (lane w = 0 of wavefronts 0 and NW/2) meet in
+    // wavefront 0's exchange rows; row -ky is the other one, or the same
+    // for p = 0 (rows 0 and P/2 are their own negatives).
+    R* const c0 = reinterpret_cast<R*>(lds);  // [side][component][kz]
+    __syncthreads();  // every forward transform is done with its rows
+    if (kx == 0) {
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        c0[(2 * side) * P + t + TL * q] = v[q].x;
+        c0[(2 * side + 1) * P + t + TL * q] = v[q].y;
+      }
+    }
+    __syncthreads();
+    if (kx == 0) {
+      const int ps = p == 0 ? side : 1 - side;
+      const R* gn = tb.gn + (size_t)kyp * H;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int kz = t + TL * q, nkz = (P - kz) & (P - 1);
+        const T cm = T{c0[(2 * ps) * P + nkz], -c0[(2 * ps + 1) * P + nkz]};
+        const R g0 = spectrum(q), gnv = gn[kz <= P / 2 ? kz : P - kz];
+        const R a = sc * (R)0.5 * (g0 + gnv), b = sc * (R)0.5 * (g0 - gnv);
+        v[q] = T{a * v[q].x + b * cm.x, a * v[q].y + b * cm.y};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const R gv = sc * spectrum(q);
+        v[q] = T{v[q].x * gv, v[q].y * gv};
+      }
+    }
+    __syncthreads();  // wavefront 0's rows are its exchange rows again
+  }
+  zs_fft<+1, R>(v, ex, w, t, tb.tw);
+  __syncthreads();  // every inverse transform is done with its rows
+  {
+    T* const wt = tile + (side * (P / 2) + t) * CS + (col ^ ((t & XM) << 2));
+#pragma unroll
+    for (int q = 0; q < E / 2; ++q) wt[q * TL * CS] = v[q];
+  }
+  __syncthreads();
+  unsigned sb = gb;
+  asm volatile("" : "+v"(sb));  // not kept across the transforms
+#pragma unroll
+  for (int k = 0; k < (P / 2) / ZR; ++k) {
+    const int z = zr + ZR * k;
+    if (full || (z >= gg.olo && z < gg.olo + gg.nout))
+      *reinterpret_cast<T*>(B + sb + (unsigned)k * ZR * ZS) = st[k * ZR * CS];
+  }
+}
+
+// One launch: the first P/2 nf workgroups take the tiles 0 (with column
+// kx = 0), the others the tiles 1.. of their unit (tile 0's exit at once).
+// The two paths are separate instances, so the column-0 exchange costs the
+// other tiles no registers.
+template <class R, bool FULLN>
+__global__ void __launch_bounds__(zs::Geo<R>::NT, (sizeof(R) == 8 ? NMC_ZS_MINW_F64 : NMC_ZS_MINW_F32))
+k_zs(FieldTable ft, PassGeom g, Tables<R> tb) {
+  using G = zs::Geo<R>;
+  __shared__ __align__(16) char lds[G::LDS];
+  const int c0_blocks = (zs::P / 2) * g.nf;  // a multiple of 8: the others keep their XCD (z_unit)
+  if ((int)blockIdx.x >= c0_blocks) {
+    int unit, f;
+    z_unit(blockIdx.x - c0_blocks, G::UNITS, g.nf, 1, unit, f);
+    const int tl = unit % G::TILES;
+    if (tl == 0) return;  // whole workgroup
+    zs_tile<R, FULLN, false>(ft, g, tb, f, unit / G::TILES, tl, lds);
+  } else {
+    zs_tile<R, FULLN, true>(ft, g, tb, blockIdx.x / (zs::P / 2), blockIdx.x % (zs::P / 2), 0, lds);
   }
 }
 
@@ -1552,7 +1828,10 @@ static void launch(K kernel, dim3 grid, dim3 block, unsigned shmem, hipStream_t 
   hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, a, b, 0, args...);
 }
 
-template <class F>
+// Periods up to MAXP: 512 for level grids (N <= 256), 1024 where a scaled
+// grid of the modified methods can need it (doubled grids of N = 256,
+// quadrupled grids of N = 128) and for the Green tables of that period.
+template <int MAXP = 512, class F>
 static hipError_t dispatch_p(int P, F&& f) {
   switch (P) {
     case 8: f(std::integral_constant<int, 8>{}); break;
@@ -1562,6 +1841,12 @@ static hipError_t dispatch_p(int P, F&& f) {
     case 128: f(std::integral_constant<int, 128>{}); break;
     case 256: f(std::integral_constant<int, 256>{}); break;
     case 512: f(std::integral_constant<int, 512>{}); break;
+    case 1024:
+      if constexpr (MAXP >= 1024) {
+        f(std::integral_constant<int, 1024>{});
+        break;
+      }
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1577,7 +1862,7 @@ bool x_pairs(int N) {
 template <class R>
 hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
   const bool pairs = x_pairs<R>(g.N);
-  return dispatch_p(g.P, [&](auto pc) {
+  return dispatch_p<1024>(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassX>;
     const int units = pairs ? g.n * g.n / 2 : g.n * g.n;
@@ -1590,7 +1875,8 @@ hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
         return;
       }
     }
-    if (pairs && full) launch(k_fwd_x<R, PP, true, true>, grid, block, 0, s, ft, g, tb);
+    if constexpr (PP > 512) return;  // level grids stop at 512 (the runtime checks)
+    else if (pairs && full) launch(k_fwd_x<R, PP, true, true>, grid, block, 0, s, ft, g, tb);
     else if (pairs) launch(k_fwd_x<R, PP, false, true>, grid, block, 0, s, ft, g, tb);
     else if (full) launch(k_fwd_x<R, PP, true, false>, grid, block, 0, s, ft, g, tb);
     else launch(k_fwd_x<R, PP, false, false>, grid, block, 0, s, ft, g, tb);
@@ -1599,7 +1885,7 @@ hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
 
 template <class R>
 hipError_t launch_fwd_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
-  return dispatch_p(g.P, [&](auto pc) {
+  return dispatch_p<1024>(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassY>;
     dim3 grid(((PP / 2) / C::WS) * g.n, g.nf);
@@ -1609,7 +1895,8 @@ hipError_t launch_fwd_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
         return;
       }
     }
-    if (g.N == PP / 2)
+    if constexpr (PP > 512) return;  // level grids stop at 512
+    else if (g.N == PP / 2)
       launch(k_fwd_y<R, PP, true>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
     else
       launch(k_fwd_y<R, PP, false>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
@@ -1618,7 +1905,7 @@ hipError_t launch_fwd_y(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
 
 template <class R>
 hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t s) {
-  return dispatch_p(g.P, [&](auto pc) {
+  return dispatch_p<1024>(g.P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassZ>;
     constexpr int NT = (PP / 2) / C::WZ;
@@ -1636,11 +1923,22 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
       }
       return;
     }
-    if constexpr (z_col0_split<R, PP, 1>()) grid.x += z_col0_blocks(NT, g.nf);
-    if (g.N == PP / 2)
-      launch(k_z<R, PP, true>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
-    else
-      launch(k_z<R, PP, false>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
+    if constexpr (PP <= 512) {  // level grids stop at 512 (the runtime checks)
+      if constexpr (PP == 512 && sizeof(R) == 4 && NMC_Z_STAGED) {  // FP32 (FP64: k_z measured faster)
+        using G = zs::Geo<R>;
+        const dim3 gs((G::UNITS + PP / 2) * g.nf), bs(G::NT);
+        if (g.N == PP / 2)
+          launch(k_zs<R, true>, gs, bs, 0, s, ft, g, tb);
+        else
+          launch(k_zs<R, false>, gs, bs, 0, s, ft, g, tb);
+        return;
+      }
+      if constexpr (z_col0_split<R, PP, 1>()) grid.x += z_col0_blocks(NT, g.nf);
+      if (g.N == PP / 2)
+        launch(k_z<R, PP, true>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
+      else
+        launch(k_z<R, PP, false>, grid, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
+    }
   });
 }
 
@@ -1690,15 +1988,14 @@ hipError_t launch_inv_y_fold(const FieldTable& ft, PassGeom g, Tables<R> tb, hip
   if ((g.S != 2 && g.S != 4) || g.P < 4 * g.N || g.P / g.S < 8) return hipErrorInvalidValue;
   return dispatch_p(g.P / g.S, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
-    if constexpr (PP <= 256) {
-      using C = Cfg<R, PP, kPassIY>;
-      if (g.S == 2) {
-        dim3 grid((PP / C::WS) * g.N, g.nf);
-        launch(k_inv_y_fold<R, PP, 2>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
-      } else if constexpr (PP <= 128) {
-        dim3 grid((2 * PP / C::WS) * g.N, g.nf);
-        launch(k_inv_y_fold<R, PP, 4>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
-      }
+    // S P <= 1024: doubled grids up to P = 512, quadrupled up to 256
+    using C = Cfg<R, PP, kPassIY>;
+    if (g.S == 2) {
+      dim3 grid((PP / C::WS) * g.N, g.nf);
+      launch(k_inv_y_fold<R, PP, 2>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
+    } else if constexpr (PP <= 256) {
+      dim3 grid((2 * PP / C::WS) * g.N, g.nf);
+      launch(k_inv_y_fold<R, PP, 4>, grid, dim3(C::WS * C::TL), 0, s, ft, g, tb);
     }
   });
 }
@@ -1708,17 +2005,15 @@ hipError_t launch_inv_x_fold(const FieldTable& ft, PassGeom g, Tables<R> tb, hip
   if ((g.S != 2 && g.S != 4) || g.P < 4 * g.N || g.P / g.S < 8) return hipErrorInvalidValue;
   return dispatch_p(g.P / g.S, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
-    if constexpr (PP <= 256) {
-      using C = Cfg<R, PP, kPassIX>;
-      dim3 grid((g.N * g.N / 2 + C::WC - 1) / C::WC, g.nf);
-      const bool tri = ft.f[0].tri != 0;
-      if (g.S == 2) {
-        if (tri) launch(k_inv_x_fold<R, PP, 2, true>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
-        else launch(k_inv_x_fold<R, PP, 2, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
-      } else if constexpr (PP <= 128) {
-        // quadrupled grids add no carry
-        launch(k_inv_x_fold<R, PP, 4, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
-      }
+    using C = Cfg<R, PP, kPassIX>;
+    dim3 grid((g.N * g.N / 2 + C::WC - 1) / C::WC, g.nf);
+    const bool tri = ft.f[0].tri != 0;
+    if (g.S == 2) {
+      if (tri) launch(k_inv_x_fold<R, PP, 2, true>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+      else launch(k_inv_x_fold<R, PP, 2, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
+    } else if constexpr (PP <= 256) {
+      // quadrupled grids add no carry
+      launch(k_inv_x_fold<R, PP, 4, false>, grid, dim3(C::WC * C::TL), 0, s, ft, g, tb);
     }
   });
 }
@@ -1818,7 +2113,7 @@ hipError_t launch_carry(const CarryTable& tab, int count, int N, int n0, hipStre
 
 hipError_t launch_green(int P, double beta, const double2* tw, double* t1, double* t2, double* out,
                         hipStream_t s) {
-  return dispatch_p(P, [&](auto pc) {
+  return dispatch_p<1024>(P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<double, PP, kPassOther>;
     constexpr int H = PP / 2 + 1;
@@ -1833,7 +2128,7 @@ hipError_t launch_green(int P, double beta, const double2* tw, double* t1, doubl
 template <class R>
 size_t green_layout_elems(int P) {
   size_t n = 0;
-  (void)dispatch_p(P, [&](auto pc) {
+  (void)dispatch_p<1024>(P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     n = (size_t)(PP / 2 + 1) * (PP / 2 + 1) * (PP / 2);
   });
@@ -1842,7 +2137,7 @@ size_t green_layout_elems(int P) {
 
 template <class R>
 hipError_t launch_green_layout(int P, const double* octant, R* gz, R* gn, hipStream_t s) {
-  return dispatch_p(P, [&](auto pc) {
+  return dispatch_p<1024>(P, [&](auto pc) {
     constexpr int PP = decltype(pc)::value;
     const size_t n = (size_t)(PP / 2 + 1) * (PP / 2 + 1) * (PP / 2);
     launch(k_green_layout<R, PP>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, octant,

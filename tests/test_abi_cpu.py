@@ -86,18 +86,19 @@ def test_footprint_of_the_modified_method(lib):
     assert fp > nmc.footprint_bytes(N, L, torch.float64)
     assert nmc.footprint_bytes(N, L, torch.float64, 0) == nmc.footprint_bytes(N, L, torch.float64)
     out = ctypes.c_size_t()
-    # the doubled grid's period 2P must stay within 512: N <= 128
+    # doubled period 2P <= 1024: every N up to 256
     assert lib.nmc_footprint_bytes_flags(128, 3, 0, nmc.NMC_MODIFIED, ctypes.byref(out)) == nmc.NMC_OK
-    assert lib.nmc_footprint_bytes_flags(132, 3, 0, nmc.NMC_MODIFIED, ctypes.byref(out)) == nmc.NMC_EUNSUPPORTED
+    assert lib.nmc_footprint_bytes_flags(256, 3, 0, nmc.NMC_MODIFIED, ctypes.byref(out)) == nmc.NMC_OK
+    assert lib.nmc_footprint_bytes_flags(260, 3, 0, nmc.NMC_MODIFIED, ctypes.byref(out)) == nmc.NMC_EUNSUPPORTED
     assert lib.nmc_footprint_bytes_flags(132, 3, 0, 0, ctypes.byref(out)) == nmc.NMC_OK
     # the three-level scheme adds L-2 quadrupled grids of period 4P: A = N^2 (2P)
-    # and B = N (4P) (2P) complex values; 4P <= 512 needs N <= 64 from L = 3
+    # and B = N (4P) (2P) complex values; 4P <= 1024 needs N <= 128 from L = 3
     qdp = (N * N * 2 * P + N * 4 * P * 2 * P) * 16
     fp3 = nmc.footprint_bytes(N, L, torch.float64, nmc.NMC_MODIFIED3)
     assert fp + (L - 2) * qdp <= fp3 < (fp + (L - 2) * qdp) * 1.05
-    assert lib.nmc_footprint_bytes_flags(64, 3, 0, nmc.NMC_MODIFIED3, ctypes.byref(out)) == nmc.NMC_OK
-    assert lib.nmc_footprint_bytes_flags(68, 3, 0, nmc.NMC_MODIFIED3, ctypes.byref(out)) == nmc.NMC_EUNSUPPORTED
-    assert lib.nmc_footprint_bytes_flags(128, 2, 0, nmc.NMC_MODIFIED3, ctypes.byref(out)) == nmc.NMC_OK
+    assert lib.nmc_footprint_bytes_flags(128, 3, 0, nmc.NMC_MODIFIED3, ctypes.byref(out)) == nmc.NMC_OK
+    assert lib.nmc_footprint_bytes_flags(132, 3, 0, nmc.NMC_MODIFIED3, ctypes.byref(out)) == nmc.NMC_EUNSUPPORTED
+    assert lib.nmc_footprint_bytes_flags(256, 2, 0, nmc.NMC_MODIFIED3, ctypes.byref(out)) == nmc.NMC_OK
 
 
 def test_null_context_is_rejected(lib):

@@ -160,12 +160,32 @@ def test_modified_binary128_largest_n(ctx, MOD, binary128_mod, dtype):
     assert np.max(rel_err(got, ref)) < tol_of(dtype)
 
 
-def test_modified_rejects_n_above_128(ctx, MOD):
-    from paper_2301_06763_amd import nmc
-    rho = torch.zeros(2, 132, 132, 132, device="cuda", dtype=torch.float32)
-    with pytest.raises(nmc.NmcError) as e:
-        ctx.solve(rho, 1.0, 1.0, MOD)
-    assert e.value.code == nmc.NMC_EUNSUPPORTED
+def _sampled_cells(N, L, seed):
+    """A few cells per level: inside and outside the child region, next to
+    its faces and at the grid's edge."""
+    rng = np.random.default_rng(seed)
+    base = [(N // 2, N // 2, N // 2), (N // 4 - 1, N // 2, N // 3), (0, N - 1, 5), (3 * N // 4, N // 4, N // 2 + 1)]
+    out = []
+    for l in range(L):
+        cells = base + [tuple(int(v) for v in rng.integers(0, N, 3))]
+        out += [(l,) + c for c in cells]
+    return out
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_modified_pairs_n256_period_1024(ctx, MOD, dtype):
+    """N = 256: the doubled grids have period 1024.  Sampled cells of both
+    levels against the oracle's direct sums of the pairwise scheme (the full
+    oracle would need 1024^3 transforms)."""
+    w = inputs.random_levels(256, 2, seed=1260)
+    rho = w.rho.numpy()
+    pts = _sampled_cells(256, 2, 1261)
+    ref = oracle.solve_points(rho, w.h0, pts, scheme="pairs")
+    got = run(ctx, rho, w.h0, MOD, dtype=dtype)
+    g = np.array([got[p] for p in pts])
+    e = np.abs(g - ref) / np.abs(ref)
+    print(f"N=256 pairs {dtype}: max rel err at {len(pts)} sampled cells {e.max():.3e}", flush=True)
+    assert e.max() < tol_of(dtype)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -243,23 +263,41 @@ def test_modified3_ellipsoid64_largest_n(ctx, MOD3, ellipsoid64_mod3, dtype):
     assert np.max(rel_err(got, ref)) < tol_of(dtype)
 
 
-def test_modified3_rejects_n_above_64(ctx, MOD3):
+def test_modified3_rejects_n_above_128(ctx, MOD3):
     from paper_2301_06763_amd import nmc
-    rho = torch.zeros(3, 68, 68, 68, device="cuda", dtype=torch.float32)
+    rho = torch.zeros(3, 132, 132, 132, device="cuda", dtype=torch.float32)
     with pytest.raises(nmc.NmcError) as e:
         ctx.solve(rho, 1.0, 1.0, MOD3)
     assert e.value.code == nmc.NMC_EUNSUPPORTED
-    ok = torch.zeros(2, 128, 128, 128, device="cuda", dtype=torch.float32)  # two levels: no quadrupled grid
+    ok = torch.zeros(2, 256, 256, 256, device="cuda", dtype=torch.float32)  # two levels: no quadrupled grid
     ctx.solve(ok, 1.0, 1.0, MOD3)
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("n", [32, 64])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_modified3_n128_period_1024(ctx, MOD, MOD3, dtype):
+    """N = 128, three levels: the quadrupled grid has period 1024.  The two
+    finer levels equal the pairwise scheme's; sampled cells of every level
+    against the oracle's direct sums of the three-level scheme."""
+    w = inputs.random_levels(128, 3, seed=1280)
+    rho = w.rho.numpy()
+    pts = _sampled_cells(128, 3, 1281)
+    ref = oracle.solve_points(rho, w.h0, pts, scheme="triples")
+    p3 = run(ctx, rho, w.h0, MOD3, dtype=dtype)
+    p2 = run(ctx, rho, w.h0, MOD, dtype=dtype)
+    assert np.array_equal(p2[1:], p3[1:])
+    g = np.array([p3[p] for p in pts])
+    e = np.abs(g - ref) / np.abs(ref)
+    print(f"N=128 triples {dtype}: max rel err at {len(pts)} sampled cells {e.max():.3e}", flush=True)
+    assert e.max() < tol_of(dtype)
+
+
+@pytest.mark.parametrize("n", [32, 64, 128])
 def test_modified3_close_binary_fig18(ctx, MOD, MOD3, n):
     """Fig. 18, right column, on the GPU path: the pairwise and three-level
     schemes agree on the two finer grids and differ on the coarsest by at
-    most 1.5 % (N = 32) / 0.7 % (N = 64) on the plane through the binary
-    (up to 15 % slack for the unstated placement)."""
+    most 1.5 % (N = 32) / 0.7 % (N = 64) / 0.35 % (N = 128) on the plane
+    through the binary (up to 15 % slack for the unstated placement)."""
     import json
     import os
     with open(os.path.join(os.path.dirname(__file__), "golden", "modified_vs_original.json")) as fh:
@@ -276,6 +314,8 @@ def test_modified3_close_binary_fig18(ctx, MOD, MOD3, n):
     m[c, c, c] = False
     e = np.where(m, np.abs(p2[0] - p3[0]) / np.abs(p3[0]), 0.0)
     plane = 100 * e[:, n // 2, :].max()
+    print(f"N={n}: pairs against triples on the coarsest grid, plane through the pair: {plane:.3f} % "
+          f"(paper: {bound} %)", flush=True)
     assert 0.6 * bound < plane < 1.15 * bound, plane
 
 

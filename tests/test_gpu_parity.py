@@ -87,6 +87,21 @@ def test_random_levels_fp64(ctx, N, L):
     assert np.max(rel_err(got, ref)) < F64_TOL
 
 
+# N in (128, 256) with period 512: the z pass's wavefront kernel with input
+# and output rows below the period's half, child-region boxes, both the
+# one- and two-stream schedules.
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("N,L,flags", [(132, 2, 0), (200, 2, 0), (144, 3, 1 << 4)])
+def test_period512_partial_grids(ctx, dtype, N, L, flags):
+    w = inputs.random_levels(N, L, seed=150 + N + L)
+    rho = w.rho.numpy()
+    ref = oracle.solve(rho, w.h0, G=0.7)
+    got = run(ctx, rho, w.h0, G=0.7, dtype=dtype, flags=flags)
+    e = rel_err(got, ref)
+    print(f"N={N} L={L} {dtype}: max rel err {np.max(e):.3e}", flush=True)
+    assert np.max(e) < (F64_TOL if dtype == torch.float64 else F32_TOL)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_restriction_modes_in_one_batch(ctx, dtype):
     """One group mixing pyramid (L = 3, 4) and cascaded (L = 5, 6)

@@ -523,3 +523,33 @@ def test_triples_keep_the_dipole_across_two_levels():
     exact = pot(c - 2) - pot(c - 1)
     far = np.sqrt(X ** 2 + Y ** 2 + Z ** 2) > 4 * h0
     assert np.max(np.abs(triples[0] - exact)[far]) < 0.05 * np.abs(exact[far]).max()
+
+
+@pytest.mark.parametrize("N", [4, 8])
+def test_scaled_potential_at_is_the_reduced_fft_potential(N):
+    """The point form of the doubled and quadrupled grids (direct sums over
+    the fine masses at the S^3 fine cells of each coarse cell) equals
+    doubled_potential and quadrupled_potential (FFT route) on every cell."""
+    rng = np.random.default_rng(60 + N)
+    mf = rng.random((N, N, N))
+    h = 0.37
+    cells = [(z, y, x) for z in range(N) for y in range(N) for x in range(N)]
+    for S, full in ((2, oracle.doubled_potential(mf, h, G=1.1)), (4, oracle.quadrupled_potential(mf, h, G=1.1))):
+        pt = oracle.scaled_potential_at(mf, h, S, cells, G=1.1)
+        ref = np.array([full[c] for c in cells])
+        assert np.max(np.abs(pt - ref) / np.abs(ref)) < 1e-13
+
+
+@pytest.mark.parametrize("scheme,L", [("pairs", 3), ("triples", 3), ("triples", 4)])
+def test_solve_points_of_the_modified_schemes(scheme, L):
+    """solve_points(scheme=...) (direct sums and the per-cell carry) equals
+    solve_modified (FFT route, prolong) at cells of every level."""
+    N = 8
+    rng = np.random.default_rng(70 + L)
+    rho = rng.random((L, N, N, N))
+    h0 = 0.45
+    pts = [(l, z, y, x) for l in range(L) for (z, y, x) in [(0, 1, 2), (3, 4, 5), (7, 7, 0), (2, 5, 3), (4, 4, 4)]]
+    full = oracle.solve_modified(rho, h0, G=0.9, scheme=scheme)
+    pp = oracle.solve_points(rho, h0, pts, G=0.9, scheme=scheme)
+    ref = np.array([full[p] for p in pts])
+    assert np.max(np.abs(pp - ref) / np.abs(ref)) < 1e-13
