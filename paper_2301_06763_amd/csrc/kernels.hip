@@ -48,6 +48,13 @@ namespace nmc {
 #ifndef NMC_Z_STAGED
 #define NMC_Z_STAGED 1
 #endif
+// FP64 z pass at P = 512 with one-row workgroups (k_z<..., ONE>)
+#ifndef NMC_Z_ONE_ROW
+#define NMC_Z_ONE_ROW 1
+#endif
+#ifndef NMC_Z_ONE_ROW_F32
+#define NMC_Z_ONE_ROW_F32 0
+#endif
 #ifndef NMC_ZS_MINW_F64
 #define NMC_ZS_MINW_F64 2
 #endif
@@ -429,7 +436,12 @@ constexpr bool z_col0_split() { return SC == 1 ? P == 128 && sizeof(R) == 8 : P 
 // so that the other workgroups keep their XCD (blockIdx mod 8, see z_unit).
 __host__ __device__ constexpr int z_col0_blocks(int NT, int nf) { return (NT * nf + 7) / 8 * 8; }
 
-template <class R, int P, bool FULLN, int SC = 1>
+// ONE (level grids): the workgroups other than the column-0 ones own 2 W
+// adjacent columns of a single row instead of W columns of the row pair ky,
+// -ky, so that each memory instruction covers runs of 2 W values: at P = 512
+// FP64 128-byte runs instead of 64-byte ones, with the same LDS tile.  The
+// DC/Nyquist column is then left to the column-0 workgroups.
+template <class R, int P, bool FULLN, int SC = 1, bool ONE = false>
 __global__ void __launch_bounds__((2 * Cfg<R, P, SC == 1 ? kPassZ : kPassZScaled>::WZ *
                                    Cfg<R, P, SC == 1 ? kPassZ : kPassZScaled>::TL),
                                   (Cfg<R, P, SC == 1 ? kPassZ : kPassZScaled>::MINW))
@@ -443,17 +455,28 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   __shared__ R sre[2 * W * P], sim[2 * W * P];
   __shared__ cplx<R> stw[P];
   const TwStage<R, P, 2 * C::WZ * C::TL> tws(tb.tw);
-  constexpr int TP = W * (int)sizeof(T) < 128 ? 2 : 1;  // tiles sharing a 128-byte line
-  const int w = threadIdx.x % W, side = (threadIdx.x / W) & 1, t = threadIdx.x / (2 * W);
-  constexpr bool SPLIT = z_col0_split<R, P, SC>();
+  static_assert(!ONE || SC == 1, "one-row workgroups: level grids only");
+  constexpr int WM = ONE ? 2 * W : W, NTM = (P / 2) / WM;  // columns and tiles of a workgroup's row(s)
+  constexpr int TP = WM * (int)sizeof(T) < 128 ? 2 : 1;   // tiles sharing a 128-byte line
+  constexpr bool SPLIT = ONE || z_col0_split<R, P, SC>();
   const int nc0 = SPLIT ? z_col0_blocks(NT, g.nf) : 0;
   const bool col0 = SPLIT && (int)blockIdx.x < nc0;  // uniform: a column-0 workgroup
+  const int t = threadIdx.x / (2 * W);
+  int w = threadIdx.x % W, side = (threadIdx.x / W) & 1;
   int f, tile, p;
   if (col0) {
     if ((int)blockIdx.x >= NT * g.nf) return;  // padding
     f = blockIdx.x / NT;
     tile = 0;
     p = (blockIdx.x % NT) * W + w;
+  } else if constexpr (ONE) {
+    // unit (row ky, tile of WM columns); side 0 and p = ky, the row itself
+    int unit;
+    z_unit(blockIdx.x - nc0, NTM * P, g.nf, TP, unit, f);
+    w = threadIdx.x % WM;
+    side = 0;
+    tile = unit % NTM;
+    p = unit / NTM;
   } else {
     int unit;
     z_unit(blockIdx.x - nc0, NT * (P / 2), g.nf, TP, unit, f);
@@ -465,8 +488,8 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   const bool full = FULLN && F.kind == 0;     // nout = N = P/2 as well
   const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N, g.S);
   const int n = gg.nin;
-  const int ky = side == 0 ? p : (p == 0 ? P / 2 : P - p);
-  const int kx = col0 ? 0 : tile * W + w;
+  const int ky = side == 0 ? p : (p == 0 ? P / 2 : P - p);  // ONE: p is any row in [0, P)
+  const int kx = col0 ? 0 : tile * WM + w;
   const bool owner = !SPLIT || col0 || kx != 0;  // this lane stores its line
   const int kyp = ky <= P / 2 ? ky : P - ky;
   T* B = static_cast<T*>(F.B) + (size_t)ky * (P / 2) + kx;  // row z at + z * P * (P/2)
@@ -486,7 +509,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   // spectrum values of this thread's points (the spectrum is even in kz:
   // kz = t + TL q reads row kz for q < E/2 and row P - kz = P/2 - t - TL (q - E/2)
   // above)
-  const R* gcol = tb.gz + (size_t)(kyp * NT + tile) * H * W + (col0 ? 0 : w);
+  const R* gcol = tb.gz + (size_t)(kyp * NT + kx / W) * H * W + kx % W;
   const R* glo = gcol + t * W;
   const R* ghi = gcol + (P / 2 - t) * W;
   // FP32: fetched after the forward transform, so that they hold no
@@ -502,7 +525,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
     }
   };
   if constexpr (!late) fetch_spectrum();
-  LdsView<R> lds{sre, sim, 2 * W, 1, w + W * side};
+  LdsView<R> lds{sre, sim, 2 * W, 1, w + W * side};  // ONE: line w < 2 W, side 0
   tws.put(stw);
   fft_line<R, P, -1, true, false, KZ>(v, t, lds, stw);
   if constexpr (late) fetch_spectrum();
@@ -1931,6 +1954,15 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
           launch(k_zs<R, true>, gs, bs, 0, s, ft, g, tb);
         else
           launch(k_zs<R, false>, gs, bs, 0, s, ft, g, tb);
+        return;
+      }
+      if constexpr (PP == 512 && NMC_Z_ONE_ROW && (sizeof(R) == 8 || NMC_Z_ONE_ROW_F32)) {
+        // one-row workgroups of 2 W columns (128-byte runs), column 0 apart
+        const dim3 g1(z_col0_blocks(NT, g.nf) + (PP / 2) / (2 * C::WZ) * PP * g.nf);
+        if (g.N == PP / 2)
+          launch(k_z<R, PP, true, 1, true>, g1, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
+        else
+          launch(k_z<R, PP, false, 1, true>, g1, dim3(2 * C::WZ * C::TL), 0, s, ft, g, tb);
         return;
       }
       if constexpr (z_col0_split<R, PP, 1>()) grid.x += z_col0_blocks(NT, g.nf);
