@@ -132,7 +132,7 @@ def pass_table(prof):
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "z_pass_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2301_06763_amd", "csrc", f) for f in ("kernels.hip", "fft_core.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2301_06763_amd", "csrc", f) for f in ("kernels.hip", "fft_core.hpp", "kernels.h")]
 
 
 def kernel_source_hash() -> str:

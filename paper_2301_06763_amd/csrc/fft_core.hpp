@@ -123,18 +123,26 @@ __device__ __forceinline__ void dft(T* u) {
 }
 
 // LDS view for the exchange between stages: point n of line w lives at
-// re[n * SN + w * SW] / im[...] (SoA, so every access is one scalar).
-template <class R>
+// re[n' * SN + w * SW] / im[...] (SoA, so every access is one scalar), with
+// n' = n, or with SWZ n' = n XOR bit 3 of n (into bit 0).  SWZ is for eight
+// interleaved lines (SN = 8, lanes w = lane % 8): a stage's accesses then
+// touch points n of one parity per instruction, all in one half of the 32
+// LDS banks, and the swizzle spreads them over both halves.
+template <class R, bool SWZ = false>
 struct LdsView {
   R* re;
   R* im;
   int SN, SW, w;
+  __device__ __forceinline__ int at(int n) const {
+    if constexpr (SWZ) n ^= (n >> 3) & 1;
+    return n * SN + w * SW;
+  }
   __device__ __forceinline__ void put(int n, cplx<R> v) const {
-    re[n * SN + w * SW] = v.x;
-    im[n * SN + w * SW] = v.y;
+    re[at(n)] = v.x;
+    im[at(n)] = v.y;
   }
   __device__ __forceinline__ cplx<R> get(int n) const {
-    return cplx<R>{re[n * SN + w * SW], im[n * SN + w * SW]};
+    return cplx<R>{re[at(n)], im[at(n)]};
   }
 };
 
@@ -148,24 +156,37 @@ constexpr bool twiddle_powers() {
   return sizeof(R) == 8 && NMC_TWIDDLE_POWERS_F64;
 }
 
+// Ordering of the LDS exchange between stages.  Workgroup barrier, or, when
+// every line's threads are lanes of one wavefront (WAVE), the wait for the
+// wavefront's own LDS accesses: its instructions issue in order, so once its
+// writes have completed its later reads see them, and its reads are done
+// before its next writes issue; waves then run without waiting for each
+// other.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  else __syncthreads();
+}
+
 // One Stockham stage and, recursively, the following ones.
 //  P: line length, E: points per thread, DIR: -1 forward / +1 inverse,
 //  NS: product of radices already applied, FIRST: data comes from registers,
 //  PIN: input index >= P/2 is zero (only valid on the first stage),
-//  POUT: only outputs < P/2 are needed (last stage).
-template <class R, int P, int E, int DIR, int NS, bool FIRST, bool PIN, bool POUT, int RAD, int... REST>
-__device__ __forceinline__ void fft_stages(cplx<R>* v, int t, const LdsView<R>& lds,
-                                           const cplx<R>* __restrict__ tw) {
+//  POUT: only outputs < P/2 are needed (last stage),
+//  WAVE: a line's threads are lanes of one wavefront (lds_sync).
+template <class R, int P, int E, int DIR, int NS, bool FIRST, bool PIN, bool POUT, bool WAVE, class LV, int RAD,
+          int... REST>
+__device__ __forceinline__ void fft_stages(cplx<R>* v, int t, const LV& lds, const cplx<R>* __restrict__ tw) {
   constexpr int TL = P / E;
   constexpr int NB = E / RAD;  // butterflies per thread in this stage
   constexpr bool LAST = sizeof...(REST) == 0;
   static_assert(E % RAD == 0, "radix must divide points per thread");
   if constexpr (!FIRST) {
-    __syncthreads();  // previous stage's writes are visible
+    lds_sync<WAVE>();  // previous stage's writes are visible
 #pragma unroll
     for (int q = 0; q < E; ++q) v[q] = lds.get(t + TL * q);
   }
-  if constexpr (!LAST) __syncthreads();  // everyone has read before anyone overwrites
+  if constexpr (!LAST) lds_sync<WAVE>();  // everyone has read before anyone overwrites
 #pragma unroll
   for (int m = 0; m < NB; ++m) {
     cplx<R> u[RAD];
@@ -205,7 +226,7 @@ __device__ __forceinline__ void fft_stages(cplx<R>* v, int t, const LdsView<R>& 
     }
   }
   if constexpr (!LAST)
-    fft_stages<R, P, E, DIR, NS * RAD, false, false, POUT, REST...>(v, t, lds, tw);
+    fft_stages<R, P, E, DIR, NS * RAD, false, false, POUT, WAVE, LV, REST...>(v, t, lds, tw);
 }
 
 // Per-length plans: points per thread E and the radix sequence.  Narrow
@@ -286,24 +307,24 @@ struct PlanSel<R, P, kPassZFold4> {
 template <class R, int P, int K = kPassOther>
 struct Plan : PlanSel<R, P, K>::type {};
 
-template <class R, int P, int DIR, bool PIN, bool POUT, int K>
+template <class R, int P, int DIR, bool PIN, bool POUT, int K, bool WAVE, class LV>
 struct FftRun {
   cplx<R>* v;
   int t;
-  const LdsView<R>* lds;
+  const LV* lds;
   const cplx<R>* tw;
   template <int... RS>
   __device__ __forceinline__ void go() const {
-    fft_stages<R, P, Plan<R, P, K>::E, DIR, 1, true, PIN, POUT, RS...>(v, t, *lds, tw);
+    fft_stages<R, P, Plan<R, P, K>::E, DIR, 1, true, PIN, POUT, WAVE, LV, RS...>(v, t, *lds, tw);
   }
 };
 
 // Transform one line held as v[q] = x[t + TL q] in place (natural order out),
-// TL = P / Plan<R, P, K>::E.
-template <class R, int P, int DIR, bool PIN, bool POUT, int K = kPassOther>
-__device__ __forceinline__ void fft_line(cplx<R>* v, int t, const LdsView<R>& lds,
-                                         const cplx<R>* __restrict__ tw) {
-  Plan<R, P, K>::run(FftRun<R, P, DIR, PIN, POUT, K>{v, t, &lds, tw});
+// TL = P / Plan<R, P, K>::E.  WAVE: the line's TL threads are lanes of one
+// wavefront and the caller has made the twiddle table visible to them.
+template <class R, int P, int DIR, bool PIN, bool POUT, int K = kPassOther, bool WAVE = false, class LV>
+__device__ __forceinline__ void fft_line(cplx<R>* v, int t, const LV& lds, const cplx<R>* __restrict__ tw) {
+  Plan<R, P, K>::run(FftRun<R, P, DIR, PIN, POUT, K, WAVE, LV>{v, t, &lds, tw});
 }
 
 }  // namespace nmc

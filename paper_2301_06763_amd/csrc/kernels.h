@@ -37,7 +37,7 @@ struct FieldDesc {
   const void* rho;   // level density [N][N][N] (x fastest), caller-owned
   const void* rc;    // restriction data of the child region (pyramid slab of level l+1), or null
   void* A;           // workspace [nin][nin][P/2] complex: x-pass output, y-inverse output
-  void* B;           // workspace [nin][P][P/2] complex ([2N][P][P/2] for kind 3): y-pass output, z-pass in place
+  void* B;           // workspace [nin][P][P/2] complex, z rows zrow_pitch apart: y-pass output, z-pass in place
   void* out;         // kind 0: potential [N][N][N]; kinds 1, 2: box [(N/2+2)^3]
   const void* S;     // kind 0, level >= 1: carried coarse potential S_{l-1} on the box (hi)
   const void* Slo;   // its compensation term (FP32 path) or null
@@ -52,6 +52,21 @@ struct FieldDesc {
   int comp;          // FP32: compensated (two-term) carry
   int tri;           // carry by the tensor-product rule (NMC_PROLONG_TRILINEAR), else Eqs. 3-6
 };
+
+// Elements between consecutive z rows of a grid's B (a z row holds P rows ky
+// of P/2 complex values of cbytes bytes each).  The z pass reads and writes
+// B down its columns, one value per z row; at a power-of-two row pitch (2 MB
+// at P = 512 in FP64) the values of a column, and those that neighbouring
+// workgroups touch at the same time, fall on the same few HBM channels.  A
+// plain read and write of 128-byte column runs of such a B moves 4.2 TB/s
+// at the power-of-two pitch and 4.5 TB/s (4.9 TB/s with the rows ky
+// fastest across workgroups) with 256 bytes more per z row.
+#ifndef NMC_ZROW_PAD
+#define NMC_ZROW_PAD 256
+#endif
+__host__ __device__ constexpr size_t zrow_pitch(int P, size_t cbytes) {
+  return (size_t)P * (P / 2) + (size_t)NMC_ZROW_PAD / cbytes;
+}
 
 // Restriction data (Sect. 2: the density of a level's child region is the
 // mean over the 2x2x2 children of the next finer level, whose own child

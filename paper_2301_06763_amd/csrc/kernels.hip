@@ -55,6 +55,13 @@ namespace nmc {
 #ifndef NMC_Z_ONE_ROW_F32
 #define NMC_Z_ONE_ROW_F32 0
 #endif
+// LDS swizzle (LdsView) of the eight interleaved lines of the one-row z
+// workgroups: 256^3 x 6 levels FP64, z pass 3.04 -> 2.99 ms.  The y passes'
+// workgroups of eight FP64 columns at P = 512 have the same layout and ran
+// no faster with it (1.24 ms either way), so they keep the plain one.
+#ifndef NMC_Z_SWZ_ONE
+#define NMC_Z_SWZ_ONE 1
+#endif
 #ifndef NMC_ZS_MINW_F64
 #define NMC_ZS_MINW_F64 2
 #endif
@@ -246,6 +253,27 @@ __device__ __forceinline__ double lane_read(double x, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Units (line pairs or lines) per workgroup of the x passes, and whether
+// their exchanges wait per wavefront instead of per workgroup.  A line's
+// threads are lanes of one wavefront, so once the workgroup has staged the
+// twiddle table its wavefronts need no workgroup barrier: each takes IT
+// units in turn at its own pace, and the table is staged once per IT units.
+// Measured at 256^3 x 6 levels, FP64: forward x pass 0.755 ms with one unit
+// per wavefront, 0.636 ms with four; the inverse x pass, whose carry
+// epilogue gathers from the carried box, ran slower with four (0.127 ->
+// 0.140 ms per launch), so it keeps one.
+#ifndef NMC_X_ITERS
+#define NMC_X_ITERS 4
+#endif
+#ifndef NMC_IX_ITERS
+#define NMC_IX_ITERS 1
+#endif
+#ifndef NMC_X_WAVE
+#define NMC_X_WAVE 1
+#endif
+template <int P, bool INV = false>
+constexpr int x_iters() { return P >= 512 ? (INV ? NMC_IX_ITERS : NMC_X_ITERS) : 1; }
+
 // PAIRS: two real lines a, b per complex transform: z = a + i b,
 // Z = FFT(z), A[k] = (Z[k] + conj Z[P-k]) / 2, B[k] = (Z[k] - conj Z[P-k]) / (2i).
 // The point P - k of thread t's point k = t + TL q sits in thread TL - t,
@@ -257,7 +285,8 @@ __global__ void __launch_bounds__((Cfg<R, P, kPassX>::WC * Cfg<R, P, kPassX>::TL
 k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassX>;
   using T = cplx<R>;
-  constexpr int E = C::E, TL = C::TL, W = C::WC, LPW = PAIRS ? 2 : 1;
+  constexpr int E = C::E, TL = C::TL, W = C::WC, LPW = PAIRS ? 2 : 1, IT = x_iters<P>();
+  constexpr bool WAVE = NMC_X_WAVE != 0;
   static_assert(64 % TL == 0, "a line's threads must share a wavefront");
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
@@ -265,58 +294,64 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = FULLN ? P / 2 : g.N, n = grid_geo<DBL>(F.kind, N, g.S).nin;
   const int nunits = n * n / LPW;  // n is even: the two lines of a pair share z
-  if ((int)blockIdx.x * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
+  if ((int)blockIdx.x * IT * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
-  const int unit = blockIdx.x * W + w;
-  const bool active = unit < nunits;
-  const int line = active ? LPW * unit : 0;
-  const int z = line / n, y = line % n;
-  T va[E], v[E];
   const int xo = DBL ? (g.S - 1) * N / 2 : 0;
-  x_inputs<R, P, FULLN, kPassX, DBL>(F, N, z, y, active, t, va, xo);
-  if constexpr (PAIRS) {
-    T vb[E];
-    x_inputs<R, P, FULLN, kPassX, DBL>(F, N, z, y + 1, active, t, vb, xo);
-#pragma unroll
-    for (int q = 0; q < E / 2; ++q) v[q] = T{va[q].x, vb[q].x};
-  } else {
-#pragma unroll
-    for (int q = 0; q < E / 2; ++q) v[q] = va[q];
-  }
-  LdsView<R> lds{sre, sim, 1, P, w};
+  const LdsView<R> lds{sre, sim, 1, P, w};
   tws.put(stw);
-  fft_line<R, P, -1, true, false, kPassX>(v, t, lds, stw);
-  if constexpr (!PAIRS) {
-    if (active) {
-      T* A = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
+  if constexpr (WAVE) __syncthreads();  // the table is complete before the first stage that reads it
+  for (int it = 0; it < IT; ++it) {
+    const int u0 = ((int)blockIdx.x * IT + it) * W;
+    if (u0 >= nunits) break;  // uniform
+    const int unit = u0 + w;
+    const bool active = unit < nunits;
+    const int line = active ? LPW * unit : 0;
+    const int z = line / n, y = line % n;
+    T va[E], v[E];
+    x_inputs<R, P, FULLN, kPassX, DBL>(F, N, z, y, active, t, va, xo);
+    if constexpr (PAIRS) {
+      T vb[E];
+      x_inputs<R, P, FULLN, kPassX, DBL>(F, N, z, y + 1, active, t, vb, xo);
 #pragma unroll
-      for (int q = 0; q < E / 2; ++q) A[t + TL * q] = x_packed<R, P, kPassX>(v, t, q);
+      for (int q = 0; q < E / 2; ++q) v[q] = T{va[q].x, vb[q].x};
+    } else {
+#pragma unroll
+      for (int q = 0; q < E / 2; ++q) v[q] = va[q];
     }
-    return;
-  }
-  const int lane = threadIdx.x & 63;
-  const int partner = (lane - t) + ((TL - t) & (TL - 1));
-  T zm[E / 2];
+    fft_line<R, P, -1, true, false, kPassX, WAVE>(v, t, lds, stw);
+    if constexpr (!PAIRS) {
+      if (active) {
+        T* A = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
 #pragma unroll
-  for (int q = 0; q < E / 2; ++q) {
-    const T o = v[E - 1 - q];
-    const T p = T{lane_read(o.x, partner), lane_read(o.y, partner)};
-    zm[q] = t == 0 ? v[(E - q) % E] : p;
-  }
-  if (!active) return;
-  T* Aa = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
-  T* Ab = Aa + P / 2;
+        for (int q = 0; q < E / 2; ++q) A[t + TL * q] = x_packed<R, P, kPassX>(v, t, q);
+      }
+    } else {
+      const int lane = threadIdx.x & 63;
+      const int partner = (lane - t) + ((TL - t) & (TL - 1));
+      T zm[E / 2];
 #pragma unroll
-  for (int q = 0; q < E / 2; ++q) {
-    const T zk = v[q], m = zm[q];
-    T a = T{(R)0.5 * (zk.x + m.x), (R)0.5 * (zk.y - m.y)};
-    T b = T{(R)0.5 * (zk.y + m.y), (R)0.5 * (m.x - zk.x)};
-    if (t == 0 && q == 0) {  // DC and Nyquist are real: pack them
-      a = T{v[0].x, v[E / 2].x};
-      b = T{v[0].y, v[E / 2].y};
+      for (int q = 0; q < E / 2; ++q) {
+        const T o = v[E - 1 - q];
+        const T p = T{lane_read(o.x, partner), lane_read(o.y, partner)};
+        zm[q] = t == 0 ? v[(E - q) % E] : p;
+      }
+      if (active) {
+        T* Aa = static_cast<T*>(F.A) + ((size_t)z * n + y) * (P / 2);
+        T* Ab = Aa + P / 2;
+#pragma unroll
+        for (int q = 0; q < E / 2; ++q) {
+          const T zk = v[q], m = zm[q];
+          T a = T{(R)0.5 * (zk.x + m.x), (R)0.5 * (zk.y - m.y)};
+          T b = T{(R)0.5 * (zk.y + m.y), (R)0.5 * (m.x - zk.x)};
+          if (t == 0 && q == 0) {  // DC and Nyquist are real: pack them
+            a = T{v[0].x, v[E / 2].x};
+            b = T{v[0].y, v[E / 2].y};
+          }
+          Aa[t + TL * q] = a;
+          Ab[t + TL * q] = b;
+        }
+      }
     }
-    Aa[t + TL * q] = a;
-    Ab[t + TL * q] = b;
   }
 }
 
@@ -341,7 +376,7 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int kx = tile * W + w;
   const T* A = static_cast<const T*>(F.A) + (size_t)z * n * (P / 2) + kx;
-  T* B = static_cast<T*>(F.B) + (size_t)z * P * (P / 2) + kx;
+  T* B = static_cast<T*>(F.B) + (size_t)z * zrow_pitch(P, sizeof(T)) + kx;
   T v[E];
 #pragma unroll
   for (int q = 0; q < E / 2; ++q) {
@@ -350,7 +385,7 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
     const T a = A[(size_t)(in ? yy : 0) * (P / 2)];  // branch-free: a valid row, value dropped
     v[q] = in ? a : T{0, 0};
   }
-  LdsView<R> lds{sre, sim, W, 1, w};
+  const LdsView<R> lds{sre, sim, W, 1, w};
   tws.put(stw);
   fft_line<R, P, -1, true, false, kPassY>(v, t, lds, stw);
 #pragma unroll
@@ -409,6 +444,25 @@ __device__ __forceinline__ void z_unit(int b, int U, int nf, int TP, int& u, int
   f = s % nf;
   const int j = s / nf;
   u = ((j / TP) * 8 + x) * TP + j % TP;
+}
+
+// Row r and tile of unit u of a grid of `rows` rows of NTL tiles.  With
+// NMC_Z_KYFAST consecutive units step through the rows (the workgroups in
+// flight then touch rows 4 KB apart, on different HBM channels, rather than
+// the neighbouring tiles of one row), keeping the TP tiles that share a
+// 128-byte line together; else through the tiles of a row.
+#ifndef NMC_Z_KYFAST
+#define NMC_Z_KYFAST 1
+#endif
+__device__ __forceinline__ void z_row_tile(int u, int rows, int NTL, int TP, int& r, int& tile) {
+  if (NMC_Z_KYFAST && NTL % TP == 0) {
+    const int v = u / TP;
+    r = v % rows;
+    tile = (v / rows) * TP + u % TP;
+  } else {
+    r = u / NTL;
+    tile = u % NTL;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -475,13 +529,11 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
     z_unit(blockIdx.x - nc0, NTM * P, g.nf, TP, unit, f);
     w = threadIdx.x % WM;
     side = 0;
-    tile = unit % NTM;
-    p = unit / NTM;
+    z_row_tile(unit, P, NTM, TP, p, tile);
   } else {
     int unit;
     z_unit(blockIdx.x - nc0, NT * (P / 2), g.nf, TP, unit, f);
-    tile = unit % NT;
-    p = unit / NT;
+    z_row_tile(unit, P / 2, NT, TP, p, tile);
   }
   const FieldDesc& F = ft.f[f];
   const bool full_in = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks on loads
@@ -492,8 +544,8 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int kx = col0 ? 0 : tile * WM + w;
   const bool owner = !SPLIT || col0 || kx != 0;  // this lane stores its line
   const int kyp = ky <= P / 2 ? ky : P - ky;
-  T* B = static_cast<T*>(F.B) + (size_t)ky * (P / 2) + kx;  // row z at + z * P * (P/2)
-  constexpr size_t ZS = (size_t)P * (P / 2);
+  T* B = static_cast<T*>(F.B) + (size_t)ky * (P / 2) + kx;  // row z at + z ZS
+  constexpr size_t ZS = zrow_pitch(P, sizeof(T));
   // rows z >= n are zero (no load)
   T v[E];
   if (full_in) {
@@ -525,7 +577,8 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
     }
   };
   if constexpr (!late) fetch_spectrum();
-  LdsView<R> lds{sre, sim, 2 * W, 1, w + W * side};  // ONE: line w < 2 W, side 0
+  // ONE: line w < 2 W, side 0
+  const LdsView<R, ONE && NMC_Z_SWZ_ONE && 2 * W == 8> lds{sre, sim, 2 * W, 1, w + W * side};
   tws.put(stw);
   fft_line<R, P, -1, true, false, KZ>(v, t, lds, stw);
   if constexpr (late) fetch_spectrum();
@@ -608,15 +661,16 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
 
 // ---------------------------------------------------------------------------
 // Z pass at P = 512 through staged tiles (level grids; used for FP32, where
-// it runs the 256^3 x 6 launch in 1.72 ms against k_z's 1.81 ms; for FP64
-// its 220 registers leave two wavefronts per SIMD and k_z stays faster,
-// 3.47 against 3.73 ms).
+// it ran the 256^3 x 6 launch in 1.72 ms against k_z's 1.81 ms, both at the
+// unpadded row pitch; for FP64 its 220 registers leave two wavefronts per
+// SIMD and k_z stays faster, 3.47 against 3.73 ms).
 //
-// A grid's z rows are 2 MB apart (one z row of B holds P (P/2) values), and
-// what HBM delivers for such rows depends on the contiguous run each memory
-// instruction covers: a plain read and write of B on the GPU moves 2.7 TB/s
-// with 64-byte runs (k_z's: 4 FP64 or 8 FP32 adjacent columns per lane group),
-// 4.0 TB/s with 128-byte runs and 5.0 TB/s with 256-byte runs.  Here a
+// A grid's z rows are about 2 MB apart (one z row of B holds P (P/2) values,
+// zrow_pitch), and what HBM delivers for such rows depends on the contiguous
+// run each memory instruction covers: at the power-of-two pitch a plain read
+// and write of B on the GPU moves 2.7 TB/s with 64-byte runs (k_z's: 4 FP64
+// or 8 FP32 adjacent columns per lane group), 4.0 TB/s with 128-byte runs
+// and 5.0 TB/s with 256-byte runs.  Here a
 // workgroup first stages the tile [row ky, -ky][z][CS columns] through LDS
 // with 128-byte runs, then each wavefront transforms four whole lines with
 // 32 points per lane: radix 16 then radix 32, one exchange per transform,
@@ -750,7 +804,7 @@ __device__ __forceinline__ void zs_tile(const FieldTable& ft, const PassGeom& g,
   const GridGeo gg = grid_geo<false>(F.kind, FULLN ? P / 2 : g.N);
   const int n = gg.nin;
   auto row_of = [&](int side) { return side == 0 ? p : (p == 0 ? P / 2 : P - p); };
-  constexpr unsigned ZS = (unsigned)(P * (P / 2) * sizeof(T));  // bytes between z rows of B
+  constexpr unsigned ZS = (unsigned)(zrow_pitch(P, sizeof(T)) * sizeof(T));  // bytes between z rows of B
   char* const B = static_cast<char*>(F.B);
   // staging lanes: column c, z rows zr + 16 k, row `sside` of the pair
   const int c = threadIdx.x % CS, zr = (threadIdx.x / CS) % ZR, sside = threadIdx.x / (CS * ZR);
@@ -863,9 +917,10 @@ k_zs(FieldTable ft, PassGeom g, Tables<R> tb) {
   if ((int)blockIdx.x >= c0_blocks) {
     int unit, f;
     z_unit(blockIdx.x - c0_blocks, G::UNITS, g.nf, 1, unit, f);
-    const int tl = unit % G::TILES;
+    int p, tl;
+    z_row_tile(unit, zs::P / 2, G::TILES, 1, p, tl);
     if (tl == 0) return;  // whole workgroup
-    zs_tile<R, FULLN, false>(ft, g, tb, f, unit / G::TILES, tl, lds);
+    zs_tile<R, FULLN, false>(ft, g, tb, f, p, tl, lds);
   } else {
     zs_tile<R, FULLN, true>(ft, g, tb, blockIdx.x / (zs::P / 2), blockIdx.x % (zs::P / 2), 0, lds);
   }
@@ -890,12 +945,12 @@ k_inv_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int z = gg.olo + r;
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int kx = (blockIdx.x % NT) * W + w;
-  const T* B = static_cast<const T*>(F.B) + (size_t)z * P * (P / 2) + kx;
+  const T* B = static_cast<const T*>(F.B) + (size_t)z * zrow_pitch(P, sizeof(T)) + kx;
   T* A = static_cast<T*>(F.A) + (size_t)z * gg.nin * (P / 2) + kx;
   T v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = B[(size_t)(t + TL * q) * (P / 2)];
-  LdsView<R> lds{sre, sim, W, 1, w};
+  const LdsView<R> lds{sre, sim, W, 1, w};
   tws.put(stw);
   fft_line<R, P, +1, false, true, kPassIY>(v, t, lds, stw);
 #pragma unroll
@@ -1086,6 +1141,9 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassIX>;
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WC, LPW = PAIRS ? 2 : 1;  // lines per transform
+  constexpr int IT = x_iters<P, true>();
+  constexpr bool WAVE = NMC_X_WAVE != 0;
+  static_assert(64 % TL == 0, "a line's threads must share a wavefront");
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw[P];
   const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
@@ -1094,49 +1152,56 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const GridGeo gg = grid_geo(F.kind, N);
   const int n = gg.nout;
   const int nunits = n * n / LPW;  // n is even: the two lines of a pair share z
-  if ((int)blockIdx.x * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
+  if ((int)blockIdx.x * IT * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
-  const int unit = blockIdx.x * W + w;
-  const bool active = unit < nunits;
-  const int line = active ? LPW * unit : 0;
-  const int zr = line / n, yr = line % n;  // within the output box
-  const int z = gg.olo + zr, y = gg.olo + yr;
-  const T* ra = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
-  const T* rb = ra + P / 2;
-  // packed half spectra: k = 0 holds the real DC (.x) and Nyquist (.y) values;
-  // every load is issued without a branch (inactive units read row 0 and drop it)
-  T v[E];
-#pragma unroll
-  for (int q = 0; q < E / 2; ++q) {
-    const int k = t + TL * q;
-    T a = ra[k], b = PAIRS ? rb[k] : T{0, 0};
-    if (k == 0) {
-      a.y = 0;
-      b.y = 0;
-    }
-    v[q] = active ? T{a.x - b.y, a.y + b.x} : T{0, 0};
-  }
-#pragma unroll
-  for (int q = E / 2; q < E; ++q) {
-    const int kk = P - (t + TL * q);  // in (0, P/2]
-    const int idx = kk == P / 2 ? 0 : kk;
-    T a = ra[idx], b = PAIRS ? rb[idx] : T{0, 0};
-    if (kk == P / 2) {
-      a = T{a.y, 0};
-      b = T{b.y, 0};
-    }
-    v[q] = active ? T{a.x + b.y, b.x - a.y} : T{0, 0};  // conj(A) + i conj(B)
-  }
-  LdsView<R> lds{sre, sim, 1, P, w};
+  const LdsView<R> lds{sre, sim, 1, P, w};
   tws.put(stw);
-  fft_line<R, P, +1, false, true, kPassIX>(v, t, lds, stw);
-  if (!active) return;
-  ix_outputs<R, P, kPassIX, TRI>(F, N, gg, z, y, zr, yr, t, v);
-  if constexpr (PAIRS) {
-    T vb[E / 2];
+  if constexpr (WAVE) __syncthreads();  // the table is complete before the first stage that reads it
+  for (int it = 0; it < IT; ++it) {
+    const int u0 = ((int)blockIdx.x * IT + it) * W;
+    if (u0 >= nunits) break;  // uniform
+    const int unit = u0 + w;
+    const bool active = unit < nunits;
+    const int line = active ? LPW * unit : 0;
+    const int zr = line / n, yr = line % n;  // within the output box
+    const int z = gg.olo + zr, y = gg.olo + yr;
+    const T* ra = static_cast<const T*>(F.A) + ((size_t)z * gg.nin + y) * (P / 2);
+    const T* rb = ra + P / 2;
+    // packed half spectra: k = 0 holds the real DC (.x) and Nyquist (.y)
+    // values; every load is issued without a branch (inactive units read
+    // row 0 and drop it)
+    T v[E];
 #pragma unroll
-    for (int q = 0; q < E / 2; ++q) vb[q] = T{v[q].y, 0};
-    ix_outputs<R, P, kPassIX, TRI>(F, N, gg, z, y + 1, zr, yr + 1, t, vb);
+    for (int q = 0; q < E / 2; ++q) {
+      const int k = t + TL * q;
+      T a = ra[k], b = PAIRS ? rb[k] : T{0, 0};
+      if (k == 0) {
+        a.y = 0;
+        b.y = 0;
+      }
+      v[q] = active ? T{a.x - b.y, a.y + b.x} : T{0, 0};
+    }
+#pragma unroll
+    for (int q = E / 2; q < E; ++q) {
+      const int kk = P - (t + TL * q);  // in (0, P/2]
+      const int idx = kk == P / 2 ? 0 : kk;
+      T a = ra[idx], b = PAIRS ? rb[idx] : T{0, 0};
+      if (kk == P / 2) {
+        a = T{a.y, 0};
+        b = T{b.y, 0};
+      }
+      v[q] = active ? T{a.x + b.y, b.x - a.y} : T{0, 0};  // conj(A) + i conj(B)
+    }
+    fft_line<R, P, +1, false, true, kPassIX, WAVE>(v, t, lds, stw);
+    if (active) {
+      ix_outputs<R, P, kPassIX, TRI>(F, N, gg, z, y, zr, yr, t, v);
+      if constexpr (PAIRS) {
+        T vb[E / 2];
+#pragma unroll
+        for (int q = 0; q < E / 2; ++q) vb[q] = T{v[q].y, 0};
+        ix_outputs<R, P, kPassIX, TRI>(F, N, gg, z, y + 1, zr, yr + 1, t, vb);
+      }
+    }
   }
 }
 
@@ -1158,7 +1223,7 @@ k_inv_y_fold(FieldTable ft, PassGeom g, Tables<R> tb) {
   if (z >= N) return;  // uniform: a smaller grid of a mixed launch
   const int w = threadIdx.x % W, t = threadIdx.x / W;
   const int kx = (blockIdx.x % NT) * W + w;
-  const T* B0 = static_cast<const T*>(F.B) + (size_t)z * PS * HS + kx;  // ky at + ky HS
+  const T* B0 = static_cast<const T*>(F.B) + (size_t)z * zrow_pitch(PS, sizeof(T)) + kx;  // ky at + ky HS
   T v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q)
@@ -1347,7 +1412,7 @@ __global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_fwd_xy(FieldTable ft,
     const int w = threadIdx.x % WL, t = threadIdx.x / WL;
     const LdsView<R> lds{sre, sim, WL, 1, w};
     const bool full_in = FULLN && F.kind != 1;
-    T* Bz = static_cast<T*>(F.B) + (size_t)z * P * H2;
+    T* Bz = static_cast<T*>(F.B) + (size_t)z * zrow_pitch(P, sizeof(T));
     for (int k0 = 0; k0 < H2; k0 += WL) {
       const int kx = k0 + w;
       T v[E];
@@ -1383,7 +1448,7 @@ __global__ void __launch_bounds__((PlaneCfg<R, P>::NTH)) k_inv_yx(FieldTable ft,
   {  // y columns kx: inverse, keep the output rows [olo, olo + n)
     const int w = threadIdx.x % WL, t = threadIdx.x / WL;
     const LdsView<R> lds{sre, sim, WL, 1, w};
-    const T* Bz = static_cast<const T*>(F.B) + (size_t)z * P * H2;
+    const T* Bz = static_cast<const T*>(F.B) + (size_t)z * zrow_pitch(P, sizeof(T));
     // the next round's columns are loaded while this round is transformed
     T vn[E];
 #pragma unroll
@@ -1889,7 +1954,8 @@ hipError_t launch_fwd_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassX>;
     const int units = pairs ? g.n * g.n / 2 : g.n * g.n;
-    dim3 grid((units + C::WC - 1) / C::WC, g.nf), block(C::WC * C::TL);
+    constexpr int UW = C::WC * x_iters<PP>();  // units per workgroup
+    dim3 grid((units + UW - 1) / UW, g.nf), block(C::WC * C::TL);
     const bool full = g.N == PP / 2;
     if constexpr (PP >= 16) {
       if (PP >= 4 * g.N) {  // scaled grids
@@ -2000,7 +2066,8 @@ hipError_t launch_inv_x(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStrea
     constexpr int PP = decltype(pc)::value;
     using C = Cfg<R, PP, kPassIX>;
     const int units = pairs ? g.n * g.n / 2 : g.n * g.n;
-    dim3 grid((units + C::WC - 1) / C::WC, g.nf);
+    constexpr int UW = C::WC * x_iters<PP, true>();  // units per workgroup
+    dim3 grid((units + UW - 1) / UW, g.nf);
     // a launch's grids share the carry rule (the runtime groups by it)
     const bool tri = ft.f[0].tri != 0;
     if (pairs && tri)

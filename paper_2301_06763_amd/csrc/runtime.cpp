@@ -115,17 +115,17 @@ Layout make_layout(int N, int L, nmc_precision p, unsigned flags) {
   lo.c = 2 * lo.r;
   const size_t P = lo.P, NC = lo.NC, ns = lo.boxes ? NC : (size_t)N;
   lo.a_full = align_up((size_t)N * N * (P / 2) * lo.c);
-  lo.b_full = align_up((size_t)N * P * (P / 2) * lo.c);
+  lo.b_full = align_up((size_t)N * nmc::zrow_pitch((int)P, lo.c) * lo.c);
   if (lo.mod) {
     // doubled grid, period 2P: N x N rows of the x half spectrum (P values;
     // x-pass output and folded y-inverse output), N z rows (y-pass output,
     // folded z-pass output in place)
     const size_t PD = 2 * P;
     lo.a_sec = align_up((size_t)N * N * (PD / 2) * lo.c);
-    lo.b_sec = align_up((size_t)N * PD * (PD / 2) * lo.c);
+    lo.b_sec = align_up((size_t)N * nmc::zrow_pitch((int)PD, lo.c) * lo.c);
   } else {
     lo.a_sec = align_up(ns * ns * (P / 2) * lo.c);
-    lo.b_sec = align_up(ns * P * (P / 2) * lo.c);
+    lo.b_sec = align_up(ns * nmc::zrow_pitch((int)P, lo.c) * lo.c);
   }
   lo.rc_bytes = align_up((size_t)nmc::pyramid_slab(N, L) * lo.r);
   lo.box_bytes = align_up(NC * NC * NC * lo.r);
@@ -134,7 +134,7 @@ Layout make_layout(int N, int L, nmc_precision p, unsigned flags) {
     // values), N z rows
     const size_t PQ = 4 * P;
     lo.a_q = align_up((size_t)N * N * (PQ / 2) * lo.c);
-    lo.b_q = align_up((size_t)N * PQ * (PQ / 2) * lo.c);
+    lo.b_q = align_up((size_t)N * nmc::zrow_pitch((int)PQ, lo.c) * lo.c);
   }
   lo.total = lo.Aq(0) + (lo.mod3 ? (size_t)(L - 2) * (lo.a_q + lo.b_q) : 0);
   lo.total = std::max(lo.total, kAlign);
