@@ -158,6 +158,42 @@ struct Block {
 struct Lease {
   std::vector<Block> blocks;
   hipEvent_t ev = nullptr;
+  bool in_arena = false;  // a serving batch's region of the serving arena
+};
+
+// Workspace of the serving batches under a budget: one device allocation
+// used as a ring.  Batches retire in launch order, so regions are released
+// oldest first and the free space is one run (wrapping at the end); no
+// allocation, free or device-wide wait happens while the serving loop runs
+// at its budget.
+struct ServeArena {
+  char* base = nullptr;
+  size_t size = 0;
+  std::deque<std::pair<size_t, size_t>> live;  // (offset, bytes), oldest first
+  // A region of `bytes` after the newest one (or at the start, past the
+  // end); false when it does not fit beside the regions in use.
+  bool alloc(size_t bytes, size_t* off) {
+    if (bytes > size) return false;
+    size_t at = 0;
+    if (!live.empty()) {
+      const size_t tail = live.front().first;
+      const size_t head = live.back().first + live.back().second;
+      const bool wrapped = live.back().first < tail;
+      if (!wrapped && head + bytes <= size) at = head;
+      else if (!wrapped && bytes <= tail) at = 0;
+      else if (wrapped && head + bytes <= tail) at = head;
+      else return false;
+    }
+    live.emplace_back(at, bytes);
+    *off = at;
+    return true;
+  }
+  void release_oldest() {
+    if (!live.empty()) live.pop_front();
+  }
+  void release_newest() {
+    if (!live.empty()) live.pop_back();
+  }
 };
 
 struct PerP {
@@ -219,6 +255,7 @@ struct nmc_ctx {
   hipStream_t streams[kServeStreams] = {};
   int next_stream = 0;
   std::vector<hipEvent_t> ev_pool;  // reusable submit events
+  ServeArena arena;                  // serving workspace under a budget
   // second stream of a solve (hole grids and carry cascade) and its fork/join events
   hipStream_t aux_stream = nullptr;
   // this device's static scratch array (nmc_solve_noalloc)
@@ -941,6 +978,12 @@ void make_room(nmc_ctx* ctx, size_t need, const std::vector<int>& keep) {
       ctx->free_blocks.erase(it);
       continue;
     }
+    if (ctx->arena.base && ctx->arena.live.empty() && (!ctx->serve || ctx->serve->idle())) {
+      (void)hipFree(ctx->arena.base);  // the serving arena, while no batch uses it
+      ctx->allocated -= ctx->arena.size;
+      ctx->arena = ServeArena{};
+      continue;
+    }
     if (!synced) {
       (void)hipDeviceSynchronize();
       reap_leases(ctx, false);
@@ -960,20 +1003,33 @@ void make_room(nmc_ctx* ctx, size_t need, const std::vector<int>& keep) {
 
 // Green tables (and twiddles) of every period a group needs, and room for
 // its workspace of ws_bytes, under the budget.
-int prepare(nmc_ctx* ctx, int N, unsigned flags, hipStream_t s, size_t ws_bytes) {
+std::vector<int> periods_of(int N, unsigned flags) {
   const int P = period_of(N);
   std::vector<int> keep{P};
   if (is_modified(flags)) keep.push_back(2 * P);
   if ((flags & NMC_MODIFIED3) && 4 * P <= kMaxScaledP) keep.push_back(4 * P);
+  return keep;
+}
+
+// The Green tables (and twiddles) of every period a group needs.
+int prepare_tables(nmc_ctx* ctx, int N, unsigned flags, hipStream_t s) {
+  const std::vector<int> keep = periods_of(N, flags);
   size_t need = 0;
   for (int q : keep)
     if (!ctx->perp[q].bytes) need += green_table_bytes(q);
-  make_room(ctx, need, keep);
+  if (need) make_room(ctx, need, keep);
   for (int q : keep) {
     int rc = ensure_green(ctx, q, s);
     if (rc) return rc;
     ctx->perp[q].used = ++ctx->clock;
   }
+  return NMC_OK;
+}
+
+int prepare(nmc_ctx* ctx, int N, unsigned flags, hipStream_t s, size_t ws_bytes) {
+  int rc = prepare_tables(ctx, N, flags, s);
+  if (rc) return rc;
+  const std::vector<int> keep = periods_of(N, flags);
   // a cached block the pool will reuse for the workspace needs no room
   const size_t ws = align_up(ws_bytes, 2u << 20);
   reap_leases(ctx, false);
@@ -1112,6 +1168,36 @@ int scratch_address(nmc_ctx* ctx, int dev, char** out) {
 // The serving scheduler's device side: each batch is one batched solve on
 // the next serving stream, ordered after the events recorded at submission,
 // and completes with an event recorded after it.
+// The serving arena of a context with a budget: created at the first
+// serving launch from what the budget leaves beside the Green tables, the
+// workspace of solves in flight and room for the tables of other periods
+// (a sixteenth of the budget, at most 1 GiB); cached solve workspace blocks
+// are released first.  make_room frees it again while no batch uses it.
+int ensure_arena(nmc_ctx* ctx) {
+  if (ctx->arena.base) return NMC_OK;
+  reap_leases(ctx, false);
+  for (auto& b : ctx->free_blocks) {
+    (void)hipFree(b.ptr);
+    ctx->allocated -= b.bytes;
+  }
+  ctx->free_blocks.clear();
+  const size_t headroom = std::min<size_t>(ctx->budget / 16, size_t(1) << 30);
+  const size_t held = ctx->allocated + ctx->green_bytes + headroom;
+  if (held >= ctx->budget) return fail(ctx, NMC_ENOMEM, "serving: the budget leaves no room for serving workspace");
+  const size_t size = (ctx->budget - held) / (2u << 20) * (2u << 20);
+  void* p = nullptr;
+  const hipError_t e = hipMalloc(&p, size);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, NMC_ENOMEM, "serving: workspace arena of " + std::to_string(size) + " bytes: " +
+                                     hipGetErrorString(e));
+  }
+  ctx->arena.base = static_cast<char*>(p);
+  ctx->arena.size = size;
+  ctx->allocated += size;
+  return NMC_OK;
+}
+
 class HipServeDevice final : public nmc::ServeDevice {
  public:
   explicit HipServeDevice(nmc_ctx* c) : ctx_(c) {}
@@ -1126,8 +1212,20 @@ class HipServeDevice final : public nmc::ServeDevice {
     std::vector<Req> rs;
     for (uint64_t t : b.tickets) rs.push_back(ctx_->sreq.at(t).r);
     hipStream_t s = ctx_->streams[ctx_->next_stream];
-    // order the batch after the callers' work on its inputs and outputs
     int rc = NMC_OK;
+    // under a budget the batch's workspace is a region of the serving arena;
+    // NMC_ENOMEM (nothing enqueued) when it does not fit beside the batches
+    // in flight, and the scheduler retries after some retire
+    size_t arena_bytes = 0, arena_off = 0;
+    if (ctx_->budget) {
+      for (const Req& r : rs) arena_bytes += make_layout(r.N, r.L, r.p, r.flags).total;
+      arena_bytes = align_up(arena_bytes, size_t(64) << 10);
+      if ((rc = prepare_tables(ctx_, rs[0].N, rs[0].flags, s))) return rc;
+      if ((rc = ensure_arena(ctx_))) return rc == NMC_ENOMEM ? NMC_EDEVICE : rc;
+      if (!ctx_->arena.alloc(arena_bytes, &arena_off)) return NMC_ENOMEM;
+      lease->in_arena = true;
+    }
+    // order the batch after the callers' work on its inputs and outputs
     for (uint64_t t : b.tickets) {
       hipError_t e = hipStreamWaitEvent(s, ctx_->sreq.at(t).ready, 0);
       if (e != hipSuccess) {
@@ -1135,7 +1233,15 @@ class HipServeDevice final : public nmc::ServeDevice {
         break;
       }
     }
-    if (rc == NMC_OK) rc = launch_group(ctx_, rs.data(), (int)rs.size(), s, lease.get(), nullptr);
+    if (rc == NMC_OK) {
+      if (lease->in_arena) {
+        char* ws = ctx_->arena.base + arena_off;
+        rc = rs[0].p == NMC_F64 ? run_group<double>(ctx_, rs.data(), (int)rs.size(), ws, s, nullptr)
+                                : run_group<float>(ctx_, rs.data(), (int)rs.size(), ws, s, nullptr);
+      } else {
+        rc = launch_group(ctx_, rs.data(), (int)rs.size(), s, lease.get(), nullptr);
+      }
+    }
     if (rc == NMC_OK) {
       hipError_t e = hipEventCreateWithFlags(&lease->ev, hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventRecord(lease->ev, s);
@@ -1146,16 +1252,17 @@ class HipServeDevice final : public nmc::ServeDevice {
       }
     }
     if (rc) {
-      // a failed launch may have enqueued part of the group: its blocks are
+      // a failed launch may have enqueued part of the group: its workspace is
       // free once the stream has drained.  ENOMEM: the pool could not place
       // it next to the work in flight (block sizes differ from footprints);
       // nothing was enqueued, and a later tick retries
       if (rc != NMC_ENOMEM) (void)hipStreamSynchronize(s);
       for (auto& blk : lease->blocks) ctx_->free_blocks.push_back(blk);
+      if (lease->in_arena) ctx_->arena.release_newest();
       return rc;
     }
     ctx_->next_stream = (ctx_->next_stream + 1) % kServeStreams;
-    b.bytes = 0;
+    b.bytes = arena_bytes;
     for (auto& blk : lease->blocks) b.bytes += blk.bytes;  // what the device really holds
     b.dev = lease.release();
     return NMC_OK;
@@ -1168,6 +1275,7 @@ class HipServeDevice final : public nmc::ServeDevice {
       q.ready = nullptr;
     }
     for (auto& blk : l->blocks) ctx_->free_blocks.push_back(blk);
+    if (l->in_arena) ctx_->arena.release_oldest();  // batches retire in launch order
     (void)hipEventDestroy(l->ev);
     delete l;
     b.dev = nullptr;
@@ -1258,6 +1366,7 @@ void nmc_destroy(nmc_ctx* ctx) {
   for (auto& l : ctx->leases)
     for (auto& blk : l.blocks) (void)hipFree(blk.ptr);
   for (auto& b : ctx->free_blocks) (void)hipFree(b.ptr);
+  if (ctx->arena.base) (void)hipFree(ctx->arena.base);
   for (auto& kv : ctx->perp) {
     (void)hipFree(kv.second.tw64);
     (void)hipFree(kv.second.tw32);
