@@ -161,41 +161,6 @@ struct Lease {
   bool in_arena = false;  // a serving batch's region of the serving arena
 };
 
-// Workspace of the serving batches under a budget: one device allocation
-// used as a ring.  Batches retire in launch order, so regions are released
-// oldest first and the free space is one run (wrapping at the end); no
-// allocation, free or device-wide wait happens while the serving loop runs
-// at its budget.
-struct ServeArena {
-  char* base = nullptr;
-  size_t size = 0;
-  std::deque<std::pair<size_t, size_t>> live;  // (offset, bytes), oldest first
-  // A region of `bytes` after the newest one (or at the start, past the
-  // end); false when it does not fit beside the regions in use.
-  bool alloc(size_t bytes, size_t* off) {
-    if (bytes > size) return false;
-    size_t at = 0;
-    if (!live.empty()) {
-      const size_t tail = live.front().first;
-      const size_t head = live.back().first + live.back().second;
-      const bool wrapped = live.back().first < tail;
-      if (!wrapped && head + bytes <= size) at = head;
-      else if (!wrapped && bytes <= tail) at = 0;
-      else if (wrapped && head + bytes <= tail) at = head;
-      else return false;
-    }
-    live.emplace_back(at, bytes);
-    *off = at;
-    return true;
-  }
-  void release_oldest() {
-    if (!live.empty()) live.pop_front();
-  }
-  void release_newest() {
-    if (!live.empty()) live.pop_back();
-  }
-};
-
 struct PerP {
   void* tw64 = nullptr;  // double2[P]
   void* tw32 = nullptr;  // float2[P]
@@ -255,7 +220,8 @@ struct nmc_ctx {
   hipStream_t streams[kServeStreams] = {};
   int next_stream = 0;
   std::vector<hipEvent_t> ev_pool;  // reusable submit events
-  ServeArena arena;                  // serving workspace under a budget
+  char* arena_base = nullptr;        // serving workspace under a budget: one allocation
+  nmc::RingArena arena;              // and its regions in use
   // second stream of a solve (hole grids and carry cascade) and its fork/join events
   hipStream_t aux_stream = nullptr;
   // this device's static scratch array (nmc_solve_noalloc)
@@ -978,10 +944,11 @@ void make_room(nmc_ctx* ctx, size_t need, const std::vector<int>& keep) {
       ctx->free_blocks.erase(it);
       continue;
     }
-    if (ctx->arena.base && ctx->arena.live.empty() && (!ctx->serve || ctx->serve->idle())) {
-      (void)hipFree(ctx->arena.base);  // the serving arena, while no batch uses it
-      ctx->allocated -= ctx->arena.size;
-      ctx->arena = ServeArena{};
+    if (ctx->arena_base && ctx->arena.empty() && (!ctx->serve || ctx->serve->idle())) {
+      (void)hipFree(ctx->arena_base);  // the serving arena, while no batch uses it
+      ctx->allocated -= ctx->arena.size();
+      ctx->arena_base = nullptr;
+      ctx->arena = nmc::RingArena{};
       continue;
     }
     if (!synced) {
@@ -1174,7 +1141,7 @@ int scratch_address(nmc_ctx* ctx, int dev, char** out) {
 // (a sixteenth of the budget, at most 1 GiB); cached solve workspace blocks
 // are released first.  make_room frees it again while no batch uses it.
 int ensure_arena(nmc_ctx* ctx) {
-  if (ctx->arena.base) return NMC_OK;
+  if (ctx->arena_base) return NMC_OK;
   reap_leases(ctx, false);
   for (auto& b : ctx->free_blocks) {
     (void)hipFree(b.ptr);
@@ -1192,8 +1159,8 @@ int ensure_arena(nmc_ctx* ctx) {
     return fail(ctx, NMC_ENOMEM, "serving: workspace arena of " + std::to_string(size) + " bytes: " +
                                      hipGetErrorString(e));
   }
-  ctx->arena.base = static_cast<char*>(p);
-  ctx->arena.size = size;
+  ctx->arena_base = static_cast<char*>(p);
+  ctx->arena = nmc::RingArena(size);
   ctx->allocated += size;
   return NMC_OK;
 }
@@ -1235,7 +1202,7 @@ class HipServeDevice final : public nmc::ServeDevice {
     }
     if (rc == NMC_OK) {
       if (lease->in_arena) {
-        char* ws = ctx_->arena.base + arena_off;
+        char* ws = ctx_->arena_base + arena_off;
         rc = rs[0].p == NMC_F64 ? run_group<double>(ctx_, rs.data(), (int)rs.size(), ws, s, nullptr)
                                 : run_group<float>(ctx_, rs.data(), (int)rs.size(), ws, s, nullptr);
       } else {
@@ -1366,7 +1333,7 @@ void nmc_destroy(nmc_ctx* ctx) {
   for (auto& l : ctx->leases)
     for (auto& blk : l.blocks) (void)hipFree(blk.ptr);
   for (auto& b : ctx->free_blocks) (void)hipFree(b.ptr);
-  if (ctx->arena.base) (void)hipFree(ctx->arena.base);
+  if (ctx->arena_base) (void)hipFree(ctx->arena_base);
   for (auto& kv : ctx->perp) {
     (void)hipFree(kv.second.tw64);
     (void)hipFree(kv.second.tw32);

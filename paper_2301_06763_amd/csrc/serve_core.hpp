@@ -45,6 +45,52 @@ class ServeDevice {
   virtual void release(ServeBatch& b) = 0;
 };
 
+// Regions of the serving workspace in one allocation of `size` bytes, used
+// as a ring: batches retire in launch order, so regions are released oldest
+// first and the free space is one run (wrapping at the end).  The device
+// side holds the allocation; this tracks offsets only.
+class RingArena {
+ public:
+  RingArena() = default;
+  explicit RingArena(size_t size) : size_(size) {}
+  // A region of `bytes` after the newest one, or at the start once the end
+  // is reached; false when it does not fit beside the regions in use.
+  bool alloc(size_t bytes, size_t* off) {
+    if (bytes == 0 || bytes > size_) return false;
+    size_t at = 0;
+    if (!live_.empty()) {
+      const size_t tail = live_.front().first;
+      const size_t head = live_.back().first + live_.back().second;
+      const bool wrapped = live_.back().first < tail;
+      if (!wrapped && head + bytes <= size_) at = head;
+      else if (!wrapped && bytes <= tail) at = 0;
+      else if (wrapped && head + bytes <= tail) at = head;
+      else return false;
+    }
+    live_.emplace_back(at, bytes);
+    *off = at;
+    return true;
+  }
+  void release_oldest() {
+    if (!live_.empty()) live_.pop_front();
+  }
+  void release_newest() {  // a launch that did not go ahead
+    if (!live_.empty()) live_.pop_back();
+  }
+  bool empty() const { return live_.empty(); }
+  size_t size() const { return size_; }
+  size_t used() const {
+    size_t u = 0;
+    for (const auto& r : live_) u += r.second;
+    return u;
+  }
+  const std::deque<std::pair<size_t, size_t>>& live() const { return live_; }
+
+ private:
+  size_t size_ = 0;
+  std::deque<std::pair<size_t, size_t>> live_;  // (offset, bytes), oldest first
+};
+
 class ServeCore {
  public:
   enum State { kQueued = 0, kInflight = 1, kDone = 2 };

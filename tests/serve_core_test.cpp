@@ -2,7 +2,8 @@
 // serve_core.hpp) against a simulated device with a fake clock and fake
 // footprints: admission in arrival order under the budget, grouping and
 // batch bounds, retirement, requeueing after NMC_ENOMEM and device errors,
-// and completion of every ticket exactly once.  Built and run with
+// completion of every ticket exactly once, and the ring of serving
+// workspace regions (RingArena).  Built and run with
 // AddressSanitizer and UndefinedBehaviorSanitizer by test_serve_core_cpu.py.
 #include <cstdio>
 #include <cstdlib>
@@ -266,7 +267,58 @@ static void test_random_simulation() {
   }
 }
 
+// The ring of serving workspace regions: regions never overlap, stay in
+// bounds, are released oldest first, and a region that fits the free run
+// (at the head or, past the end, at the start) is placed.
+static void test_ring_arena() {
+  nmc::RingArena a(100);
+  size_t o = 0;
+  CHECK(!a.alloc(0, &o) && !a.alloc(101, &o));
+  CHECK(a.alloc(40, &o) && o == 0);
+  CHECK(a.alloc(40, &o) && o == 40);
+  CHECK(!a.alloc(30, &o));  // 20 left at the end, the start is taken
+  CHECK(a.alloc(20, &o) && o == 80);
+  a.release_oldest();       // [0, 40) free
+  CHECK(!a.alloc(41, &o));
+  CHECK(a.alloc(30, &o) && o == 0);  // wrapped
+  CHECK(a.alloc(10, &o) && o == 30);
+  CHECK(!a.alloc(1, &o));   // full up to the oldest region
+  a.release_newest();       // a launch that did not go ahead
+  CHECK(a.alloc(10, &o) && o == 30);
+  a.release_oldest();
+  a.release_oldest();       // [40, 100) free, live: [0, 40)
+  CHECK(a.alloc(60, &o) && o == 40);
+  CHECK(a.used() == 100);
+  a.release_oldest();
+  a.release_oldest();
+  a.release_oldest();
+  CHECK(a.empty() && a.used() == 0);
+  CHECK(a.alloc(100, &o) && o == 0);
+  a.release_oldest();
+  // random FIFO traffic: every placed region is disjoint from the others
+  std::mt19937_64 rng(7);
+  nmc::RingArena r(1000);
+  for (int i = 0; i < 20000; ++i) {
+    if (!r.empty() && (rng() % 3 == 0)) {
+      r.release_oldest();
+      continue;
+    }
+    const size_t b = 1 + rng() % 300;
+    const size_t before = r.used();
+    if (r.alloc(b, &o)) {
+      CHECK(o + b <= 1000);
+      const auto& lv = r.live();
+      for (size_t k = 0; k + 1 < lv.size(); ++k)
+        CHECK(lv[k].first + lv[k].second <= o || o + b <= lv[k].first);
+    } else {
+      CHECK(r.used() == before);
+      CHECK(before + b > 1000 || !r.empty());  // an empty ring places anything that fits
+    }
+  }
+}
+
 int main() {
+  test_ring_arena();
   test_fifo_admission_under_budget();
   test_grouping_and_batch_bounds();
   test_enomem_and_errors_requeue_in_order();
