@@ -55,6 +55,22 @@ namespace nmc {
 #ifndef NMC_Z_ONE_ROW_F32
 #define NMC_Z_ONE_ROW_F32 0
 #endif
+// one-row workgroups for the scaled grids at period 1024 (both precisions)
+#ifndef NMC_Z_ONE_ROW_SCALED
+#define NMC_Z_ONE_ROW_SCALED 1
+#endif
+// FP64 passes at P = 1024 (the scaled grids) read the twiddle table from
+// global memory (L2) instead of staging its 16 KB in LDS: the x, y and z
+// tiles then leave room for two workgroups per CU instead of one (z pass of
+// the quadrupled grids, 128^3 x 8: 8.1 -> 4.8 ms per launch on average;
+// three-level solves 31 -> 45 per second)
+#ifndef NMC_GLOBAL_TW_1024
+#define NMC_GLOBAL_TW_1024 1
+#endif
+template <class R, int P>
+constexpr bool global_twiddles() {
+  return sizeof(R) == 8 && P >= 1024 && NMC_GLOBAL_TW_1024;
+}
 // LDS swizzle (LdsView) of the eight interleaved lines of the one-row z
 // workgroups: 256^3 x 6 levels FP64, z pass 3.04 -> 2.99 ms.  The y passes'
 // workgroups of eight FP64 columns at P = 512 have the same layout and ran
@@ -261,7 +277,9 @@ __device__ __forceinline__ double lane_read(double x, int src) {
 // Measured at 256^3 x 6 levels, FP64: forward x pass 0.755 ms with one unit
 // per wavefront, 0.636 ms with four; the inverse x pass, whose carry
 // epilogue gathers from the carried box, ran slower with four (0.127 ->
-// 0.140 ms per launch), so it keeps one.
+// 0.140 ms per launch), so it keeps one.  At P = 1024 (scaled grids, 16
+// points per lane) four units took the FP64 pass to over 300 registers and
+// from 0.82 to 1.0 ms, so there too one.
 #ifndef NMC_X_ITERS
 #define NMC_X_ITERS 4
 #endif
@@ -272,7 +290,7 @@ __device__ __forceinline__ double lane_read(double x, int src) {
 #define NMC_X_WAVE 1
 #endif
 template <int P, bool INV = false>
-constexpr int x_iters() { return P >= 512 ? (INV ? NMC_IX_ITERS : NMC_X_ITERS) : 1; }
+constexpr int x_iters() { return P == 512 ? (INV ? NMC_IX_ITERS : NMC_X_ITERS) : 1; }
 
 // PAIRS: two real lines a, b per complex transform: z = a + i b,
 // Z = FFT(z), A[k] = (Z[k] + conj Z[P-k]) / 2, B[k] = (Z[k] - conj Z[P-k]) / (2i).
@@ -288,9 +306,11 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   constexpr int E = C::E, TL = C::TL, W = C::WC, LPW = PAIRS ? 2 : 1, IT = x_iters<P>();
   constexpr bool WAVE = NMC_X_WAVE != 0;
   static_assert(64 % TL == 0, "a line's threads must share a wavefront");
+  constexpr bool GTW = global_twiddles<R, P>();  // twiddles from global memory
   __shared__ R sre[W * P], sim[W * P];
-  __shared__ cplx<R> stw[P];
-  const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
+  __shared__ cplx<R> stw_lds[GTW ? 1 : P];
+  const cplx<R>* const stw = GTW ? tb.tw : stw_lds;
+  const TwStage<R, GTW ? 1 : P, C::WC * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = FULLN ? P / 2 : g.N, n = grid_geo<DBL>(F.kind, N, g.S).nin;
   const int nunits = n * n / LPW;  // n is even: the two lines of a pair share z
@@ -298,11 +318,13 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
   const int xo = DBL ? (g.S - 1) * N / 2 : 0;
   const LdsView<R> lds{sre, sim, 1, P, w};
-  tws.put(stw);
-  if constexpr (WAVE) __syncthreads();  // the table is complete before the first stage that reads it
-  for (int it = 0; it < IT; ++it) {
-    const int u0 = ((int)blockIdx.x * IT + it) * W;
-    if (u0 >= nunits) break;  // uniform
+  if constexpr (!GTW) {
+    tws.put(stw_lds);
+    if constexpr (WAVE) __syncthreads();  // the table is complete before the first stage that reads it
+  }
+  // units u0 + w of the workgroup's wavefronts (a loop even of one trip
+  // measurably costs registers at 16 points per lane, so IT = 1 has none)
+  auto units = [&](int u0) {
     const int unit = u0 + w;
     const bool active = unit < nunits;
     const int line = active ? LPW * unit : 0;
@@ -352,6 +374,15 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
         }
       }
     }
+  };
+  if constexpr (IT == 1) {
+    units((int)blockIdx.x * W);
+  } else {
+    for (int it = 0; it < IT; ++it) {
+      const int u0 = ((int)blockIdx.x * IT + it) * W;
+      if (u0 >= nunits) break;  // uniform
+      units(u0);
+    }
   }
 }
 
@@ -364,9 +395,11 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
   using C = Cfg<R, P, kPassY>;
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WS, NT = (P / 2) / W;
+  constexpr bool GTW = global_twiddles<R, P>();  // twiddles from global memory
   __shared__ R sre[W * P], sim[W * P];
-  __shared__ cplx<R> stw[P];
-  const TwStage<R, P, C::WS * C::TL> tws(tb.tw);
+  __shared__ cplx<R> stw_lds[GTW ? 1 : P];
+  const cplx<R>* const stw = GTW ? tb.tw : stw_lds;
+  const TwStage<R, GTW ? 1 : P, C::WS * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const bool full = FULLN && F.kind != 1;  // nin = N = P/2: no bound checks
   const GridGeo gg = grid_geo<DBL>(F.kind, FULLN ? P / 2 : g.N, g.S);
@@ -386,7 +419,7 @@ k_fwd_y(FieldTable ft, PassGeom g, Tables<R> tb) {
     v[q] = in ? a : T{0, 0};
   }
   const LdsView<R> lds{sre, sim, W, 1, w};
-  tws.put(stw);
+  if constexpr (!GTW) tws.put(stw_lds);
   fft_line<R, P, -1, true, false, kPassY>(v, t, lds, stw);
 #pragma unroll
   for (int q = 0; q < E; ++q) B[(size_t)(t + TL * q) * (P / 2)] = v[q];
@@ -490,11 +523,12 @@ constexpr bool z_col0_split() { return SC == 1 ? P == 128 && sizeof(R) == 8 : P 
 // so that the other workgroups keep their XCD (blockIdx mod 8, see z_unit).
 __host__ __device__ constexpr int z_col0_blocks(int NT, int nf) { return (NT * nf + 7) / 8 * 8; }
 
-// ONE (level grids): the workgroups other than the column-0 ones own 2 W
-// adjacent columns of a single row instead of W columns of the row pair ky,
-// -ky, so that each memory instruction covers runs of 2 W values: at P = 512
-// FP64 128-byte runs instead of 64-byte ones, with the same LDS tile.  The
-// DC/Nyquist column is then left to the column-0 workgroups.
+// ONE (FP64 level grids at P = 512, scaled grids at P = 1024): the
+// workgroups other than the column-0 ones own 2 W adjacent columns of a
+// single row instead of W columns of the row pair ky, -ky, so that each
+// memory instruction covers runs of 2 W values (at P = 512 FP64 128-byte
+// runs instead of 64-byte ones), with the same LDS tile.  The DC/Nyquist
+// column is then left to the column-0 workgroups.
 template <class R, int P, bool FULLN, int SC = 1, bool ONE = false>
 __global__ void __launch_bounds__((2 * Cfg<R, P, SC == 1 ? kPassZ : kPassZScaled>::WZ *
                                    Cfg<R, P, SC == 1 ? kPassZ : kPassZScaled>::TL),
@@ -507,9 +541,10 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WZ, NT = (P / 2) / W, H = P / 2 + 1;
   __shared__ R sre[2 * W * P], sim[2 * W * P];
-  __shared__ cplx<R> stw[P];
-  const TwStage<R, P, 2 * C::WZ * C::TL> tws(tb.tw);
-  static_assert(!ONE || SC == 1, "one-row workgroups: level grids only");
+  constexpr bool GTW = global_twiddles<R, P>();  // twiddles from global memory
+  __shared__ cplx<R> stw_lds[GTW ? 1 : P];
+  const cplx<R>* const stw = GTW ? tb.tw : stw_lds;
+  const TwStage<R, GTW ? 1 : P, 2 * C::WZ * C::TL> tws(tb.tw);
   constexpr int WM = ONE ? 2 * W : W, NTM = (P / 2) / WM;  // columns and tiles of a workgroup's row(s)
   constexpr int TP = WM * (int)sizeof(T) < 128 ? 2 : 1;   // tiles sharing a 128-byte line
   constexpr bool SPLIT = ONE || z_col0_split<R, P, SC>();
@@ -579,7 +614,7 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   if constexpr (!late) fetch_spectrum();
   // ONE: line w < 2 W, side 0
   const LdsView<R, ONE && NMC_Z_SWZ_ONE && 2 * W == 8> lds{sre, sim, 2 * W, 1, w + W * side};
-  tws.put(stw);
+  if constexpr (!GTW) tws.put(stw_lds);
   fft_line<R, P, -1, true, false, KZ>(v, t, lds, stw);
   if constexpr (late) fetch_spectrum();
 
@@ -1157,9 +1192,7 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   const LdsView<R> lds{sre, sim, 1, P, w};
   tws.put(stw);
   if constexpr (WAVE) __syncthreads();  // the table is complete before the first stage that reads it
-  for (int it = 0; it < IT; ++it) {
-    const int u0 = ((int)blockIdx.x * IT + it) * W;
-    if (u0 >= nunits) break;  // uniform
+  auto units = [&](int u0) {  // as in k_fwd_x
     const int unit = u0 + w;
     const bool active = unit < nunits;
     const int line = active ? LPW * unit : 0;
@@ -1201,6 +1234,15 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
         for (int q = 0; q < E / 2; ++q) vb[q] = T{v[q].y, 0};
         ix_outputs<R, P, kPassIX, TRI>(F, N, gg, z, y + 1, zr, yr + 1, t, vb);
       }
+    }
+  };
+  if constexpr (IT == 1) {
+    units((int)blockIdx.x * W);
+  } else {
+    for (int it = 0; it < IT; ++it) {
+      const int u0 = ((int)blockIdx.x * IT + it) * W;
+      if (u0 >= nunits) break;  // uniform
+      units(u0);
     }
   }
 }
@@ -2003,6 +2045,13 @@ hipError_t launch_z(const FieldTable& ft, PassGeom g, Tables<R> tb, hipStream_t 
       using CS = Cfg<R, PP, kPassZScaled>;
       const dim3 block(2 * CS::WZ * CS::TL);
       static_assert(z_col0_split<R, PP, 2>() == z_col0_split<R, PP, 4>(), "one grid size for both scales");
+      if constexpr (PP == 1024 && NMC_Z_ONE_ROW_SCALED) {
+        // one-row workgroups of 2 W columns, column 0 apart
+        const dim3 g1(z_col0_blocks(NT, g.nf) + (PP / 2) / (2 * C::WZ) * PP * g.nf);
+        if (g.S == 2) launch(k_z<R, PP, false, 2, true>, g1, block, 0, s, ft, g, tb);
+        else if (g.S == 4) launch(k_z<R, PP, false, 4, true>, g1, block, 0, s, ft, g, tb);
+        return;
+      }
       if constexpr (z_col0_split<R, PP, 2>()) grid.x += z_col0_blocks(NT, g.nf);
       if constexpr (PP >= 16) {
         if (g.S == 2) launch(k_z<R, PP, false, 2>, grid, block, 0, s, ft, g, tb);
