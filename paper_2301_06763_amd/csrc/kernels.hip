@@ -67,6 +67,12 @@ namespace nmc {
 #ifndef NMC_GLOBAL_TW_1024
 #define NMC_GLOBAL_TW_1024 1
 #endif
+// and so does the FP64 inverse x pass at P = 512: 32 KB of LDS per
+// workgroup, five resident per CU instead of four (256^3 x 6: full grids
+// 0.130 -> 0.115 ms, child-region boxes 0.109 -> 0.084 ms per launch)
+#ifndef NMC_IX_GLOBAL_TW
+#define NMC_IX_GLOBAL_TW 1
+#endif
 template <class R, int P>
 constexpr bool global_twiddles() {
   return sizeof(R) == 8 && P >= 1024 && NMC_GLOBAL_TW_1024;
@@ -1179,9 +1185,11 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   constexpr int IT = x_iters<P, true>();
   constexpr bool WAVE = NMC_X_WAVE != 0;
   static_assert(64 % TL == 0, "a line's threads must share a wavefront");
+  constexpr bool GTW = global_twiddles<R, P>() || (NMC_IX_GLOBAL_TW && sizeof(R) == 8 && P == 512);
   __shared__ R sre[W * P], sim[W * P];
-  __shared__ cplx<R> stw[P];
-  const TwStage<R, P, C::WC * C::TL> tws(tb.tw);
+  __shared__ cplx<R> stw_lds[GTW ? 1 : P];
+  const cplx<R>* const stw = GTW ? tb.tw : stw_lds;
+  const TwStage<R, GTW ? 1 : P, C::WC * C::TL> tws(tb.tw);
   const FieldDesc& F = ft.f[blockIdx.y];
   const int N = g.N;
   const GridGeo gg = grid_geo(F.kind, N);
@@ -1190,8 +1198,10 @@ k_inv_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   if ((int)blockIdx.x * IT * W >= nunits) return;  // uniform: a smaller grid of a mixed launch
   const int t = threadIdx.x % TL, w = threadIdx.x / TL;
   const LdsView<R> lds{sre, sim, 1, P, w};
-  tws.put(stw);
-  if constexpr (WAVE) __syncthreads();  // the table is complete before the first stage that reads it
+  if constexpr (!GTW) {
+    tws.put(stw_lds);
+    if constexpr (WAVE) __syncthreads();  // the table is complete before the first stage that reads it
+  }
   auto units = [&](int u0) {  // as in k_fwd_x
     const int unit = u0 + w;
     const bool active = unit < nunits;
