@@ -67,11 +67,14 @@ namespace nmc {
 #ifndef NMC_GLOBAL_TW_1024
 #define NMC_GLOBAL_TW_1024 1
 #endif
-// and so does the FP64 inverse x pass at P = 512: 32 KB of LDS per
-// workgroup, five resident per CU instead of four (256^3 x 6: full grids
-// 0.130 -> 0.115 ms, child-region boxes 0.109 -> 0.084 ms per launch)
+// and so do the FP64 x passes at P = 512: 32 KB of LDS per workgroup, five
+// resident per CU instead of four (256^3 x 6, inverse x: full grids 0.130
+// -> 0.115 ms, child-region boxes 0.109 -> 0.084 ms per launch)
 #ifndef NMC_IX_GLOBAL_TW
 #define NMC_IX_GLOBAL_TW 1
+#endif
+#ifndef NMC_X_GLOBAL_TW
+#define NMC_X_GLOBAL_TW 1
 #endif
 template <class R, int P>
 constexpr bool global_twiddles() {
@@ -280,14 +283,17 @@ __device__ __forceinline__ double lane_read(double x, int src) {
 // threads are lanes of one wavefront, so once the workgroup has staged the
 // twiddle table its wavefronts need no workgroup barrier: each takes IT
 // units in turn at its own pace, and the table is staged once per IT units.
-// Measured at 256^3 x 6 levels, FP64: forward x pass 0.755 ms with one unit
-// per wavefront, 0.636 ms with four; the inverse x pass, whose carry
-// epilogue gathers from the carried box, ran slower with four (0.127 ->
-// 0.140 ms per launch), so it keeps one.  At P = 1024 (scaled grids, 16
-// points per lane) four units took the FP64 pass to over 300 registers and
-// from 0.82 to 1.0 ms, so there too one.
+// Measured at 256^3 x 6 levels, FP64, with the twiddle table in LDS: forward
+// x pass 0.755 ms with one unit per wavefront, 0.636 ms with four; the
+// inverse x pass, whose carry epilogue gathers from the carried box, ran
+// slower with four (0.127 -> 0.140 ms per launch).  With the FP64 table
+// read from global memory (NMC_X_GLOBAL_TW, NMC_IX_GLOBAL_TW) the LDS it
+// frees gives the same or better with one unit (forward 0.60 ms with one,
+// two or four), so both keep one.  At P = 1024 (scaled grids, 16 points per
+// lane) four units took the FP64 pass to over 300 registers and from 0.82
+// to 1.0 ms.
 #ifndef NMC_X_ITERS
-#define NMC_X_ITERS 4
+#define NMC_X_ITERS 1
 #endif
 #ifndef NMC_IX_ITERS
 #define NMC_IX_ITERS 1
@@ -312,7 +318,7 @@ k_fwd_x(FieldTable ft, PassGeom g, Tables<R> tb) {
   constexpr int E = C::E, TL = C::TL, W = C::WC, LPW = PAIRS ? 2 : 1, IT = x_iters<P>();
   constexpr bool WAVE = NMC_X_WAVE != 0;
   static_assert(64 % TL == 0, "a line's threads must share a wavefront");
-  constexpr bool GTW = global_twiddles<R, P>();  // twiddles from global memory
+  constexpr bool GTW = global_twiddles<R, P>() || (NMC_X_GLOBAL_TW && sizeof(R) == 8 && P == 512);
   __shared__ R sre[W * P], sim[W * P];
   __shared__ cplx<R> stw_lds[GTW ? 1 : P];
   const cplx<R>* const stw = GTW ? tb.tw : stw_lds;
