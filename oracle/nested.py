@@ -65,6 +65,7 @@ Readings where the paper is silent or ambiguous:
 """
 from __future__ import annotations
 
+import functools
 import math
 import os
 
@@ -140,14 +141,22 @@ def potential_fft(mass: np.ndarray, h: float, G: float = 1.0, P: int | None = No
     if P is None:
         P = 2 * N
     assert P >= 2 * N - 1
-    g = green_periodic(P)
     Mp = np.zeros((P, P, P), dtype=np.float64)
     Mp[:N, :N, :N] = mass
     w = _workers()
     Fm = scipy.fft.rfftn(Mp, workers=w)
-    Fg = scipy.fft.rfftn(g, workers=w)
+    Fg = _green_spectrum(P)
     conv = scipy.fft.irfftn(Fm * Fg, s=(P, P, P), workers=w)
     return -(G / h) * conv[:N, :N, :N]
+
+
+@functools.lru_cache(maxsize=2)
+def _green_spectrum(P: int) -> np.ndarray:
+    """FFT(g) of green_periodic(P), kept for the next grid of the same
+    period (the same array every time; read-only)."""
+    Fg = scipy.fft.rfftn(green_periodic(P), workers=_workers())
+    Fg.setflags(write=False)
+    return Fg
 
 
 def potential_direct(mass: np.ndarray, h: float, G: float = 1.0) -> np.ndarray:
