@@ -209,8 +209,16 @@ int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_
  * stays within the budget, groups the admitted ones as nmc_solve_batch does
  * (N, precision, method and carry rule) and launches each group as one
  * batched solve on the next serving stream, so new work overlaps the work
- * already on the device.  rho/phi of a submitted request must stay valid
- * until it is reported done. */
+ * already on the device.  Under a budget the batches' workspace comes from
+ * one device allocation made at the first serving launch (what the budget
+ * leaves beside the Green tables, the workspace of solves in flight and a
+ * sixteenth of the budget, at most 1 GiB, kept for tables of other periods)
+ * and used as a ring, so a serving loop at its budget makes no allocation,
+ * free or device-wide wait; a batch that does not fit beside the batches in
+ * flight waits for the next tick.  The allocation is released when a solve
+ * outside the serving loop needs its room and no batch is in flight.
+ * rho/phi of a submitted request must stay valid until it is reported
+ * done. */
 
 /* Queue a request; *ticket receives its id.  hip_stream is the stream on
  * which the caller wrote req->rho (and last used req->phi): an event is
