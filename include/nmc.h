@@ -215,8 +215,10 @@ int nmc_solve_batch(nmc_ctx* ctx, const nmc_request* reqs, int count, void* hip_
  * sixteenth of the budget, at most 1 GiB, kept for tables of other periods)
  * and used as a ring, so a serving loop at its budget makes no allocation,
  * free or device-wide wait; a batch that does not fit beside the batches in
- * flight waits for the next tick.  The allocation is released when a solve
- * outside the serving loop needs its room and no batch is in flight.
+ * flight waits for the next tick, and one larger than the whole ring (with
+ * nothing in flight) releases it and runs on workspace of its own, as a
+ * solve does.  The allocation is released when a solve outside the serving
+ * loop needs its room and no batch is in flight.
  * rho/phi of a submitted request must stay valid until it is reported
  * done. */
 
@@ -256,6 +258,7 @@ typedef struct {
   size_t budget_bytes;      /* admission budget (0 = unlimited) */
   size_t peak_inflight_bytes;
   size_t green_cache_bytes; /* Green-spectrum tables held by the context */
+  size_t arena_bytes;       /* serving workspace allocation held (budget set; 0 when released) */
 } nmc_serve_stats;
 
 int nmc_serve_stats_get(nmc_ctx* ctx, nmc_serve_stats* out);

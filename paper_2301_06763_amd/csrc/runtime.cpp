@@ -925,6 +925,15 @@ int run_group(nmc_ctx* ctx, const Req* reqs, int count, char* ws, hipStream_t s,
 
 void drop_graph(nmc_ctx* ctx, std::map<GraphKey, GraphEntry>::iterator it);
 
+// The serving arena's allocation (hipFree waits for the device).
+void release_arena(nmc_ctx* ctx) {
+  if (!ctx->arena_base) return;
+  (void)hipFree(ctx->arena_base);
+  ctx->allocated -= ctx->arena.size();
+  ctx->arena_base = nullptr;
+  ctx->arena = nmc::RingArena{};
+}
+
 // Under a budget, until `need` more bytes fit: release cached workspace
 // blocks, then the captured graphs (they hold workspace and the tables'
 // addresses), then the least recently used Green tables whose period is not
@@ -945,10 +954,7 @@ void make_room(nmc_ctx* ctx, size_t need, const std::vector<int>& keep) {
       continue;
     }
     if (ctx->arena_base && ctx->arena.empty() && (!ctx->serve || ctx->serve->idle())) {
-      (void)hipFree(ctx->arena_base);  // the serving arena, while no batch uses it
-      ctx->allocated -= ctx->arena.size();
-      ctx->arena_base = nullptr;
-      ctx->arena = nmc::RingArena{};
+      release_arena(ctx);  // the serving arena, while no batch uses it
       continue;
     }
     if (!synced) {
@@ -1189,8 +1195,16 @@ class HipServeDevice final : public nmc::ServeDevice {
       arena_bytes = align_up(arena_bytes, size_t(64) << 10);
       if ((rc = prepare_tables(ctx_, rs[0].N, rs[0].flags, s))) return rc;
       if ((rc = ensure_arena(ctx_))) return rc == NMC_ENOMEM ? NMC_EDEVICE : rc;
-      if (!ctx_->arena.alloc(arena_bytes, &arena_off)) return NMC_ENOMEM;
-      lease->in_arena = true;
+      if (ctx_->arena.alloc(arena_bytes, &arena_off)) {
+        lease->in_arena = true;
+      } else if (!ctx_->arena.empty() || arena_bytes <= ctx_->arena.size()) {
+        return NMC_ENOMEM;  // fits once batches in flight retire
+      } else {
+        // larger than the whole ring, nothing in flight: release it and take
+        // workspace of its own (the pool can also evict other periods' tables)
+        release_arena(ctx_);
+        arena_bytes = 0;
+      }
     }
     // order the batch after the callers' work on its inputs and outputs
     for (uint64_t t : b.tickets) {
@@ -1541,6 +1555,7 @@ int nmc_serve_stats_get(nmc_ctx* ctx, nmc_serve_stats* out) {
   *out = ctx->serve->stats();
   out->budget_bytes = ctx->budget;
   out->green_cache_bytes = ctx->green_bytes;
+  out->arena_bytes = ctx->arena_base ? ctx->arena.size() : 0;
   return NMC_OK;
 }
 

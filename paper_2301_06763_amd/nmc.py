@@ -56,7 +56,8 @@ class ServeStats(ctypes.Structure):
                 ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("queued", ctypes.c_uint64), ("inflight", ctypes.c_uint64),
                 ("inflight_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
-                ("peak_inflight_bytes", ctypes.c_size_t), ("green_cache_bytes", ctypes.c_size_t)]
+                ("peak_inflight_bytes", ctypes.c_size_t), ("green_cache_bytes", ctypes.c_size_t),
+                ("arena_bytes", ctypes.c_size_t)]
 
 
 _lib = None

@@ -332,6 +332,43 @@ def test_serving_mix_equals_alone(dtype):
         c.close()
 
 
+def test_serving_request_larger_than_the_ring():
+    """Under a budget the serving batches share one allocation used as a
+    ring, sized from what the budget leaves; a request larger than the ring
+    but within the budget releases it, runs on workspace of its own and
+    gives the result it gives alone; the ring is back for the next batch."""
+    from paper_2301_06763_amd import nmc
+    N, L = 64, 10
+    fp = nmc.footprint_bytes(N, L, torch.float64)
+    budget = int(fp * 1.04) + (4 << 20)  # the ring (budget less 1/16) is smaller than fp
+    w = inputs.random_levels(N, L, seed=32)
+    rho = w.rho.to("cuda", torch.float64).contiguous()
+    free = nmc.Context()
+    try:
+        alone = free.solve(rho, w.h0, flags=nmc.NMC_NO_GRAPH).clone()
+    finally:
+        free.close()
+    small = inputs.random_levels(16, 2, seed=31)
+    r0 = small.rho.to("cuda", torch.float64).contiguous()
+    c = nmc.Context(budget_bytes=budget)
+    try:
+        c.submit(r0, small.h0)
+        c.drain()
+        ring = c.stats()["arena_bytes"]
+        assert 0 < ring < fp, (ring, fp)
+        tk = c.submit(rho, w.h0)
+        c.drain()
+        assert c.poll(tk)
+        assert torch.equal(tk.phi, alone)
+        tk2 = c.submit(r0, small.h0)
+        c.drain()
+        assert c.poll(tk2)
+        st = c.stats()
+        assert st["arena_bytes"] > 0 and st["completed"] == 3
+    finally:
+        c.close()
+
+
 # --- boundary errors ------------------------------------------------------------
 
 def test_invalid_arguments(ctx):
