@@ -141,12 +141,10 @@ def potential_fft(mass: np.ndarray, h: float, G: float = 1.0, P: int | None = No
     if P is None:
         P = 2 * N
     assert P >= 2 * N - 1
-    Mp = np.zeros((P, P, P), dtype=np.float64)
-    Mp[:N, :N, :N] = mass
     w = _workers()
-    Fm = scipy.fft.rfftn(Mp, workers=w)
-    Fg = _green_spectrum(P)
-    conv = scipy.fft.irfftn(Fm * Fg, s=(P, P, P), workers=w)
+    Fm = scipy.fft.rfftn(np.asarray(mass, dtype=np.float64), s=(P, P, P), workers=w)  # zero-padded to P^3
+    Fm *= _green_spectrum(P)
+    conv = scipy.fft.irfftn(Fm, s=(P, P, P), workers=w, overwrite_x=True)
     return -(G / h) * conv[:N, :N, :N]
 
 
