@@ -146,6 +146,20 @@ struct LdsView {
   }
 };
 
+// The same with the complex points interleaved (one access of 2 reals per
+// point instead of one per real and imaginary part).
+template <class R, bool SWZ = false>
+struct LdsViewC {
+  cplx<R>* a;
+  int SN, SW, w;
+  __device__ __forceinline__ int at(int n) const {
+    if constexpr (SWZ) n ^= (n >> 3) & 1;
+    return n * SN + w * SW;
+  }
+  __device__ __forceinline__ void put(int n, cplx<R> v) const { a[at(n)] = v; }
+  __device__ __forceinline__ cplx<R> get(int n) const { return a[at(n)]; }
+};
+
 // Twiddles of a stage from powers of the first one (FP64: trades LDS reads,
 // its limit, for vector products, which have room; FP32 keeps the table).
 #ifndef NMC_TWIDDLE_POWERS_F64

@@ -81,11 +81,21 @@ constexpr bool global_twiddles() {
   return sizeof(R) == 8 && P >= 1024 && NMC_GLOBAL_TW_1024;
 }
 // LDS swizzle (LdsView) of the eight interleaved lines of the one-row z
-// workgroups: 256^3 x 6 levels FP64, z pass 3.04 -> 2.99 ms.  The y passes'
+// workgroups, real and imaginary parts apart: 256^3 x 6 levels FP64, z pass
+// 3.04 -> 2.99 ms.  The y passes'
 // workgroups of eight FP64 columns at P = 512 have the same layout and ran
 // no faster with it (1.24 ms either way), so they keep the plain one.
 #ifndef NMC_Z_SWZ_ONE
 #define NMC_Z_SWZ_ONE 1
+#endif
+// ... and with the points' real and imaginary parts interleaved (one
+// 16-byte LDS access per FP64 point; 256^3 x 6: 3.06 -> 2.91 ms, where the
+// swizzle no longer helps: 2.98 ms with it)
+#ifndef NMC_Z_AOS
+#define NMC_Z_AOS 1
+#endif
+#ifndef NMC_Z_AOS_SWZ
+#define NMC_Z_AOS_SWZ 0
 #endif
 #ifndef NMC_ZS_MINW_F64
 #define NMC_ZS_MINW_F64 2
@@ -552,7 +562,9 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   static_assert(C::WZ == Cfg<R, P, kPassZ>::WZ, "the spectrum layout assumes the z pass's tile width");
   using T = cplx<R>;
   constexpr int E = C::E, TL = C::TL, W = C::WZ, NT = (P / 2) / W, H = P / 2 + 1;
-  __shared__ R sre[2 * W * P], sim[2 * W * P];
+  __shared__ __align__(16) R sbuf[4 * W * P];
+  R* const sre = sbuf;
+  R* const sim = sbuf + 2 * W * P;
   constexpr bool GTW = global_twiddles<R, P>();  // twiddles from global memory
   __shared__ cplx<R> stw_lds[GTW ? 1 : P];
   const cplx<R>* const stw = GTW ? tb.tw : stw_lds;
@@ -625,7 +637,13 @@ k_z(FieldTable ft, PassGeom g, Tables<R> tb) {
   };
   if constexpr (!late) fetch_spectrum();
   // ONE: line w < 2 W, side 0
-  const LdsView<R, ONE && NMC_Z_SWZ_ONE && 2 * W == 8> lds{sre, sim, 2 * W, 1, w + W * side};
+  constexpr bool SWZV = ONE && NMC_Z_SWZ_ONE && 2 * W == 8;
+  const auto lds = [&] {
+    if constexpr (ONE && NMC_Z_AOS && sizeof(R) == 8)
+      return LdsViewC<R, SWZV && NMC_Z_AOS_SWZ>{reinterpret_cast<cplx<R>*>(sbuf), 2 * W, 1, w + W * side};
+    else
+      return LdsView<R, SWZV>{sre, sim, 2 * W, 1, w + W * side};
+  }();
   if constexpr (!GTW) tws.put(stw_lds);
   fft_line<R, P, -1, true, false, KZ>(v, t, lds, stw);
   if constexpr (late) fetch_spectrum();
