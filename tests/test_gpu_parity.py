@@ -369,6 +369,38 @@ def test_serving_request_larger_than_the_ring():
         c.close()
 
 
+def test_serving_ring_wraps_at_the_budget():
+    """Many requests under a budget a few times their footprint: the
+    batches' workspace regions wrap around the ring many times, batches
+    wait for room instead of failing, and every result equals the same
+    request solved alone."""
+    from paper_2301_06763_amd import nmc
+    shapes = [(32, 3), (64, 4), (32, 5), (64, 2), (48, 3), (64, 5)]
+    items = []
+    for i in range(48):
+        N, L = shapes[i % len(shapes)]
+        w = inputs.random_levels(N, L, seed=2000 + i)
+        items.append((w.rho.to("cuda", torch.float32).contiguous(), w.h0))
+    big = max(nmc.footprint_bytes(r.shape[1], r.shape[0], torch.float32) for r, _ in items)
+    budget = 6 * big + (64 << 20)
+    c = nmc.Context(budget_bytes=budget)
+    try:
+        alone = [c.solve(r, h, flags=nmc.NMC_NO_GRAPH).clone() for r, h in items]
+        torch.cuda.synchronize()
+        tickets = [c.submit(r, h) for r, h in items]
+        c.drain()
+        for k, (tk, a) in enumerate(zip(tickets, alone)):
+            assert c.poll(tk)
+            assert torch.equal(tk.phi, a), k
+        st = c.stats()
+        assert st["completed"] == len(items) and st["inflight"] == 0
+        assert 0 < st["arena_bytes"] < budget
+        assert st["peak_inflight_bytes"] <= st["arena_bytes"]
+        assert st["batches"] >= 4
+    finally:
+        c.close()
+
+
 # --- boundary errors ------------------------------------------------------------
 
 def test_invalid_arguments(ctx):
